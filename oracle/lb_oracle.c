@@ -1,0 +1,638 @@
+/*
+ * lb_oracle.c -- plain, slow, FP64 CPU oracle for one time step of the coupled
+ * pair of D2Q9 cascaded central-moment lattice Boltzmann schemes of
+ * Hajabdollahi, Premnath & Welch, "Central moment lattice Boltzmann method using
+ * a pressure-based formulation for multiphase flows at high density ratios and
+ * including effects of surface tension and Marangoni stresses" (arXiv:1909.04166).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the checker that the HIP path is
+ * compared against.  Only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark may load it.  It shares no code, header, table or
+ * constant generator with the GPU library.
+ *
+ * What it computes, in the paper's order and notation (Secs. 2-5):
+ *   O1  phi = sum_a f_a                                      (Sec. 5, last eq.)
+ *   O2  ghost extension of phi (periodic wrap, or mirror at a halfway wall)
+ *   O3  grad phi by the isotropic D2Q9 stencil, |grad phi|, n  (Sec. 4, eq. fluidviscosity text)
+ *   O4  div n by the same stencil (or, chemical-potential variant: lap phi, mu_phi)
+ *   O5  rho, mu by linear interpolation in phi              (Eq. sfluidpropertiesinterpolation)
+ *   O6  F_s (geometric form with Marangoni term), F_ext, F_t (Eqs. surfacetensiongeometric,
+ *       surfacetensiongeometricsurfactantsxcomp/ycomp)
+ *   O7  u from the first moment of gbar                      (Eq. hydrodynamicfields)
+ *   O8  pbar = sum gbar, grad pbar, F_p, p, psi              (Eqs. netgradientpressureforce, hydrodynamicfields)
+ *   O9  raw source moments sigma'_mn                         (Sec. 4, after Eq. matchingmoments)
+ *   O10 m^s'_j and delta g^s_a                               (Eq. cumulativesourcetermcomponents)
+ *   O11 raw moments of gbar and h_0..h_8                     (Eq. cascadedcollisionoperator)
+ *   O12 post-collision gbar                                  (Eq. postcollisioncascadedLBscheme)
+ *   O13 raw moments of f, g_0..g_8 and post-collision f      (Sec. 5)
+ *   O14 pull streaming, halfway bounce-back at walls         (Eqs. ACEstreamingLB and Sec. 4 streaming)
+ *
+ * Readings taken where the paper is silent or has typos (each is listed in the
+ * design notes of the repository):
+ *   - rho(phi), mu(phi) interpolate from phase B (phi=0) to phase A (phi=1):
+ *     the printed (phi - phi_A) is read as (phi - phi_B).
+ *   - kappa~ = 1.5 sigma W (gamma * int (dphi/dzeta)^2 = 1 for the tanh profile).
+ *   - c_s^2 = c_sphi^2 = 1/3.
+ *   - in m^s'_8 the coefficient of sigma'_00 is +4 (the projection on K_8),
+ *     not the printed -8 (constant MS8_C00 below).
+ *   - in g_7 the term -(3/2) u_y g_3 is read as -(3/2) u_x g_3.
+ *   - sigma'_21 = sigma'_12 = sigma'_22 = 0 (third and higher order dropped).
+ *   - the gradient of p uses pbar = sum gbar at time t.
+ *   - n = 0 where |grad phi| < 1e-12.
+ *   - walls are halfway bounce-back; ghost scalars are mirrored across walls.
+ *   - F_ext = (rho - rho_ref) g, rho_ref selectable (mean of the phases by default).
+ *   - initial state f_a = w_a phi0, gbar_a = 0.
+ *
+ * Parity status: the per-node collision functions are pinned by brute-force
+ * central-moment solves and invariants, the stencils by exact polynomials, the
+ * whole step by conservation, symmetry and analytic laws (see tests).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define Q 9
+
+/* D2Q9 particle velocities in the paper's order (Eq. particlevelocities). */
+static const int EX[Q] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+static const int EY[Q] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+/* Opposite direction of each velocity. */
+static const int OPP[Q] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+/* Standard D2Q9 lattice weights (used only by the stencils and the initial state). */
+static const double WT[Q] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                             1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+
+static const double CS2 = 1.0 / 3.0; /* c_s^2 = c_sphi^2 (D2Q9, dx = dt = 1) */
+/* Coefficient of sigma'_00 in <K_8|S> (reading: +4; the paper prints -8). */
+static const double MS8_C00 = 4.0;
+/* Threshold below which the interface normal is set to zero. */
+static const double N_EPS = 1e-12;
+
+enum { ORC_PERIODIC = 0, ORC_WALL = 1 };
+enum { ORC_FREF_MEAN = 0, ORC_FREF_LIGHT = 1, ORC_FREF_HEAVY = 2, ORC_FREF_NONE = 3 };
+enum { ORC_ST_GEOMETRIC = 0, ORC_ST_CHEMPOT = 1 };
+
+typedef struct {
+    int32_t nx, ny;
+    int32_t bc_y;             /* ORC_PERIODIC or ORC_WALL (x is always periodic) */
+    int32_t force_ref;        /* reference density of the body force */
+    int32_t st_form;          /* surface-tension form */
+    int32_t pad_;
+    double rho_A, rho_B;      /* phase A (phi = 1), phase B (phi = 0) */
+    double nu_A, nu_B;        /* kinematic viscosities */
+    double sigma0, sigma_T;   /* sigma(y) = sigma0 + sigma_T * T(y) */
+    double T0, dTdy, y_ref;   /* T(y) = T0 + dTdy * (y - y_ref) */
+    double W, M;              /* interface width, mobility */
+    double gx, gy;            /* body-force acceleration vector */
+} orc_params;
+
+typedef struct {
+    orc_params P;
+    int64_t N;
+    int64_t step;
+    double *f, *g;   /* pre-collision distributions [a][y][x] */
+    double *ft, *gt; /* post-collision scratch [a][y][x] */
+    /* per-node coupling fields at time t */
+    double *phi, *pbar, *rho;
+    double *gx_, *gy_, *nnx, *nny, *mag2; /* on (ny+2) rows: one ghost row per side */
+    double *divn, *mu_phi;                /* divn on ny rows, mu_phi on (ny+2) rows */
+    double *ux, *uy, *p, *psi, *Ftx, *Fty, *Fpx, *Fpy;
+} orc_state;
+
+/* ---------------------------------------------------------------- indexing */
+
+static inline int wrap(int i, int n) { i %= n; return i < 0 ? i + n : i; }
+
+/* Row index of a (possibly ghost) row j: periodic wrap, or mirror across a
+ * halfway wall at y = -1/2 and y = ny - 1/2. */
+static inline int row_of(const orc_params *P, int j) {
+    if (P->bc_y == ORC_PERIODIC) return wrap(j, P->ny);
+    if (j < 0) return -1 - j;
+    if (j >= P->ny) return 2 * P->ny - 1 - j;
+    return j;
+}
+
+static inline double phi_at(const orc_state *S, int i, int j) {
+    return S->phi[(int64_t)row_of(&S->P, j) * S->P.nx + wrap(i, S->P.nx)];
+}
+static inline double pbar_at(const orc_state *S, int i, int j) {
+    return S->pbar[(int64_t)row_of(&S->P, j) * S->P.nx + wrap(i, S->P.nx)];
+}
+/* fields stored with one ghost row on each side: row j in [-1, ny] */
+static inline int64_t gidx(const orc_state *S, int i, int j) {
+    return (int64_t)(j + 1) * S->P.nx + wrap(i, S->P.nx);
+}
+/* For ghost rows beyond the range stored, use the periodic image. */
+static inline int64_t gidx_any(const orc_state *S, int i, int j) {
+    if (S->P.bc_y == ORC_PERIODIC) j = wrap(j, S->P.ny);
+    return gidx(S, i, j);
+}
+
+/* -------------------------------------------------- per-node stencils (O3, O4) */
+
+/* Isotropic second-order gradient of a sampled field:
+ * d_i q(x) = (1/c_s^2) sum_a w_a e_ai q(x + e_a). q9[a] = q(x + e_a). */
+void orc_grad9(const double q9[Q], double *dx, double *dy) {
+    double sx = 0, sy = 0;
+    for (int a = 0; a < Q; ++a) {
+        sx += WT[a] * EX[a] * q9[a];
+        sy += WT[a] * EY[a] * q9[a];
+    }
+    *dx = sx / CS2;
+    *dy = sy / CS2;
+}
+
+/* Isotropic second-order Laplacian: lap q = (2/c_s^2) sum_a w_a (q(x+e_a) - q(x)). */
+double orc_lap9(const double q9[Q]) {
+    double s = 0;
+    for (int a = 0; a < Q; ++a) s += WT[a] * (q9[a] - q9[0]);
+    return 2.0 * s / CS2;
+}
+
+/* ---------------------------------------------- hydrodynamic collision (O9-O12) */
+
+/*
+ * One node of the pressure-based cascaded scheme (Sec. 4).
+ * Inputs: gbar[9] pre-collision, p, rho, psi = p - rho c_s^2, u, total force F_t,
+ * net gradient-pressure force F_p, relaxation rates om[9].
+ * Output: post-collision gbar (Eq. postcollisioncascadedLBscheme).
+ */
+void orc_hydro_collide(const double gbar[Q], double p, double rho, double psi,
+                       double ux, double uy, double Ftx, double Fty,
+                       double Fpx, double Fpy, const double om[Q], double out[Q]) {
+    const double c2 = CS2;
+
+    /* O9: raw moments of the cumulative source (binomial transform of the matched
+     * central moments, third and fourth order set to zero). */
+    const double Gp = Fpx * ux + Fpy * uy; /* Gamma^p_00 = F_p . u */
+    const double s00 = Gp;
+    const double s10 = c2 * Ftx;
+    const double s01 = c2 * Fty;
+    const double s20 = 2.0 * c2 * (Ftx * ux + Fpx * ux) + c2 * Gp;
+    const double s02 = 2.0 * c2 * (Fty * uy + Fpy * uy) + c2 * Gp;
+    const double s11 = c2 * (Ftx * uy + Fty * ux) + c2 * (Fpx * uy + Fpy * ux);
+    const double s21 = 0.0, s12 = 0.0, s22 = 0.0;
+
+    /* O10: projections on the orthogonal basis scaled by (1 - omega_j / 2). */
+    double ms[Q];
+    ms[0] = (1.0 - 0.5 * om[0]) * s00;
+    ms[1] = (1.0 - 0.5 * om[1]) * s10;
+    ms[2] = (1.0 - 0.5 * om[2]) * s01;
+    ms[3] = (1.0 - 0.5 * om[3]) * (3.0 * (s20 + s02) - 4.0 * s00);
+    ms[4] = (1.0 - 0.5 * om[4]) * (s20 - s02);
+    ms[5] = (1.0 - 0.5 * om[5]) * s11;
+    ms[6] = (1.0 - 0.5 * om[6]) * (-3.0 * s21 + 2.0 * s01);
+    ms[7] = (1.0 - 0.5 * om[7]) * (-3.0 * s12 + 2.0 * s10);
+    ms[8] = (1.0 - 0.5 * om[8]) * (9.0 * s22 - 6.0 * (s20 + s02) + MS8_C00 * s00);
+
+    /* delta g^s = K^{-1} m^s' written out row by row. */
+    double dgs[Q];
+    dgs[0] = (ms[0] - ms[3] + ms[8]) / 9.0;
+    dgs[1] = (4 * ms[0] + 6 * ms[1] - ms[3] + 9 * ms[4] + 6 * ms[7] - 2 * ms[8]) / 36.0;
+    dgs[2] = (4 * ms[0] + 6 * ms[2] - ms[3] - 9 * ms[4] + 6 * ms[6] - 2 * ms[8]) / 36.0;
+    dgs[3] = (4 * ms[0] - 6 * ms[1] - ms[3] + 9 * ms[4] - 6 * ms[7] - 2 * ms[8]) / 36.0;
+    dgs[4] = (4 * ms[0] - 6 * ms[2] - ms[3] - 9 * ms[4] - 6 * ms[6] - 2 * ms[8]) / 36.0;
+    dgs[5] = (4 * ms[0] + 6 * ms[1] + 6 * ms[2] + 2 * ms[3] + 9 * ms[5] - 3 * ms[6] - 3 * ms[7] + ms[8]) / 36.0;
+    dgs[6] = (4 * ms[0] - 6 * ms[1] + 6 * ms[2] + 2 * ms[3] - 9 * ms[5] - 3 * ms[6] + 3 * ms[7] + ms[8]) / 36.0;
+    dgs[7] = (4 * ms[0] - 6 * ms[1] - 6 * ms[2] + 2 * ms[3] + 9 * ms[5] + 3 * ms[6] + 3 * ms[7] + ms[8]) / 36.0;
+    dgs[8] = (4 * ms[0] + 6 * ms[1] - 6 * ms[2] + 2 * ms[3] - 9 * ms[5] + 3 * ms[6] - 3 * ms[7] + ms[8]) / 36.0;
+
+    /* O11: raw moments eta'_mn of gbar. */
+    double e20 = 0, e02 = 0, e11 = 0, e21 = 0, e12 = 0, e22 = 0;
+    for (int a = 0; a < Q; ++a) {
+        const double ex = EX[a], ey = EY[a], g = gbar[a];
+        e20 += g * ex * ex;
+        e02 += g * ey * ey;
+        e11 += g * ex * ey;
+        e21 += g * ex * ex * ey;
+        e12 += g * ex * ey * ey;
+        e22 += g * ex * ex * ey * ey;
+    }
+
+    /* Moment changes h_0..h_8 as printed (Eq. cascadedcollisionoperator). */
+    const double ux2 = ux * ux, uy2 = uy * uy;
+    double h[Q];
+    h[0] = 0.5 * om[0] * Gp / 9.0;
+    h[1] = 0.5 * om[1] * c2 * Ftx / 6.0;
+    h[2] = 0.5 * om[2] * c2 * Fty / 6.0;
+    h[3] = om[3] / 12.0 * (2.0 * p * c2 + rho * c2 * (ux2 + uy2) - (e20 + e02));
+    h[4] = om[4] / 4.0 * (rho * c2 * (ux2 - uy2) - (e20 - e02));
+    h[5] = om[5] / 4.0 * (rho * c2 * ux * uy - e11);
+    h[6] = om[6] / 4.0 * (psi * (c2 + ux2) * uy + e21 - uy * e20 - 2.0 * ux * e11
+                          + 3.0 * c2 * rho * ux2 * uy - ux2 * uy * p)
+           - uy * (1.5 * h[3] + 0.5 * h[4]) - 2.0 * ux * h[5];
+    h[7] = om[7] / 4.0 * (psi * (c2 + uy2) * ux + e12 - 2.0 * uy * e11 - ux * e02
+                          + 3.0 * c2 * rho * ux * uy2 - ux * uy2 * p)
+           - ux * (1.5 * h[3] - 0.5 * h[4]) - 2.0 * uy * h[5];
+    h[8] = om[8] / 4.0 * (c2 * c2 * c2 * rho + psi * (c2 + ux2) * (c2 + uy2) - e22
+                          + 2.0 * (uy * e21 + ux * e12) - (uy2 * e20 + ux2 * e02)
+                          - 4.0 * ux * uy * e11 + 4.0 * c2 * rho * ux2 * uy2 - ux2 * uy2 * p)
+           - 2.0 * h[3] - 0.5 * uy2 * (3.0 * h[3] + h[4]) - 0.5 * ux2 * (3.0 * h[3] - h[4])
+           - 4.0 * ux * uy * h[5] - 2.0 * uy * h[6] - 2.0 * ux * h[7];
+
+    /* O12: post-collision values, K . h expanded row by row, plus the source. */
+    out[0] = gbar[0] + (h[0] - 4.0 * (h[3] - h[8])) + dgs[0];
+    out[1] = gbar[1] + (h[0] + h[1] - h[3] + h[4] + 2.0 * (h[7] - h[8])) + dgs[1];
+    out[2] = gbar[2] + (h[0] + h[2] - h[3] - h[4] + 2.0 * (h[6] - h[8])) + dgs[2];
+    out[3] = gbar[3] + (h[0] - h[1] - h[3] + h[4] - 2.0 * (h[7] + h[8])) + dgs[3];
+    out[4] = gbar[4] + (h[0] - h[2] - h[3] - h[4] - 2.0 * (h[6] + h[8])) + dgs[4];
+    out[5] = gbar[5] + (h[0] + h[1] + h[2] + 2.0 * h[3] + h[5] - h[6] - h[7] + h[8]) + dgs[5];
+    out[6] = gbar[6] + (h[0] - h[1] + h[2] + 2.0 * h[3] - h[5] - h[6] + h[7] + h[8]) + dgs[6];
+    out[7] = gbar[7] + (h[0] - h[1] - h[2] + 2.0 * h[3] + h[5] + h[6] + h[7] + h[8]) + dgs[7];
+    out[8] = gbar[8] + (h[0] + h[1] - h[2] + 2.0 * h[3] - h[5] + h[6] - h[7] + h[8]) + dgs[8];
+}
+
+/* ------------------------------------------------ phase-field collision (O13) */
+
+/*
+ * One node of the conservative Allen-Cahn cascaded scheme (Sec. 5).
+ * Inputs: f[9], phi = sum f, u, mobility M, theta, normal n, rates om[9].
+ * Output: post-collision f.
+ */
+void orc_ace_collide(const double f[Q], double phi, double ux, double uy,
+                     double M, double theta, double nx, double ny,
+                     const double om[Q], double out[Q]) {
+    const double c2 = CS2;
+    double k10 = 0, k01 = 0, k20 = 0, k02 = 0, k11 = 0, k21 = 0, k12 = 0, k22 = 0;
+    for (int a = 0; a < Q; ++a) {
+        const double ex = EX[a], ey = EY[a], v = f[a];
+        k10 += v * ex;
+        k01 += v * ey;
+        k20 += v * ex * ex;
+        k02 += v * ey * ey;
+        k11 += v * ex * ey;
+        k21 += v * ex * ex * ey;
+        k12 += v * ex * ey * ey;
+        k22 += v * ex * ex * ey * ey;
+    }
+    const double ux2 = ux * ux, uy2 = uy * uy;
+    double g[Q];
+    g[0] = 0.0;
+    g[1] = om[1] / 6.0 * (phi * ux + M * theta * nx - k10);
+    g[2] = om[2] / 6.0 * (phi * uy + M * theta * ny - k01);
+    g[3] = om[3] / 12.0 * (2.0 * c2 * phi - (ux2 + uy2) * phi - (k20 + k02)
+                           + 2.0 * (ux * k10 + uy * k01))
+           + ux * g[1] + uy * g[2];
+    g[4] = om[4] / 4.0 * (-(ux2 - uy2) * phi - (k20 - k02) + 2.0 * (ux * k10 - uy * k01))
+           + 3.0 * (ux * g[1] - uy * g[2]);
+    g[5] = om[5] / 4.0 * (-ux * uy * phi - k11 + (ux * k01 + uy * k10))
+           + 1.5 * (ux * g[2] + uy * g[1]);
+    g[6] = om[6] / 4.0 * (-ux2 * uy * phi + k21 - uy * k20 - 2.0 * ux * k11
+                          + 2.0 * ux * uy * k10 + ux2 * k01)
+           + 3.0 * ux * uy * g[1] + (1.5 * ux2 + 1.0) * g[2]
+           - 1.5 * uy * g[3] - 0.5 * uy * g[4] - 2.0 * ux * g[5];
+    /* reading: the g_3 term carries u_x (mirror image of g_6). */
+    g[7] = om[7] / 4.0 * (-ux * uy2 * phi + k12 - ux * k02 - 2.0 * uy * k11
+                          + 2.0 * ux * uy * k01 + uy2 * k10)
+           + (1.5 * uy2 + 1.0) * g[1] + 3.0 * ux * uy * g[2]
+           - 1.5 * ux * g[3] + 0.5 * ux * g[4] - 2.0 * uy * g[5];
+    g[8] = om[8] / 4.0 * (c2 * c2 * phi - k22 + 2.0 * (ux * k12 + uy * k21)
+                          - (uy2 * k20 + ux2 * k02) - 4.0 * ux * uy * k11
+                          + 2.0 * (ux * uy2 * k10 + ux2 * uy * k01) - ux2 * uy2 * phi)
+           + (2.0 * ux + 3.0 * ux * uy2) * g[1] + (2.0 * uy + 3.0 * ux2 * uy) * g[2]
+           - (2.0 + 1.5 * (ux2 + uy2)) * g[3] + 0.5 * (ux2 - uy2) * g[4]
+           - 4.0 * ux * uy * g[5] - 2.0 * uy * g[6] - 2.0 * ux * g[7];
+
+    out[0] = f[0] + (g[0] - 4.0 * (g[3] - g[8]));
+    out[1] = f[1] + (g[0] + g[1] - g[3] + g[4] + 2.0 * (g[7] - g[8]));
+    out[2] = f[2] + (g[0] + g[2] - g[3] - g[4] + 2.0 * (g[6] - g[8]));
+    out[3] = f[3] + (g[0] - g[1] - g[3] + g[4] - 2.0 * (g[7] + g[8]));
+    out[4] = f[4] + (g[0] - g[2] - g[3] - g[4] - 2.0 * (g[6] + g[8]));
+    out[5] = f[5] + (g[0] + g[1] + g[2] + 2.0 * g[3] + g[5] - g[6] - g[7] + g[8]);
+    out[6] = f[6] + (g[0] - g[1] + g[2] + 2.0 * g[3] - g[5] - g[6] + g[7] + g[8]);
+    out[7] = f[7] + (g[0] - g[1] - g[2] + 2.0 * g[3] + g[5] + g[6] + g[7] + g[8]);
+    out[8] = f[8] + (g[0] + g[1] - g[2] + 2.0 * g[3] - g[5] + g[6] - g[7] + g[8]);
+}
+
+/* ------------------------------------------------------------ grid state */
+
+static double sigma_of_y(const orc_params *P, double y) {
+    return P->sigma0 + P->sigma_T * (P->T0 + P->dTdy * (y - P->y_ref));
+}
+
+static double rho_ref_of(const orc_params *P) {
+    switch (P->force_ref) {
+    case ORC_FREF_LIGHT: return P->rho_A < P->rho_B ? P->rho_A : P->rho_B;
+    case ORC_FREF_HEAVY: return P->rho_A > P->rho_B ? P->rho_A : P->rho_B;
+    case ORC_FREF_NONE: return 0.0;
+    default: return 0.5 * (P->rho_A + P->rho_B);
+    }
+}
+
+void orc_destroy(orc_state *S) {
+    if (!S) return;
+    double **bufs[] = {&S->f, &S->g, &S->ft, &S->gt, &S->phi, &S->pbar, &S->rho,
+                       &S->gx_, &S->gy_, &S->nnx, &S->nny, &S->mag2, &S->divn, &S->mu_phi,
+                       &S->ux, &S->uy, &S->p, &S->psi, &S->Ftx, &S->Fty, &S->Fpx, &S->Fpy};
+    for (size_t i = 0; i < sizeof(bufs) / sizeof(bufs[0]); ++i) free(*bufs[i]);
+    free(S);
+}
+
+/* Returns 0 on success, -1 on invalid parameters, -2 on allocation failure. */
+int orc_create(const orc_params *P, orc_state **out) {
+    *out = NULL;
+    if (P->nx < 4 || P->ny < 4 || !(P->W > 0) || !(P->M > 0) || !(P->rho_A > 0) ||
+        !(P->rho_B > 0) || !(P->nu_A > 0) || !(P->nu_B > 0))
+        return -1;
+    orc_state *S = (orc_state *)calloc(1, sizeof(orc_state));
+    if (!S) return -2;
+    S->P = *P;
+    S->N = (int64_t)P->nx * P->ny;
+    const int64_t N = S->N, NG = (int64_t)P->nx * (P->ny + 2);
+    int ok = 1;
+#define ALLOC(ptr, n) do { (ptr) = (double *)calloc((size_t)(n), sizeof(double)); ok &= (ptr) != NULL; } while (0)
+    ALLOC(S->f, Q * N); ALLOC(S->g, Q * N); ALLOC(S->ft, Q * N); ALLOC(S->gt, Q * N);
+    ALLOC(S->phi, N); ALLOC(S->pbar, N); ALLOC(S->rho, N);
+    ALLOC(S->gx_, NG); ALLOC(S->gy_, NG); ALLOC(S->nnx, NG); ALLOC(S->nny, NG); ALLOC(S->mag2, NG);
+    ALLOC(S->divn, N); ALLOC(S->mu_phi, NG);
+    ALLOC(S->ux, N); ALLOC(S->uy, N); ALLOC(S->p, N); ALLOC(S->psi, N);
+    ALLOC(S->Ftx, N); ALLOC(S->Fty, N); ALLOC(S->Fpx, N); ALLOC(S->Fpy, N);
+#undef ALLOC
+    if (!ok) { orc_destroy(S); return -2; }
+    *out = S;
+    return 0;
+}
+
+/* Initial state: f_a = w_a phi0, gbar_a = 0 (u = 0, p = 0). */
+void orc_init(orc_state *S, const double *phi0) {
+    const int64_t N = S->N;
+    for (int a = 0; a < Q; ++a)
+        for (int64_t k = 0; k < N; ++k) {
+            S->f[a * N + k] = WT[a] * phi0[k];
+            S->g[a * N + k] = 0.0;
+        }
+    S->step = 0;
+}
+
+void orc_set_dist(orc_state *S, const double *f, const double *g, int64_t step) {
+    memcpy(S->f, f, sizeof(double) * Q * S->N);
+    memcpy(S->g, g, sizeof(double) * Q * S->N);
+    S->step = step;
+}
+
+void orc_get_dist(const orc_state *S, double *f, double *g) {
+    if (f) memcpy(f, S->f, sizeof(double) * Q * S->N);
+    if (g) memcpy(g, S->g, sizeof(double) * Q * S->N);
+}
+
+int64_t orc_step_count(const orc_state *S) { return S->step; }
+
+/* O1-O8: every coupling field at time t from the pre-collision state. */
+static void orc_fields_internal(orc_state *S) {
+    const orc_params *P = &S->P;
+    const int nx = P->nx, ny = P->ny;
+    const int64_t N = S->N;
+    const double dRho = P->rho_A - P->rho_B;
+    const double muA = P->rho_A * P->nu_A, muB = P->rho_B * P->nu_B;
+    (void)muA; (void)muB;
+
+    /* O1: phi = sum_a f_a ; O8 (first part): pbar = sum_a gbar_a. */
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            const int64_t k = (int64_t)j * nx + i;
+            double sf = 0, sg = 0;
+            for (int a = 0; a < Q; ++a) { sf += S->f[a * N + k]; sg += S->g[a * N + k]; }
+            S->phi[k] = sf;
+            S->pbar[k] = sg;
+        }
+
+    /* O2 + O3: grad phi, |grad phi|^2 and n on interior rows and one ghost row
+     * per side, sampling phi through its ghost extension. */
+#pragma omp parallel for schedule(static)
+    for (int j = -1; j <= ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            double q9[Q], dx, dy;
+            for (int a = 0; a < Q; ++a) q9[a] = phi_at(S, i + EX[a], j + EY[a]);
+            orc_grad9(q9, &dx, &dy);
+            const double m2 = dx * dx + dy * dy, m = sqrt(m2);
+            const int64_t g = gidx(S, i, j);
+            S->gx_[g] = dx;
+            S->gy_[g] = dy;
+            S->mag2[g] = m2;
+            if (m < N_EPS) { S->nnx[g] = 0.0; S->nny[g] = 0.0; }
+            else { S->nnx[g] = dx / m; S->nny[g] = dy / m; }
+            if (P->st_form == ORC_ST_CHEMPOT) {
+                /* O4 variant: chemical potential with beta = 12 sigma / W and
+                 * kappa = 1.5 sigma W (Eq. surfacetensionthermodynamic). */
+                const int jr = row_of(P, j);
+                const double sig = sigma_of_y(P, (double)jr);
+                const double beta = 12.0 * sig / P->W, kap = 1.5 * sig * P->W;
+                const double ph = q9[0];
+                S->mu_phi[g] = 4.0 * beta * (ph - 1.0) * (ph - 0.0) * (ph - 0.5) - kap * orc_lap9(q9);
+            }
+        }
+
+    /* O4 .. O8 at every interior node. */
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            const int64_t k = (int64_t)j * nx + i;
+            const int64_t g0 = gidx(S, i, j);
+            const double ph = S->phi[k];
+            const double dphx = S->gx_[g0], dphy = S->gy_[g0], m2 = S->mag2[g0];
+            const double nx0 = S->nnx[g0], ny0 = S->nny[g0];
+
+            /* O5: properties (reading: interpolate from phase B at phi = 0). */
+            const double rho = P->rho_B + ph * (P->rho_A - P->rho_B);
+            const double drhox = dRho * dphx, drhoy = dRho * dphy;
+
+            /* O4 + O6: surface tension. */
+            double Fsx, Fsy;
+            const double y = (double)j;
+            if (P->st_form == ORC_ST_CHEMPOT) {
+                double q9[Q], dmx, dmy;
+                for (int a = 0; a < Q; ++a) q9[a] = S->mu_phi[gidx_any(S, i + EX[a], j + EY[a])];
+                orc_grad9(q9, &dmx, &dmy);
+                Fsx = -ph * dmx;
+                Fsy = -ph * dmy;
+                S->divn[k] = 0.0;
+            } else {
+                double qx[Q], qy[Q], a1, a2, b1, b2;
+                for (int a = 0; a < Q; ++a) {
+                    const int64_t gn = gidx_any(S, i + EX[a], j + EY[a]);
+                    qx[a] = S->nnx[gn];
+                    qy[a] = S->nny[gn];
+                }
+                orc_grad9(qx, &a1, &a2);
+                orc_grad9(qy, &b1, &b2);
+                const double divn = a1 + b2;
+                S->divn[k] = divn;
+                /* kappa~(y) = 1.5 W sigma(y); its gradient is analytic. */
+                const double kt = 1.5 * P->W * sigma_of_y(P, y);
+                const double dktx = 0.0, dkty = 1.5 * P->W * P->sigma_T * P->dTdy;
+                Fsx = -kt * m2 * divn * nx0 + m2 * ((1.0 - nx0 * nx0) * dktx - nx0 * ny0 * dkty);
+                Fsy = -kt * m2 * divn * ny0 + m2 * ((1.0 - ny0 * ny0) * dkty - nx0 * ny0 * dktx);
+            }
+            /* F_ext = (rho - rho_ref) g ; F_t = F_s + F_ext. */
+            const double rref = rho_ref_of(P);
+            const double Ftx = Fsx + (rho - rref) * P->gx;
+            const double Fty = Fsy + (rho - rref) * P->gy;
+
+            /* O7: rho c_s^2 u = sum gbar e + (1/2) c_s^2 F_t. */
+            double jx = 0, jy = 0;
+            for (int a = 0; a < Q; ++a) {
+                jx += S->g[a * N + k] * EX[a];
+                jy += S->g[a * N + k] * EY[a];
+            }
+            const double ux = (jx + 0.5 * CS2 * Ftx) / (rho * CS2);
+            const double uy = (jy + 0.5 * CS2 * Fty) / (rho * CS2);
+
+            /* O8: F_p = -grad pbar + c_s^2 grad rho ; p = pbar + (1/2) F_p . u. */
+            double q9[Q], dpx, dpy;
+            for (int a = 0; a < Q; ++a) q9[a] = pbar_at(S, i + EX[a], j + EY[a]);
+            orc_grad9(q9, &dpx, &dpy);
+            const double Fpx = -dpx + CS2 * drhox;
+            const double Fpy = -dpy + CS2 * drhoy;
+            const double p = S->pbar[k] + 0.5 * (Fpx * ux + Fpy * uy);
+
+            S->rho[k] = rho;
+            S->ux[k] = ux; S->uy[k] = uy;
+            S->p[k] = p; S->psi[k] = p - rho * CS2;
+            S->Ftx[k] = Ftx; S->Fty[k] = Fty;
+            S->Fpx[k] = Fpx; S->Fpy[k] = Fpy;
+        }
+}
+
+/* O9-O14: collide both schemes at every node and stream. */
+void orc_step(orc_state *S, int64_t nsteps) {
+    const orc_params *P = &S->P;
+    const int nx = P->nx, ny = P->ny;
+    const int64_t N = S->N;
+    const double muA = P->rho_A * P->nu_A, muB = P->rho_B * P->nu_B;
+    const double omphi = 1.0 / (0.5 + P->M / CS2); /* M = c^2 (1/omega - 1/2) */
+
+    for (int64_t s = 0; s < nsteps; ++s) {
+        orc_fields_internal(S);
+
+#pragma omp parallel for schedule(static)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const int64_t k = (int64_t)j * nx + i;
+                const double ph = S->phi[k];
+                /* mu(phi), nu = mu / rho, omega_4 = omega_5 from mu = rho c^2 (1/omega - 1/2). */
+                const double mu = muB + ph * (muA - muB);
+                const double nu = mu / S->rho[k];
+                const double omv = 1.0 / (0.5 + nu / CS2);
+                const double om_h[Q] = {1, 1, 1, 1, omv, omv, 1, 1, 1};
+                double gin[Q], gout[Q], fin[Q], fout[Q];
+                for (int a = 0; a < Q; ++a) { gin[a] = S->g[a * N + k]; fin[a] = S->f[a * N + k]; }
+                orc_hydro_collide(gin, S->p[k], S->rho[k], S->psi[k], S->ux[k], S->uy[k],
+                                  S->Ftx[k], S->Fty[k], S->Fpx[k], S->Fpy[k], om_h, gout);
+                const double om_f[Q] = {1, omphi, omphi, 1, 1, 1, 1, 1, 1};
+                const double theta = 4.0 * ph * (1.0 - ph) / P->W;
+                const int64_t g0 = gidx(S, i, j);
+                orc_ace_collide(fin, ph, S->ux[k], S->uy[k], P->M, theta,
+                                S->nnx[g0], S->nny[g0], om_f, fout);
+                for (int a = 0; a < Q; ++a) { S->gt[a * N + k] = gout[a]; S->ft[a * N + k] = fout[a]; }
+            }
+
+        /* O14: pull streaming; halfway bounce-back where the source lies beyond a wall. */
+#pragma omp parallel for schedule(static)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const int64_t k = (int64_t)j * nx + i;
+                for (int a = 0; a < Q; ++a) {
+                    const int js = j - EY[a];
+                    const int is = wrap(i - EX[a], nx);
+                    if (P->bc_y == ORC_WALL && (js < 0 || js >= ny)) {
+                        S->f[a * N + k] = S->ft[OPP[a] * N + k];
+                        S->g[a * N + k] = S->gt[OPP[a] * N + k];
+                    } else {
+                        const int64_t ks = (int64_t)wrap(js, ny) * nx + is;
+                        S->f[a * N + k] = S->ft[a * N + ks];
+                        S->g[a * N + k] = S->gt[a * N + ks];
+                    }
+                }
+            }
+        S->step++;
+    }
+}
+
+/* Macroscopic outputs at time t: phi (O1), p (O8), u (O7).  NULL skips a field. */
+void orc_fields(orc_state *S, double *phi, double *p, double *ux, double *uy) {
+    orc_fields_internal(S);
+    const size_t n = sizeof(double) * (size_t)S->N;
+    if (phi) memcpy(phi, S->phi, n);
+    if (p) memcpy(p, S->p, n);
+    if (ux) memcpy(ux, S->ux, n);
+    if (uy) memcpy(uy, S->uy, n);
+}
+
+/* Intermediate coupling fields at time t, for diagnosis of a parity failure:
+ * out[0..7][N] = grad phi x, grad phi y, n_x, n_y, div n, F_t x, F_t y, F_p x;
+ * out[8][N] = F_p y. */
+void orc_coupling(orc_state *S, double *out) {
+    orc_fields_internal(S);
+    const int nx = S->P.nx, ny = S->P.ny;
+    const int64_t N = S->N;
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            const int64_t k = (int64_t)j * nx + i, g = gidx(S, i, j);
+            out[0 * N + k] = S->gx_[g];
+            out[1 * N + k] = S->gy_[g];
+            out[2 * N + k] = S->nnx[g];
+            out[3 * N + k] = S->nny[g];
+            out[4 * N + k] = S->divn[k];
+            out[5 * N + k] = S->Ftx[k];
+            out[6 * N + k] = S->Fty[k];
+            out[7 * N + k] = S->Fpx[k];
+            out[8 * N + k] = S->Fpy[k];
+        }
+}
+
+/* Crossing of phi = 1/2 on column i, scanning upward (dir = +1, lowest crossing)
+ * or downward (dir = -1, highest crossing); linear interpolation in y; NAN if none. */
+static double crossing(const orc_state *S, int i, int dir) {
+    const int nx = S->P.nx, ny = S->P.ny;
+    if (dir > 0) {
+        for (int j = 0; j + 1 < ny; ++j) {
+            const double a = S->phi[(int64_t)j * nx + i] - 0.5, b = S->phi[(int64_t)(j + 1) * nx + i] - 0.5;
+            if ((a < 0) != (b < 0)) return j + a / (a - b);
+        }
+    } else {
+        for (int j = ny - 2; j >= 0; --j) {
+            const double a = S->phi[(int64_t)j * nx + i] - 0.5, b = S->phi[(int64_t)(j + 1) * nx + i] - 0.5;
+            if ((a < 0) != (b < 0)) return j + a / (a - b);
+        }
+    }
+    return NAN;
+}
+
+/*
+ * FP64 diagnostics at time t, out[10] =
+ *  {step, sum phi, sum rho, max |u|, dp = p(centre) - p(corner), R_eff = sqrt(sum phi / pi),
+ *   spike y (lowest phi = 1/2 crossing on column nx/2), bubble y (highest crossing on column 0),
+ *   centroid y = sum y phi / sum phi, nan flag}.
+ * Sums run in row-major order.
+ */
+void orc_diagnostics(orc_state *S, double *out) {
+    orc_fields_internal(S);
+    const int nx = S->P.nx, ny = S->P.ny;
+    double sphi = 0, srho = 0, umax = 0, sy = 0;
+    int nan = 0;
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            const int64_t k = (int64_t)j * nx + i;
+            const double ph = S->phi[k];
+            sphi += ph;
+            srho += S->rho[k];
+            sy += (double)j * ph;
+            const double um = sqrt(S->ux[k] * S->ux[k] + S->uy[k] * S->uy[k]);
+            if (!(um <= umax)) umax = um; /* also propagates NaN */
+            if (isnan(ph) || isnan(S->p[k]) || isnan(um) || isinf(ph) || isinf(S->p[k])) nan = 1;
+        }
+    out[0] = (double)S->step;
+    out[1] = sphi;
+    out[2] = srho;
+    out[3] = umax;
+    out[4] = S->p[(int64_t)(ny / 2) * nx + nx / 2] - S->p[0];
+    out[5] = sqrt(sphi / M_PI);
+    out[6] = crossing(S, nx / 2, +1);
+    out[7] = crossing(S, 0, -1);
+    out[8] = sy / sphi;
+    out[9] = nan ? 1.0 : 0.0;
+}
+
+int orc_sizeof_params(void) { return (int)sizeof(orc_params); }

@@ -1,0 +1,203 @@
+"""Seeded synthetic workloads: case parameters and initial phase fields.
+
+This module is the only code shared by the GPU path and the CPU oracle.  It
+holds problem set-ups (grid, boundary kind, fluid properties, the initial
+phase-field profile) and no step of the lattice Boltzmann method itself.
+
+A case is a plain dictionary::
+
+    nx, ny            lattice size (x contiguous in every array, index y*nx + x)
+    bc_y              "periodic" or "wall" (halfway bounce-back); x is periodic
+    rho_A, rho_B      densities of phase A (phi = 1) and phase B (phi = 0)
+    nu_A, nu_B        kinematic viscosities
+    sigma0, sigma_T   sigma(y) = sigma0 + sigma_T * T(y)
+    T0, dTdy, y_ref   T(y) = T0 + dTdy * (y - y_ref)
+    W, M              interface width and mobility of the Allen-Cahn equation
+    gx, gy            body-force acceleration; F_ext = (rho - rho_ref) g
+    force_ref         "mean" | "light" | "heavy" | "none" (rho_ref)
+    st_form           "geometric" | "chempot" (surface-tension form)
+
+Initial phase fields use the equilibrium tanh profile of the conservative
+Allen-Cahn equation (Sec. 2, Eq. hyperbolictangentprofile) with phi_A = 1,
+phi_B = 0.  Node (i, j) sits at (x, y) = (i, j); halfway walls sit at
+y = -1/2 and y = ny - 1/2.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def base_case(nx: int, ny: int, **kw) -> dict:
+    c = dict(nx=int(nx), ny=int(ny), bc_y="periodic", rho_A=1.0, rho_B=1.0,
+             nu_A=0.1, nu_B=0.1, sigma0=0.0, sigma_T=0.0, T0=0.0, dTdy=0.0,
+             y_ref=0.0, W=4.0, M=0.02, gx=0.0, gy=0.0, force_ref="mean",
+             st_form="geometric")
+    c.update(kw)
+    return c
+
+
+def tanh_profile(signed_dist: np.ndarray, W: float) -> np.ndarray:
+    """phi = 1/2 + 1/2 tanh(2 zeta / W), zeta > 0 inside phase A."""
+    return 0.5 + 0.5 * np.tanh(2.0 * signed_dist / W)
+
+
+def _grid(nx: int, ny: int):
+    y, x = np.mgrid[0:ny, 0:nx].astype(np.float64)
+    return x, y
+
+
+# ----------------------------------------------------------------- single cases
+
+def droplet(n: int = 128, R: float = 25.0, W: float = 4.0, ratio: float = 1000.0,
+            nu: float = 0.1, sigma: float = 0.01, M: float = 0.02, ny: int | None = None,
+            st_form: str = "geometric"):
+    """Stationary droplet (Laplace-Young test, Sec. 6.2): heavy drop of phase A
+    centred in a periodic box.  Light phase density 1, heavy = ratio."""
+    nx, ny = int(n), int(ny or n)
+    case = base_case(nx, ny, rho_A=float(ratio), rho_B=1.0, nu_A=nu, nu_B=nu,
+                     sigma0=sigma, W=W, M=M, st_form=st_form)
+    x, y = _grid(nx, ny)
+    r = np.hypot(x - nx / 2, y - ny / 2)
+    return case, tanh_profile(R - r, W)
+
+
+def ellipse(n: int, aspect: float, ratio: float = 1000.0, W: float = 4.0, nu: float = 0.1,
+            sigma: float = 0.01, M: float = 0.02, R_eq: float | None = None):
+    """Elliptic drop (capillary oscillation set-up, Sec. 7) of equal area to a
+    circle of radius R_eq = max(n/10, 12); semi-axes a = R_eq sqrt(r), b = R_eq / sqrt(r)."""
+    nx = ny = int(n)
+    R_eq = float(R_eq if R_eq is not None else max(n / 10.0, 12.0))
+    a, b = R_eq * math.sqrt(aspect), R_eq / math.sqrt(aspect)
+    case = base_case(nx, ny, rho_A=float(ratio), rho_B=1.0, nu_A=nu, nu_B=nu,
+                     sigma0=sigma, W=W, M=M)
+    x, y = _grid(nx, ny)
+    X, Y = x - nx / 2, y - ny / 2
+    # signed distance approximated by the radial scaling of the ellipse level set
+    s = np.sqrt((X / a) ** 2 + (Y / b) ** 2)
+    rr = np.hypot(X, Y)
+    d = np.where(s > 0, rr * (1.0 / np.maximum(s, 1e-300) - 1.0), max(a, b))
+    return case, tanh_profile(d, W)
+
+
+def rayleigh_taylor(nx: int = 256, ny: int | None = None, W: float = 4.0, ratio: float = 3.0,
+                    Re: float = 3000.0, Pe: float = 3000.0, Uc: float = 0.04):
+    """Single-mode Rayleigh-Taylor instability (Sec. 6.3): heavy phase A on top,
+    interface y0 = ny/2 + 0.1 nx cos(2 pi x / nx), walls at top and bottom.
+    g from sqrt(g L) = Uc with L = nx; equal dynamic viscosity mu = rho_A Uc L / Re;
+    mobility M = Uc L / Pe."""
+    L = int(nx)
+    ny = int(ny or 4 * L)
+    rho_A, rho_B = float(ratio), 1.0
+    g = Uc * Uc / L
+    mu = rho_A * Uc * L / Re
+    case = base_case(L, ny, bc_y="wall", rho_A=rho_A, rho_B=rho_B, nu_A=mu / rho_A,
+                     nu_B=mu / rho_B, W=W, M=Uc * L / Pe, gy=-g, force_ref="mean")
+    x, y = _grid(L, ny)
+    y0 = ny / 2 + 0.1 * L * np.cos(2 * np.pi * x / L)
+    return case, tanh_profile(y - y0, W)
+
+
+def thermocapillary(nx: int = 512, ny: int = 256, R: float = 32.0, ratio: float = 10.0,
+                    nu: float = 0.05, sigma0: float = 0.01, sigma_T: float = -5e-5,
+                    W: float = 4.0, M: float = 0.02):
+    """Marangoni drop migration (Sec. 6.7) driven by sigma(y) = sigma0 + sigma_T (y - yc):
+    drop of phase A at (nx/2, 2R) in a channel with walls at top and bottom."""
+    yc = 2.0 * R
+    case = base_case(nx, ny, bc_y="wall", rho_A=float(ratio), rho_B=1.0, nu_A=nu, nu_B=nu,
+                     sigma0=sigma0, sigma_T=sigma_T, T0=0.0, dTdy=1.0, y_ref=yc, W=W, M=M)
+    x, y = _grid(nx, ny)
+    r = np.hypot(x - nx / 2, y - yc)
+    return case, tanh_profile(R - r, W)
+
+
+def flat_interface(nx: int = 4, ny: int = 128, W: float = 4.0, ratio: float = 1000.0,
+                   nu: float = 0.1, sigma: float = 0.01, M: float = 0.02):
+    """Flat interface at y = (ny - 1)/2 between walls, phase A on top."""
+    case = base_case(nx, ny, bc_y="wall", rho_A=float(ratio), rho_B=1.0, nu_A=nu, nu_B=nu,
+                     sigma0=sigma, W=W, M=M)
+    x, y = _grid(nx, ny)
+    return case, tanh_profile(y - (ny - 1) / 2.0, W)
+
+
+def tiled(case: dict, phi0: np.ndarray, tx: int, ty: int):
+    """Periodic tiling of a periodic case: a (ty*ny) x (tx*nx) lattice."""
+    c = dict(case)
+    c["nx"], c["ny"] = case["nx"] * tx, case["ny"] * ty
+    return c, np.tile(phi0, (ty, tx))
+
+
+def uniform_phase(nx: int, ny: int, phi: float = 1.0, **kw):
+    case = base_case(nx, ny, **kw)
+    return case, np.full((ny, nx), float(phi))
+
+
+def random_case(nx: int, ny: int, seed: int, bc_y: str = "periodic", **kw):
+    """Smooth random blob field for parity tests: a sum of tanh droplets at
+    seeded positions, plus case parameters drawn from the seed."""
+    rng = np.random.default_rng(seed)
+    case = base_case(nx, ny, bc_y=bc_y, rho_A=float(np.exp(rng.uniform(np.log(3), np.log(1000)))),
+                     rho_B=1.0, nu_A=float(rng.uniform(0.02, 0.2)), nu_B=float(rng.uniform(0.02, 0.2)),
+                     sigma0=float(rng.uniform(0.001, 0.02)), W=4.0, M=float(rng.uniform(0.01, 0.05)))
+    case.update(kw)
+    x, y = _grid(nx, ny)
+    phi = np.zeros((ny, nx))
+    for _ in range(int(rng.integers(2, 5))):
+        cx, cy = rng.uniform(0, nx), rng.uniform(0, ny)
+        R = rng.uniform(0.1, 0.25) * min(nx, ny)
+        dx = (x - cx + nx / 2) % nx - nx / 2
+        dy = (y - cy + ny / 2) % ny - ny / 2 if bc_y == "periodic" else (y - cy)
+        phi = np.maximum(phi, tanh_profile(R - np.hypot(dx, dy), case["W"]))
+    return case, phi
+
+
+# ------------------------------------------------------------- named workloads
+
+def config(name: str):
+    """The named workloads: 'droplet128', 'rt256', 'thermo512', 'flat4x128'."""
+    if name == "droplet128":
+        return droplet(128, 25.0)
+    if name == "rt256":
+        return rayleigh_taylor(256, 1024)
+    if name == "thermo512":
+        return thermocapillary(512, 256)
+    if name == "flat4x128":
+        return flat_interface(4, 128)
+    raise KeyError(name)
+
+
+def batch_instances(n: int = 256, seed: int = 20190909, side_lo: int = 64, side_hi: int = 512):
+    """Uneven batch: droplet or Rayleigh-Taylor per seed, sides uniform in
+    [side_lo, side_hi], square with probability 1/2, density ratio log-uniform in
+    [3, 1000], W = 4.  Returns a list of (kind, case, phi0)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        kind = "droplet" if rng.random() < 0.5 else "rt"
+        nx = int(rng.integers(side_lo, side_hi + 1))
+        ny = nx if rng.random() < 0.5 else int(rng.integers(side_lo, side_hi + 1))
+        ratio = float(np.exp(rng.uniform(np.log(3.0), np.log(1000.0))))
+        if kind == "droplet":
+            case, phi0 = droplet(nx, 0.2 * min(nx, ny), ratio=ratio, ny=ny)
+        else:
+            case, phi0 = rayleigh_taylor(nx, ny, ratio=ratio, Re=256.0, Pe=3000.0)
+        out.append((kind, case, phi0))
+    return out
+
+
+def serve_arrivals(n: int = 1000, seed: int = 5, rate: float = 50.0, side_lo: int = 64,
+                   side_hi: int = 1024, steps_lo: int = 500, steps_hi: int = 20000):
+    """Poisson arrivals of elliptic-drop solves: square side log-uniform in
+    [side_lo, side_hi], steps uniform, aspect ratio uniform in [1.1, 1.5],
+    density ratio 1000.  Returns a list of dicts {t, side, steps, aspect}."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for _ in range(n):
+        t += float(rng.exponential(1.0 / rate))
+        side = int(round(math.exp(rng.uniform(math.log(side_lo), math.log(side_hi)))))
+        steps = int(rng.integers(steps_lo, steps_hi + 1))
+        aspect = float(rng.uniform(1.1, 1.5))
+        out.append(dict(t=t, side=side, steps=steps, aspect=aspect))
+    return out
