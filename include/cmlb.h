@@ -1,0 +1,227 @@
+/*
+ * cmlb.h -- C-ABI of the MI355X (gfx950) library that advances the coupled pair
+ * of D2Q9 cascaded central-moment lattice Boltzmann schemes of Hajabdollahi,
+ * Premnath & Welch (arXiv:1909.04166):
+ *
+ *   - the pressure-based hydrodynamic scheme for gbar (Sec. 4) with the
+ *     net-gradient pressure force F_p, the surface-tension force F_s (capillary and
+ *     Marangoni terms, Eqs. surfacetensiongeometricsurfactantsxcomp/ycomp, or the
+ *     chemical-potential form of Eq. surfacetensionthermodynamic) and a body force;
+ *   - the conservative Allen-Cahn (phase-field) scheme for f (Sec. 5);
+ *   - the isotropic finite-difference fields that couple them (grad phi, n,
+ *     div n, lap phi, chemical potential, grad rho, grad p; text after
+ *     Eq. fluidviscosity).
+ *
+ * Conventions
+ *   - Every function returns an lb_status: 0 on success, a negative code on error.
+ *   - The library never allocates device memory.  The caller passes one device
+ *     workspace (size from lb_workspace_bytes) and keeps it alive until
+ *     lb_destroy / lb_batch_destroy.  The library allocates small host-side state
+ *     (the handle, pinned host words for diagnostics).
+ *   - All device work is ordered on the caller's HIP stream, passed as void*
+ *     (a hipStream_t; NULL means the default stream).  Functions that return host
+ *     data synchronize that stream; lb_step and lb_batch_step do not.
+ *   - Host arrays of fields are FP64, row-major with index y*nx + x, whatever the
+ *     storage precision.  Distribution arrays are FP64 [9][ny][nx] in the
+ *     velocity order 0 rest, 1 +x, 2 +y, 3 -x, 4 -y, 5 (+,+), 6 (-,+), 7 (-,-),
+ *     8 (+,-) (Eq. particlevelocities).
+ *   - Node (x, y) = (i, j).  x is periodic.  y is periodic or bounded by
+ *     halfway bounce-back walls at y = -1/2 and y = ny - 1/2.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef CMLB_H
+#define CMLB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lb_status;
+enum {
+    LB_OK = 0,
+    LB_E_INVALID_ARG = -1, /* a parameter is out of range, a pointer is NULL */
+    LB_E_WORKSPACE = -2,   /* workspace too small or misaligned (256 B) */
+    LB_E_HIP = -3,         /* a HIP runtime call failed */
+    LB_E_UNSTABLE = -4,    /* a diagnostic found NaN/Inf or max|u| above the limit */
+    LB_E_UNSUPPORTED = -5, /* a valid but unimplemented option */
+    LB_E_STATE = -6        /* buffer of the wrong size for save/load */
+};
+
+enum { LB_PERIODIC = 0, LB_HALFWAY_BB = 1 };
+/* reference density of the body force F_ext = (rho - rho_ref) g */
+enum { LB_FREF_MEAN = 0, LB_FREF_LIGHT = 1, LB_FREF_HEAVY = 2, LB_FREF_NONE = 3 };
+/* surface-tension form: geometric with Marangoni term (default), or chemical potential */
+enum { LB_ST_GEOMETRIC = 0, LB_ST_CHEMPOT = 1 };
+/* storage precision of the 18 distribution planes; compute is FP64 for LB_FP64 and FP32 otherwise */
+enum { LB_FP64 = 0, LB_FP32 = 1, LB_FP32_F16 = 2, LB_FP32_BF16 = 3 };
+
+/*
+ * Problem description (Secs. 2, 4, 5).  Phase A is phi = 1, phase B is phi = 0.
+ *   rho(phi) = rho_B + phi (rho_A - rho_B), mu(phi) = mu_B + phi (mu_A - mu_B),
+ *   mu_X = rho_X nu_X; omega_4 = omega_5 = 1 / (1/2 + 3 nu(phi)); other hydro rates 1.
+ *   M = (1/omega^phi - 1/2) / 3 for the first-order ACE moments; other ACE rates 1.
+ *   sigma(y) = sigma0 + sigma_T * (T0 + dTdy * (y - y_ref)); kappa~ = 1.5 W sigma(y).
+ * Derived rates must lie in (0, 2).
+ */
+typedef struct lb_config {
+    int32_t nx, ny;          /* lattice size, each >= 8 */
+    int32_t bc_x, bc_y;      /* bc_x must be LB_PERIODIC; bc_y LB_PERIODIC or LB_HALFWAY_BB */
+    int32_t force_ref;       /* LB_FREF_* */
+    int32_t st_form;         /* LB_ST_* */
+    int32_t precision;       /* LB_FP64, LB_FP32, LB_FP32_F16, LB_FP32_BF16 */
+    int32_t diag_every;      /* >0: lb_step checks stability every diag_every steps */
+    double rho_A, rho_B;     /* densities, > 0 */
+    double nu_A, nu_B;       /* kinematic viscosities, > 0 */
+    double sigma0, sigma_T;  /* surface tension law */
+    double T0, dTdy, y_ref;  /* imposed linear temperature T(y) */
+    double W, M;             /* interface width (> 0) and mobility (> 0) */
+    double gx, gy;           /* body-force acceleration */
+    double shift_f, shift_g; /* 16-bit storage stores f_a - w_a shift_f and g_a - w_a shift_g */
+    double u_max;            /* stability limit for diagnostics (0: 0.3) */
+    int32_t tile_x;          /* strip width in nodes (64, 128 or 256); 0: autotuned */
+    int32_t tile_h;          /* rows per work item; 0: autotuned */
+} lb_config;
+
+typedef struct lb_diag {
+    double step;       /* time step of the state */
+    double sum_phi;    /* sum over nodes of phi */
+    double sum_rho;    /* sum over nodes of rho(phi) */
+    double max_u;      /* max |u| */
+    double dp_laplace; /* p(nx/2, ny/2) - p(0, 0) (Laplace-Young probe, Sec. 6.2) */
+    double r_eff;      /* sqrt(sum phi / pi) */
+    double spike_y;    /* lowest phi = 1/2 crossing on column nx/2 (NaN if none) */
+    double bubble_y;   /* highest phi = 1/2 crossing on column 0 (NaN if none) */
+    double centroid_y; /* sum y phi / sum phi */
+    double nan_flag;   /* 1 if any phi, p or u is NaN/Inf */
+} lb_diag;
+
+typedef struct lb_handle lb_handle;
+typedef struct lb_batch lb_batch;
+
+/* Static string for a status code. */
+const char* lb_status_string(lb_status s);
+
+/* Device workspace bytes for one lattice (two copies of the 18 planes in the
+ * storage precision, four FP64 field planes, diagnostics and the work list).
+ * Errors: LB_E_INVALID_ARG. */
+lb_status lb_workspace_bytes(const lb_config* cfg, uint64_t* bytes);
+
+/* Validates cfg, lays the lattice out in dev_ws (device memory, 256-byte aligned,
+ * at least lb_workspace_bytes), picks the tile shape and returns a handle.
+ * The state is undefined until lb_init_fields or lb_load_state / lb_set_dist.
+ * Errors: LB_E_INVALID_ARG, LB_E_WORKSPACE, LB_E_HIP. */
+lb_status lb_create(const lb_config* cfg, void* dev_ws, uint64_t ws_bytes, void* stream,
+                    lb_handle** out);
+
+/* Initial state at t = 0 (Sec. 5 / readings): f_a = w_a phi0, gbar_a = 0 (p = 0, u = 0).
+ * phi0: host, ny*nx FP64, caller-owned, read before return.  Synchronizes. */
+lb_status lb_init_fields(lb_handle* h, const double* phi0);
+
+/* Advances n time steps (stream-collide of both schemes per step).  Enqueued
+ * asynchronously on the handle's stream.  With diag_every > 0, a stability check
+ * runs every diag_every steps; LB_E_UNSTABLE is returned by the first call after
+ * a check has found NaN/Inf or max|u| > u_max. */
+lb_status lb_step(lb_handle* h, int64_t n);
+
+/* phi (Sec. 5, zeroth moment of f), p and u (Eq. hydrodynamicfields) at the
+ * current time.  Host buffers of ny*nx FP64; NULL skips a field.  Synchronizes. */
+lb_status lb_get_fields(lb_handle* h, double* phi, double* p, double* ux, double* uy);
+
+/* Writes the coupling fields at the current time into a caller-owned DEVICE
+ * buffer of 9*ny*nx FP64: grad phi x, grad phi y, n_x, n_y, div n, F_t x, F_t y,
+ * F_p x, F_p y.  For diagnosis of parity failures.  Synchronizes. */
+lb_status lb_get_coupling(lb_handle* h, double* dev_out);
+
+/* FP64 diagnostics at the current time (sums in a fixed order).  Synchronizes. */
+lb_status lb_diagnostics(lb_handle* h, lb_diag* out);
+
+/* Post-streaming distributions f, gbar at the current time (FP64 host arrays of
+ * 9*ny*nx each; NULL skips one).  Synchronizes. */
+lb_status lb_get_dist(lb_handle* h, double* f, double* g);
+
+/* Sets the state at time `step` from post-streaming FP64 distributions (host,
+ * 9*ny*nx each), rounded to the storage precision.  Synchronizes. */
+lb_status lb_set_dist(lb_handle* h, const double* f, const double* g, int64_t step);
+
+/* Bytes of a checkpoint: the 18 stored planes in the storage precision plus the
+ * step counter.  save/load copy them to/from a caller-owned host buffer; a
+ * resumed run is bit-identical.  Errors: LB_E_STATE on a size mismatch. */
+lb_status lb_state_bytes(lb_handle* h, uint64_t* bytes);
+lb_status lb_save_state(lb_handle* h, void* host, uint64_t bytes);
+lb_status lb_load_state(lb_handle* h, const void* host, uint64_t bytes);
+
+/* Current step counter. */
+lb_status lb_get_step(lb_handle* h, int64_t* step);
+
+/* Frees host-side state.  The workspace stays the caller's. */
+void lb_destroy(lb_handle* h);
+
+/* ------------------------------------------------------------------ batch ----
+ * Many independent lattices of uneven sizes advanced by ONE persistent kernel
+ * launch per step over a shared work list of (instance, strip, rows) items.
+ * All instances share the storage precision cfgs[0].precision and one tile
+ * shape.  A slot holds one lattice; slots can be filled and emptied between
+ * steps (continuous batching).  Results of a slot do not depend on the other
+ * slots (bit-identical to the same lattice alone). */
+
+/* Workspace bytes for a batch with `slots` slots whose lattices are the
+ * largest that fit in `node_capacity` nodes in total.
+ * Errors: LB_E_INVALID_ARG. */
+lb_status lb_batch_workspace_bytes(int32_t slots, int64_t node_capacity, int32_t precision,
+                                   uint64_t* bytes);
+
+/* Creates an empty batch over dev_ws. tile_x / tile_h as in lb_config (0: defaults). */
+lb_status lb_batch_create(int32_t slots, int64_t node_capacity, int32_t precision,
+                          int32_t tile_x, int32_t tile_h, void* dev_ws, uint64_t ws_bytes,
+                          void* stream, lb_batch** out);
+
+/* Places a lattice in a free slot and initializes it like lb_init_fields.
+ * Returns the slot index in *slot.  Errors: LB_E_INVALID_ARG (bad config or
+ * precision mismatch), LB_E_WORKSPACE (no free slot or not enough free nodes).
+ * Synchronizes. */
+lb_status lb_batch_add(lb_batch* b, const lb_config* cfg, const double* phi0, int32_t* slot);
+
+/* Frees a slot (its storage is reused by later adds). */
+lb_status lb_batch_remove(lb_batch* b, int32_t slot);
+
+/* Advances every occupied slot by n steps: n launches of the persistent
+ * kernel, replayed from a captured HIP graph when use_graph != 0. Asynchronous. */
+lb_status lb_batch_step(lb_batch* b, int64_t n, int32_t use_graph);
+
+/* Fields / diagnostics / step of one slot, as for a single lattice. Synchronize. */
+lb_status lb_batch_get_fields(lb_batch* b, int32_t slot, double* phi, double* p, double* ux,
+                              double* uy);
+lb_status lb_batch_diagnostics(lb_batch* b, int32_t slot, lb_diag* out);
+lb_status lb_batch_get_step(lb_batch* b, int32_t slot, int64_t* step);
+
+/* Number of occupied slots and nodes in use. */
+lb_status lb_batch_usage(lb_batch* b, int32_t* used_slots, int64_t* used_nodes);
+
+void lb_batch_destroy(lb_batch* b);
+
+/* ------------------------------------------------------------- measurement ---
+ * Average duration in milliseconds of the fused step kernel over the last
+ * lb_step / lb_batch_step call that enabled timing (HIP events on the handle's
+ * stream around the kernel launches).  timing_enable(1) before the step call,
+ * read after synchronizing. */
+lb_status lb_timing_enable(lb_handle* h, int32_t on);
+lb_status lb_timing_read(lb_handle* h, double* ms_per_step, int64_t* steps);
+lb_status lb_batch_timing_enable(lb_batch* b, int32_t on);
+lb_status lb_batch_timing_read(lb_batch* b, double* ms_per_step, int64_t* steps);
+
+/* Tile shape chosen for the handle (after autotuning when tile_x/tile_h were 0). */
+lb_status lb_get_tile(lb_handle* h, int32_t* tile_x, int32_t* tile_h);
+
+/* sizeof(lb_config) and sizeof(lb_diag) as compiled, for binding checks. */
+lb_status lb_struct_sizes(uint64_t* config_bytes, uint64_t* diag_bytes);
+
+/* Device-to-device copy kernel over n bytes (attainable-bandwidth reference for
+ * the roofline).  Enqueued on `stream`; src/dst are device pointers, 16-byte aligned. */
+lb_status lb_copy_kernel(void* dst, const void* src, uint64_t n, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CMLB_H */

@@ -1,0 +1,1065 @@
+// lb_capi.hip -- host runtime behind the C-ABI of include/cmlb.h: parameter
+// validation, workspace layout, work lists, stepping (eager or replayed HIP
+// graphs), diagnostics, checkpoints, the batch of uneven lattices with its node
+// pool, and the tile autotuner.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "lb_internal.hpp"
+
+using namespace cmlb;
+
+namespace {
+
+constexpr uint64_t kAlign = 256;
+constexpr int kMinH = 8;
+
+uint64_t align_up(uint64_t v, uint64_t a = kAlign) { return (v + a - 1) / a * a; }
+
+int store_bytes(int prec) {
+    switch (prec) {
+    case LB_FP64: return 8;
+    case LB_FP32: return 4;
+    case LB_FP32_F16:
+    case LB_FP32_BF16: return 2;
+    }
+    return 0;
+}
+
+int64_t plane_elems(int nx, int ny) { return (int64_t)align_up((uint64_t)nx * ny, 64); }
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0; }
+
+lb_status validate(const lb_config* c) {
+    if (!c) return LB_E_INVALID_ARG;
+    if (c->nx < 8 || c->ny < 8 || c->nx > (1 << 20) || c->ny > (1 << 20)) return LB_E_INVALID_ARG;
+    if ((int64_t)c->nx * c->ny > ((int64_t)1 << 31)) return LB_E_INVALID_ARG;
+    if (c->bc_x != LB_PERIODIC) return c->bc_x == LB_HALFWAY_BB ? LB_E_UNSUPPORTED : LB_E_INVALID_ARG;
+    if (c->bc_y != LB_PERIODIC && c->bc_y != LB_HALFWAY_BB) return LB_E_INVALID_ARG;
+    if (c->force_ref < LB_FREF_MEAN || c->force_ref > LB_FREF_NONE) return LB_E_INVALID_ARG;
+    if (c->st_form != LB_ST_GEOMETRIC && c->st_form != LB_ST_CHEMPOT) return LB_E_INVALID_ARG;
+    if (store_bytes(c->precision) == 0) return LB_E_INVALID_ARG;
+    if (!finite_pos(c->rho_A) || !finite_pos(c->rho_B) || !finite_pos(c->nu_A) ||
+        !finite_pos(c->nu_B) || !finite_pos(c->W) || !finite_pos(c->M))
+        return LB_E_INVALID_ARG;
+    const double vals[] = {c->sigma0, c->sigma_T, c->T0, c->dTdy, c->y_ref, c->gx, c->gy,
+                           c->shift_f, c->shift_g, c->u_max};
+    for (double v : vals)
+        if (!std::isfinite(v)) return LB_E_INVALID_ARG;
+    // derived rates in (0, 2): omega_nu = 1/(1/2 + 3 nu) at both phases, omega_phi
+    const double om[] = {1.0 / (0.5 + 3.0 * c->nu_A), 1.0 / (0.5 + 3.0 * c->nu_B),
+                         1.0 / (0.5 + 3.0 * c->M)};
+    for (double o : om)
+        if (!(o > 0.0 && o < 2.0)) return LB_E_INVALID_ARG;
+    if (c->tile_x != 0 && c->tile_x != 64 && c->tile_x != 128 && c->tile_x != 256)
+        return LB_E_INVALID_ARG;
+    if (c->tile_h < 0 || (c->tile_h > 0 && c->tile_h < kMinH)) return LB_E_INVALID_ARG;
+    if (c->diag_every < 0) return LB_E_INVALID_ARG;
+    return LB_OK;
+}
+
+double rho_ref_of(const lb_config* c) {
+    switch (c->force_ref) {
+    case LB_FREF_LIGHT: return std::min(c->rho_A, c->rho_B);
+    case LB_FREF_HEAVY: return std::max(c->rho_A, c->rho_B);
+    case LB_FREF_NONE: return 0.0;
+    default: return 0.5 * (c->rho_A + c->rho_B);
+    }
+}
+
+void fill_desc(const lb_config* c, LatDesc& D, void* b0, void* b1, int64_t plane, double* fields) {
+    std::memset(&D, 0, sizeof(D));
+    D.nx = c->nx;
+    D.ny = c->ny;
+    D.wall_y = c->bc_y == LB_HALFWAY_BB ? 1 : 0;
+    D.st_form = c->st_form;
+    D.plane = plane;
+    D.buf[0] = b0;
+    D.buf[1] = b1;
+    D.fields = fields;
+    D.rhoB = c->rho_B;
+    D.dRho = c->rho_A - c->rho_B;
+    const double muA = c->rho_A * c->nu_A, muB = c->rho_B * c->nu_B;
+    D.muB = muB;
+    D.dMu = muA - muB;
+    // sigma(y) = s_a + s_b y
+    const double s_a = c->sigma0 + c->sigma_T * (c->T0 - c->dTdy * c->y_ref);
+    const double s_b = c->sigma_T * c->dTdy;
+    D.kt_a = 1.5 * c->W * s_a;
+    D.kt_b = 1.5 * c->W * s_b;
+    D.be_a = 12.0 * s_a / c->W;
+    D.be_b = 12.0 * s_b / c->W;
+    D.ka_a = 1.5 * c->W * s_a;
+    D.ka_b = 1.5 * c->W * s_b;
+    D.four_W = 4.0 / c->W;
+    D.M = c->M;
+    D.omphi = 1.0 / (0.5 + 3.0 * c->M);
+    D.gx = c->gx;
+    D.gy = c->gy;
+    D.rho_ref = rho_ref_of(c);
+    const bool half = c->precision == LB_FP32_F16 || c->precision == LB_FP32_BF16;
+    D.shift_f = half ? c->shift_f : 0.0;
+    D.shift_g = half ? c->shift_g : 0.0;
+}
+
+// Work items of one lattice: strips of tx columns, runs of th rows; strip-major
+// so that consecutive items are vertically adjacent (they share halo rows).
+void build_items(int inst, int nx, int ny, int tx, int th, std::vector<WorkItem>& out) {
+    for (int x0 = 0; x0 < nx; x0 += tx)
+        for (int y0 = 0; y0 < ny; y0 += th) out.push_back({inst, x0, y0, std::min(ny, y0 + th)});
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs (block b -> XCD b % 8).
+// Reorder each group of `grid` consecutive items so that the items one XCD
+// receives are consecutive in the original order (they share halo rows in the
+// XCD's L2).
+void xcd_permute(std::vector<WorkItem>& items, int grid) {
+    if (grid < 16 || grid % 8) return;
+    std::vector<WorkItem> out(items.size());
+    const size_t n = items.size();
+    for (size_t g0 = 0; g0 < n; g0 += grid) {
+        const size_t len = std::min<size_t>(grid, n - g0);
+        if (len < (size_t)grid) {
+            for (size_t i = 0; i < len; ++i) out[g0 + i] = items[g0 + i];
+            continue;
+        }
+        const size_t per = grid / 8;
+        for (size_t b = 0; b < len; ++b) out[g0 + b] = items[g0 + (b % 8) * per + b / 8];
+    }
+    items.swap(out);
+}
+
+int max_items_for(int nx, int ny) { return ((nx + 63) / 64) * ((ny + kMinH - 1) / kMinH); }
+
+int cu_count() {
+    static int n = -1;
+    if (n < 0) {
+        int dev = 0;
+        hipDeviceProp_t p;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess)
+            n = p.multiProcessorCount;
+        else
+            n = 256;
+    }
+    return n;
+}
+
+void default_tile(int nx, int ny, int& tx, int& th) {
+    tx = nx >= 2048 ? 256 : (nx >= 512 ? 128 : 64);
+    const int strips = (nx + tx - 1) / tx;
+    const int target = 4 * cu_count();  // items wanted
+    th = 256;
+    while (th > 16 && (int64_t)strips * ((ny + th - 1) / th) < target) th /= 2;
+    if (th > ny) th = ny < kMinH ? kMinH : ny;
+}
+
+struct TuneKey {
+    int prec, nx, ny, wall, st, batch;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(prec, nx, ny, wall, st, batch) < std::tie(o.prec, o.nx, o.ny, o.wall, o.st, o.batch);
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, std::pair<int, int>> g_tune;
+
+#define HIPC(x)                                 \
+    do {                                        \
+        hipError_t e_ = (x);                    \
+        if (e_ != hipSuccess) return LB_E_HIP;  \
+    } while (0)
+
+}  // namespace
+
+// ======================================================================== single
+
+struct lb_handle {
+    lb_config cfg;
+    hipStream_t s = nullptr;
+    char* ws = nullptr;
+    uint64_t ws_bytes = 0;
+    LatDesc hdesc;
+    LatDesc* d_desc = nullptr;     // fields -> d_fields
+    LatDesc* d_desc_cp = nullptr;  // fields -> caller buffer (coupling output)
+    WorkItem* d_items = nullptr;
+    int n_items = 0, max_items = 0;
+    WorkItem* d_items64 = nullptr;
+    int n_items64 = 0;
+    double* d_part = nullptr;
+    double* d_dout = nullptr;
+    double* d_fields = nullptr;
+    void* buf[2] = {nullptr, nullptr};
+    int64_t plane = 0;
+    int sbytes = 0;
+    int parity = 0;
+    int64_t step = 0;
+    int tx = 0, th = 0;
+    bool tuned = false;
+    // diagnostics
+    double* h_diag = nullptr;  // pinned, 16 doubles
+    hipEvent_t ev_diag = nullptr;
+    bool diag_pending = false;
+    bool unstable = false;
+    // timing
+    bool timing = false;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    int64_t last_steps = 0;
+    // graphs: one per starting parity
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    int glen = 0;
+};
+
+namespace {
+
+struct Layout {
+    uint64_t desc, desc_cp, items, items64, part, dout, fields, bufA, bufB, total;
+};
+
+Layout layout_of(const lb_config* c) {
+    Layout L;
+    const int64_t N = (int64_t)c->nx * c->ny;
+    const int64_t P = plane_elems(c->nx, c->ny);
+    const int sb = store_bytes(c->precision);
+    uint64_t o = 0;
+    L.desc = o; o += align_up(sizeof(LatDesc));
+    L.desc_cp = o; o += align_up(sizeof(LatDesc));
+    L.items = o; o += align_up((uint64_t)max_items_for(c->nx, c->ny) * sizeof(WorkItem));
+    L.items64 = o; o += align_up((uint64_t)((c->nx + 63) / 64) * ((c->ny + 63) / 64) * sizeof(WorkItem));
+    L.part = o; o += align_up((uint64_t)4 * c->ny * sizeof(double));
+    L.dout = o; o += align_up(16 * sizeof(double));
+    L.fields = o; o += align_up((uint64_t)4 * N * sizeof(double));
+    L.bufA = o; o += align_up((uint64_t)18 * P * sb);
+    L.bufB = o; o += align_up((uint64_t)18 * P * sb);
+    L.total = o;
+    return L;
+}
+
+lb_status set_items(lb_handle* h, int tx, int th) {
+    std::vector<WorkItem> items;
+    build_items(0, h->cfg.nx, h->cfg.ny, tx, th, items);
+    if ((int)items.size() > h->max_items) return LB_E_INVALID_ARG;
+    xcd_permute(items, (int)items.size());
+    HIPC(hipMemcpyAsync(h->d_items, items.data(), items.size() * sizeof(WorkItem),
+                        hipMemcpyHostToDevice, h->s));
+    HIPC(hipStreamSynchronize(h->s));
+    h->n_items = (int)items.size();
+    h->tx = tx;
+    h->th = th;
+    for (int p = 0; p < 2; ++p)
+        if (h->gexec[p]) { (void)hipGraphExecDestroy(h->gexec[p]); h->gexec[p] = nullptr; }
+    return LB_OK;
+}
+
+lb_status launch_steps_eager(lb_handle* h, int64_t n) {
+    for (int64_t i = 0; i < n; ++i) {
+        HIPC(launch_step(h->cfg.precision, h->tx, h->d_desc, h->d_items, h->n_items, h->n_items,
+                         h->parity, h->s));
+        h->parity ^= 1;
+        h->step += 1;
+    }
+    return LB_OK;
+}
+
+// Replays a captured graph of glen steps (glen even, so the parity is restored).
+lb_status graph_for(lb_handle* h, int parity, hipGraphExec_t* out) {
+    if (!h->gexec[parity]) {
+        hipStream_t cs;
+        HIPC(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        int p = parity;
+        for (int i = 0; i < h->glen && e == hipSuccess; ++i) {
+            e = launch_step(h->cfg.precision, h->tx, h->d_desc, h->d_items, h->n_items, h->n_items,
+                            p, cs);
+            p ^= 1;
+        }
+        hipError_t e2 = hipStreamEndCapture(cs, &g);
+        (void)hipStreamDestroy(cs);
+        if (e != hipSuccess || e2 != hipSuccess || !g) {
+            if (g) (void)hipGraphDestroy(g);
+            return LB_E_HIP;
+        }
+        hipGraphExec_t ex = nullptr;
+        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return LB_E_HIP;
+        h->gexec[parity] = ex;
+    }
+    *out = h->gexec[parity];
+    return LB_OK;
+}
+
+lb_status enqueue_diag(lb_handle* h) {
+    HIPC(launch_extract(h->cfg.precision, MODE_FIELDS, h->d_desc, h->d_items64, h->n_items64,
+                        h->parity, h->s));
+    const double umax = h->cfg.u_max > 0 ? h->cfg.u_max : 0.3;
+    HIPC(launch_diag(h->d_desc, h->d_fields, h->d_part, h->d_dout, h->cfg.ny, (double)h->step,
+                     umax, h->s));
+    return LB_OK;
+}
+
+// Times `reps` launches of one candidate without advancing the state (every
+// launch reads the current buffer and overwrites the other one).
+double time_candidate(int prec, int tx, const LatDesc* d, const WorkItem* items, int n, int grid,
+                      int parity, hipStream_t s, int reps) {
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return 1e30;
+    if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return 1e30; }
+    double ms_out = 1e30;
+    bool ok = launch_step(prec, tx, d, items, n, grid, parity, s) == hipSuccess;
+    ok = ok && hipEventRecord(a, s) == hipSuccess;
+    for (int i = 0; i < reps && ok; ++i) ok = launch_step(prec, tx, d, items, n, grid, parity, s) == hipSuccess;
+    ok = ok && hipEventRecord(b, s) == hipSuccess && hipEventSynchronize(b) == hipSuccess;
+    float ms = 0;
+    if (ok && hipEventElapsedTime(&ms, a, b) == hipSuccess) ms_out = ms / reps;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return ms_out;
+}
+
+lb_status autotune_single(lb_handle* h) {
+    const TuneKey key{h->cfg.precision, h->cfg.nx, h->cfg.ny, h->hdesc.wall_y, h->cfg.st_form, 0};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) return set_items(h, it->second.first, it->second.second);
+    }
+    int best_tx = h->tx, best_th = h->th;
+    double best = 1e30;
+    const int64_t N = (int64_t)h->cfg.nx * h->cfg.ny;
+    const int reps = N >= (1 << 22) ? 3 : 10;
+    for (int tx : {64, 128, 256}) {
+        if (tx > 64 && h->cfg.nx < tx) continue;
+        for (int th : {16, 32, 64, 128, 256}) {
+            if (th > h->cfg.ny && th != 16) continue;
+            std::vector<WorkItem> items;
+            build_items(0, h->cfg.nx, h->cfg.ny, tx, th, items);
+            if ((int)items.size() > h->max_items) continue;
+            xcd_permute(items, (int)items.size());
+            HIPC(hipMemcpyAsync(h->d_items, items.data(), items.size() * sizeof(WorkItem),
+                                hipMemcpyHostToDevice, h->s));
+            const double ms = time_candidate(h->cfg.precision, tx, h->d_desc, h->d_items,
+                                             (int)items.size(), (int)items.size(), h->parity, h->s, reps);
+            if (ms < best) { best = ms; best_tx = tx; best_th = th; }
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[key] = {best_tx, best_th};
+    }
+    return set_items(h, best_tx, best_th);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lb_status_string(lb_status s) {
+    switch (s) {
+    case LB_OK: return "ok";
+    case LB_E_INVALID_ARG: return "invalid argument";
+    case LB_E_WORKSPACE: return "workspace too small, misaligned or exhausted";
+    case LB_E_HIP: return "HIP runtime error";
+    case LB_E_UNSTABLE: return "unstable: NaN/Inf or max|u| above the limit";
+    case LB_E_UNSUPPORTED: return "unsupported option";
+    case LB_E_STATE: return "state buffer of the wrong size";
+    }
+    return "unknown status";
+}
+
+lb_status lb_workspace_bytes(const lb_config* cfg, uint64_t* bytes) {
+    if (!bytes) return LB_E_INVALID_ARG;
+    lb_status st = validate(cfg);
+    if (st != LB_OK) return st;
+    *bytes = layout_of(cfg).total;
+    return LB_OK;
+}
+
+lb_status lb_create(const lb_config* cfg, void* dev_ws, uint64_t ws_bytes, void* stream,
+                    lb_handle** out) {
+    if (!out || !dev_ws) return LB_E_INVALID_ARG;
+    *out = nullptr;
+    lb_status st = validate(cfg);
+    if (st != LB_OK) return st;
+    const Layout L = layout_of(cfg);
+    if (ws_bytes < L.total || ((uintptr_t)dev_ws % kAlign)) return LB_E_WORKSPACE;
+    lb_handle* h = new lb_handle();
+    h->cfg = *cfg;
+    h->s = (hipStream_t)stream;
+    h->ws = (char*)dev_ws;
+    h->ws_bytes = ws_bytes;
+    h->d_desc = (LatDesc*)(h->ws + L.desc);
+    h->d_desc_cp = (LatDesc*)(h->ws + L.desc_cp);
+    h->d_items = (WorkItem*)(h->ws + L.items);
+    h->max_items = max_items_for(cfg->nx, cfg->ny);
+    h->d_items64 = (WorkItem*)(h->ws + L.items64);
+    h->d_part = (double*)(h->ws + L.part);
+    h->d_dout = (double*)(h->ws + L.dout);
+    h->d_fields = (double*)(h->ws + L.fields);
+    h->buf[0] = h->ws + L.bufA;
+    h->buf[1] = h->ws + L.bufB;
+    h->plane = plane_elems(cfg->nx, cfg->ny);
+    h->sbytes = store_bytes(cfg->precision);
+    h->glen = 32;
+    fill_desc(cfg, h->hdesc, h->buf[0], h->buf[1], h->plane, h->d_fields);
+    auto fail = [&](lb_status s) { lb_destroy(h); return s; };
+    if (hipHostMalloc((void**)&h->h_diag, 16 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+        return fail(LB_E_HIP);
+    std::memset(h->h_diag, 0, 16 * sizeof(double));
+    if (hipEventCreateWithFlags(&h->ev_diag, hipEventDisableTiming) != hipSuccess) return fail(LB_E_HIP);
+    if (hipEventCreate(&h->t0) != hipSuccess || hipEventCreate(&h->t1) != hipSuccess)
+        return fail(LB_E_HIP);
+    if (hipMemcpyAsync(h->d_desc, &h->hdesc, sizeof(LatDesc), hipMemcpyHostToDevice, h->s) != hipSuccess)
+        return fail(LB_E_HIP);
+    std::vector<WorkItem> it64;
+    build_items(0, cfg->nx, cfg->ny, 64, 64, it64);
+    h->n_items64 = (int)it64.size();
+    if (hipMemcpyAsync(h->d_items64, it64.data(), it64.size() * sizeof(WorkItem),
+                       hipMemcpyHostToDevice, h->s) != hipSuccess)
+        return fail(LB_E_HIP);
+    int tx, th;
+    default_tile(cfg->nx, cfg->ny, tx, th);
+    if (cfg->tile_x) tx = cfg->tile_x;
+    if (cfg->tile_h) th = cfg->tile_h;
+    h->tuned = (cfg->tile_x != 0 && cfg->tile_h != 0) || (int64_t)cfg->nx * cfg->ny < (1 << 16);
+    st = set_items(h, tx, th);
+    if (st != LB_OK) return fail(st);
+    *out = h;
+    return LB_OK;
+}
+
+lb_status lb_init_fields(lb_handle* h, const double* phi0) {
+    if (!h || !phi0) return LB_E_INVALID_ARG;
+    const int64_t N = (int64_t)h->cfg.nx * h->cfg.ny;
+    HIPC(hipMemcpyAsync(h->d_fields, phi0, N * sizeof(double), hipMemcpyHostToDevice, h->s));
+    HIPC(launch_state_op(h->cfg.precision, 0, h->d_desc, h->d_fields, 0, 0, h->parity, N, h->s));
+    HIPC(hipStreamSynchronize(h->s));
+    h->step = 0;
+    h->unstable = false;
+    h->diag_pending = false;
+    return LB_OK;
+}
+
+lb_status lb_step(lb_handle* h, int64_t n) {
+    if (!h || n < 0) return LB_E_INVALID_ARG;
+    if (h->diag_pending && hipEventQuery(h->ev_diag) == hipSuccess) {
+        h->diag_pending = false;
+        if (h->h_diag[10] != 0.0) h->unstable = true;
+    }
+    if (h->unstable) return LB_E_UNSTABLE;
+    if (!h->tuned) {
+        lb_status st = autotune_single(h);
+        if (st != LB_OK) return st;
+        h->tuned = true;
+    }
+    if (h->timing) HIPC(hipEventRecord(h->t0, h->s));
+    const int de = h->cfg.diag_every;
+    int64_t left = n;
+    while (left > 0) {
+        int64_t chunk = left;
+        if (de > 0) chunk = std::min<int64_t>(left, de - (h->step % de));
+        // replay whole graphs where possible, the rest eagerly
+        if (chunk >= h->glen) {
+            hipGraphExec_t ex;
+            const int64_t reps = chunk / h->glen;
+            for (int64_t r = 0; r < reps; ++r) {
+                lb_status st = graph_for(h, h->parity, &ex);
+                if (st != LB_OK) return st;
+                HIPC(hipGraphLaunch(ex, h->s));
+                h->step += h->glen;
+            }
+            const lb_status st = launch_steps_eager(h, chunk - reps * h->glen);
+            if (st != LB_OK) return st;
+        } else {
+            const lb_status st = launch_steps_eager(h, chunk);
+            if (st != LB_OK) return st;
+        }
+        left -= chunk;
+        if (de > 0 && h->step % de == 0) {
+            lb_status st = enqueue_diag(h);
+            if (st != LB_OK) return st;
+            HIPC(hipMemcpyAsync(h->h_diag, h->d_dout, 16 * sizeof(double), hipMemcpyDeviceToHost, h->s));
+            HIPC(hipEventRecord(h->ev_diag, h->s));
+            h->diag_pending = true;
+        }
+    }
+    if (h->timing) {
+        HIPC(hipEventRecord(h->t1, h->s));
+        h->last_steps = n;
+    }
+    return LB_OK;
+}
+
+lb_status lb_get_fields(lb_handle* h, double* phi, double* p, double* ux, double* uy) {
+    if (!h) return LB_E_INVALID_ARG;
+    const int64_t N = (int64_t)h->cfg.nx * h->cfg.ny;
+    HIPC(launch_extract(h->cfg.precision, MODE_FIELDS, h->d_desc, h->d_items64, h->n_items64,
+                        h->parity, h->s));
+    double* outs[4] = {phi, p, ux, uy};
+    for (int i = 0; i < 4; ++i)
+        if (outs[i])
+            HIPC(hipMemcpyAsync(outs[i], h->d_fields + i * N, N * sizeof(double),
+                                hipMemcpyDeviceToHost, h->s));
+    HIPC(hipStreamSynchronize(h->s));
+    return LB_OK;
+}
+
+lb_status lb_get_coupling(lb_handle* h, double* dev_out) {
+    if (!h || !dev_out) return LB_E_INVALID_ARG;
+    LatDesc d = h->hdesc;
+    d.fields = dev_out;
+    HIPC(hipMemcpyAsync(h->d_desc_cp, &d, sizeof(LatDesc), hipMemcpyHostToDevice, h->s));
+    HIPC(launch_extract(h->cfg.precision, MODE_COUPLING, h->d_desc_cp, h->d_items64, h->n_items64,
+                        h->parity, h->s));
+    HIPC(hipStreamSynchronize(h->s));
+    return LB_OK;
+}
+
+lb_status lb_diagnostics(lb_handle* h, lb_diag* out) {
+    if (!h || !out) return LB_E_INVALID_ARG;
+    lb_status st = enqueue_diag(h);
+    if (st != LB_OK) return st;
+    double tmp[16];
+    HIPC(hipMemcpyAsync(tmp, h->d_dout, 16 * sizeof(double), hipMemcpyDeviceToHost, h->s));
+    HIPC(hipStreamSynchronize(h->s));
+    static_assert(sizeof(lb_diag) == 10 * sizeof(double), "lb_diag layout");
+    std::memcpy(out, tmp, sizeof(lb_diag));
+    return LB_OK;
+}
+
+lb_status lb_get_dist(lb_handle* h, double* f, double* g) {
+    if (!h) return LB_E_INVALID_ARG;
+    const int64_t N = (int64_t)h->cfg.nx * h->cfg.ny;
+    double* outs[2] = {f, g};
+    for (int which = 0; which < 2; ++which) {
+        if (!outs[which]) continue;
+        for (int a = 0; a < 9; ++a) {
+            HIPC(launch_state_op(h->cfg.precision, 2, h->d_desc, h->d_fields, a, which, h->parity, N, h->s));
+            HIPC(hipMemcpyAsync(outs[which] + a * N, h->d_fields, N * sizeof(double),
+                                hipMemcpyDeviceToHost, h->s));
+            HIPC(hipStreamSynchronize(h->s));
+        }
+    }
+    return LB_OK;
+}
+
+lb_status lb_set_dist(lb_handle* h, const double* f, const double* g, int64_t step) {
+    if (!h || !f || !g || step < 0) return LB_E_INVALID_ARG;
+    const int64_t N = (int64_t)h->cfg.nx * h->cfg.ny;
+    const double* ins[2] = {f, g};
+    for (int which = 0; which < 2; ++which)
+        for (int b = 0; b < 9; ++b) {
+            HIPC(hipMemcpyAsync(h->d_fields, ins[which] + b * N, N * sizeof(double),
+                                hipMemcpyHostToDevice, h->s));
+            HIPC(launch_state_op(h->cfg.precision, 1, h->d_desc, h->d_fields, b, which, h->parity, N, h->s));
+            HIPC(hipStreamSynchronize(h->s));
+        }
+    h->step = step;
+    h->unstable = false;
+    h->diag_pending = false;
+    return LB_OK;
+}
+
+lb_status lb_state_bytes(lb_handle* h, uint64_t* bytes) {
+    if (!h || !bytes) return LB_E_INVALID_ARG;
+    *bytes = 16 + (uint64_t)18 * h->plane * h->sbytes;
+    return LB_OK;
+}
+
+lb_status lb_save_state(lb_handle* h, void* host, uint64_t bytes) {
+    if (!h || !host) return LB_E_INVALID_ARG;
+    uint64_t need;
+    lb_state_bytes(h, &need);
+    if (bytes != need) return LB_E_STATE;
+    int64_t hdr[2] = {h->step, (int64_t)h->cfg.precision};
+    std::memcpy(host, hdr, 16);
+    HIPC(hipMemcpyAsync((char*)host + 16, h->buf[h->parity], need - 16, hipMemcpyDeviceToHost, h->s));
+    HIPC(hipStreamSynchronize(h->s));
+    return LB_OK;
+}
+
+lb_status lb_load_state(lb_handle* h, const void* host, uint64_t bytes) {
+    if (!h || !host) return LB_E_INVALID_ARG;
+    uint64_t need;
+    lb_state_bytes(h, &need);
+    if (bytes != need) return LB_E_STATE;
+    int64_t hdr[2];
+    std::memcpy(hdr, host, 16);
+    if (hdr[1] != h->cfg.precision || hdr[0] < 0) return LB_E_STATE;
+    HIPC(hipMemcpyAsync(h->buf[h->parity], (const char*)host + 16, need - 16, hipMemcpyHostToDevice, h->s));
+    HIPC(hipStreamSynchronize(h->s));
+    h->step = hdr[0];
+    h->unstable = false;
+    h->diag_pending = false;
+    return LB_OK;
+}
+
+lb_status lb_get_step(lb_handle* h, int64_t* step) {
+    if (!h || !step) return LB_E_INVALID_ARG;
+    *step = h->step;
+    return LB_OK;
+}
+
+void lb_destroy(lb_handle* h) {
+    if (!h) return;
+    if (h->s) (void)hipStreamSynchronize(h->s);
+    for (int p = 0; p < 2; ++p)
+        if (h->gexec[p]) (void)hipGraphExecDestroy(h->gexec[p]);
+    if (h->ev_diag) (void)hipEventDestroy(h->ev_diag);
+    if (h->t0) (void)hipEventDestroy(h->t0);
+    if (h->t1) (void)hipEventDestroy(h->t1);
+    if (h->h_diag) (void)hipHostFree(h->h_diag);
+    delete h;
+}
+
+lb_status lb_timing_enable(lb_handle* h, int32_t on) {
+    if (!h) return LB_E_INVALID_ARG;
+    h->timing = on != 0;
+    h->last_steps = 0;
+    return LB_OK;
+}
+
+lb_status lb_timing_read(lb_handle* h, double* ms_per_step, int64_t* steps) {
+    if (!h || !ms_per_step || !steps) return LB_E_INVALID_ARG;
+    *steps = h->last_steps;
+    *ms_per_step = 0;
+    if (h->last_steps <= 0) return LB_OK;
+    HIPC(hipEventSynchronize(h->t1));
+    float ms = 0;
+    HIPC(hipEventElapsedTime(&ms, h->t0, h->t1));
+    *ms_per_step = ms / (double)h->last_steps;
+    return LB_OK;
+}
+
+lb_status lb_get_tile(lb_handle* h, int32_t* tile_x, int32_t* tile_h) {
+    if (!h || !tile_x || !tile_h) return LB_E_INVALID_ARG;
+    *tile_x = h->tx;
+    *tile_h = h->th;
+    return LB_OK;
+}
+
+lb_status lb_struct_sizes(uint64_t* config_bytes, uint64_t* diag_bytes) {
+    if (!config_bytes || !diag_bytes) return LB_E_INVALID_ARG;
+    *config_bytes = sizeof(lb_config);
+    *diag_bytes = sizeof(lb_diag);
+    return LB_OK;
+}
+
+lb_status lb_copy_kernel(void* dst, const void* src, uint64_t n, void* stream) {
+    if (!dst || !src || ((uintptr_t)dst % 16) || ((uintptr_t)src % 16)) return LB_E_INVALID_ARG;
+    HIPC(launch_copy(dst, src, n, (hipStream_t)stream));
+    return LB_OK;
+}
+
+}  // extern "C"
+
+// ========================================================================= batch
+
+struct BatchSlot {
+    bool used = false;
+    lb_config cfg;
+    int64_t add_step = 0;  // global step at which the slot was filled
+    uint64_t off = 0, bytes = 0;
+    int64_t plane = 0;
+};
+
+struct lb_batch {
+    int prec = 0, nslots = 0, sbytes = 0;
+    int64_t capacity = 0;
+    hipStream_t s = nullptr;
+    char* ws = nullptr;
+    uint64_t ws_bytes = 0;
+    LatDesc* d_descs = nullptr;
+    std::vector<LatDesc> hdescs;
+    WorkItem* d_items = nullptr;
+    int max_items = 0, n_items = 0;
+    WorkItem* d_items64 = nullptr;
+    int max_items64 = 0;
+    double* d_fields = nullptr;
+    double* d_part = nullptr;
+    int max_ny = 0;
+    double* d_dout = nullptr;
+    char* pool = nullptr;
+    uint64_t pool_bytes = 0;
+    std::vector<std::pair<uint64_t, uint64_t>> free_list;  // (offset, bytes), sorted
+    std::vector<BatchSlot> slot;
+    int64_t gstep = 0;
+    int parity = 0;
+    int tx = 64, th = 64;
+    bool fixed_tile = false;
+    int grid = 0;
+    bool dirty = true;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    int glen = 16;
+    bool timing = false;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    int64_t last_steps = 0;
+};
+
+namespace {
+
+struct BatchLayout {
+    uint64_t descs, items, items64, part, dout, fields, pool, total;
+    int max_items, max_items64, max_ny;
+};
+
+BatchLayout batch_layout(int32_t slots, int64_t cap, int prec) {
+    BatchLayout L;
+    const int sb = store_bytes(prec);
+    L.max_items = (int)std::min<int64_t>((int64_t)1 << 30, cap / 64 + 4 * (int64_t)slots);
+    L.max_items64 = (int)std::min<int64_t>((int64_t)1 << 30, cap / 256 + 4 * (int64_t)slots);
+    L.max_ny = (int)std::min<int64_t>(cap / 8, 1 << 20);
+    uint64_t o = 0;
+    L.descs = o; o += align_up((uint64_t)slots * sizeof(LatDesc));
+    L.items = o; o += align_up((uint64_t)L.max_items * sizeof(WorkItem));
+    L.items64 = o; o += align_up((uint64_t)L.max_items64 * sizeof(WorkItem));
+    L.part = o; o += align_up((uint64_t)4 * L.max_ny * sizeof(double));
+    L.dout = o; o += align_up(16 * sizeof(double));
+    L.fields = o; o += align_up((uint64_t)4 * cap * sizeof(double));
+    L.pool = o; o += align_up((uint64_t)2 * 18 * sb * (uint64_t)(cap + 64 * (int64_t)slots) + kAlign * 2 * slots);
+    L.total = o;
+    return L;
+}
+
+bool pool_alloc(lb_batch* b, uint64_t bytes, uint64_t* off) {
+    bytes = align_up(bytes);
+    for (size_t i = 0; i < b->free_list.size(); ++i) {
+        auto& fr = b->free_list[i];
+        if (fr.second >= bytes) {
+            *off = fr.first;
+            fr.first += bytes;
+            fr.second -= bytes;
+            if (fr.second == 0) b->free_list.erase(b->free_list.begin() + i);
+            return true;
+        }
+    }
+    return false;
+}
+
+void pool_free(lb_batch* b, uint64_t off, uint64_t bytes) {
+    bytes = align_up(bytes);
+    auto& fl = b->free_list;
+    auto it = std::lower_bound(fl.begin(), fl.end(), std::make_pair(off, (uint64_t)0));
+    it = fl.insert(it, {off, bytes});
+    // coalesce with neighbours
+    size_t i = it - fl.begin();
+    if (i + 1 < fl.size() && fl[i].first + fl[i].second == fl[i + 1].first) {
+        fl[i].second += fl[i + 1].second;
+        fl.erase(fl.begin() + i + 1);
+    }
+    if (i > 0 && fl[i - 1].first + fl[i - 1].second == fl[i].first) {
+        fl[i - 1].second += fl[i].second;
+        fl.erase(fl.begin() + i);
+    }
+}
+
+void batch_drop_graphs(lb_batch* b) {
+    for (int p = 0; p < 2; ++p)
+        if (b->gexec[p]) { (void)hipGraphExecDestroy(b->gexec[p]); b->gexec[p] = nullptr; }
+}
+
+int persistent_grid(int prec, int tx) {
+    // enough resident workgroups to fill every CU twice over
+    (void)prec;
+    const int per_cu = tx == 64 ? 8 : (tx == 128 ? 4 : 2);
+    return cu_count() * per_cu;
+}
+
+lb_status batch_rebuild(lb_batch* b, int tx, int th, int grid_mode) {
+    std::vector<WorkItem> items;
+    for (int i = 0; i < b->nslots; ++i)
+        if (b->slot[i].used) build_items(i, b->slot[i].cfg.nx, b->slot[i].cfg.ny, tx, th, items);
+    if ((int)items.size() > b->max_items) return LB_E_WORKSPACE;
+    int grid = (int)items.size();
+    if (grid_mode == 1) grid = std::min(grid, persistent_grid(b->prec, tx));
+    xcd_permute(items, grid);
+    if (!items.empty())
+        HIPC(hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(WorkItem),
+                            hipMemcpyHostToDevice, b->s));
+    HIPC(hipStreamSynchronize(b->s));
+    b->n_items = (int)items.size();
+    b->grid = grid;
+    b->tx = tx;
+    b->th = th;
+    batch_drop_graphs(b);
+    return LB_OK;
+}
+
+lb_status batch_autotune(lb_batch* b) {
+    int best_tx = b->tx, best_th = b->th, best_mode = 0;
+    double best = 1e30;
+    for (int tx : {64, 128}) {
+        for (int th : {16, 32, 64, 128}) {
+            for (int mode : {0, 1}) {
+                lb_status st = batch_rebuild(b, tx, th, mode);
+                if (st == LB_E_WORKSPACE) continue;
+                if (st != LB_OK) return st;
+                if (b->n_items == 0) return LB_OK;
+                const double ms = time_candidate(b->prec, tx, b->d_descs, b->d_items, b->n_items,
+                                                 b->grid, b->parity, b->s, 3);
+                if (ms < best) { best = ms; best_tx = tx; best_th = th; best_mode = mode; }
+            }
+        }
+    }
+    return batch_rebuild(b, best_tx, best_th, best_mode);
+}
+
+lb_status batch_graph(lb_batch* b, int parity, hipGraphExec_t* out) {
+    if (!b->gexec[parity]) {
+        hipStream_t cs;
+        HIPC(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        int p = parity;
+        for (int i = 0; i < b->glen && e == hipSuccess; ++i) {
+            e = launch_step(b->prec, b->tx, b->d_descs, b->d_items, b->n_items, b->grid, p, cs);
+            p ^= 1;
+        }
+        hipError_t e2 = hipStreamEndCapture(cs, &g);
+        (void)hipStreamDestroy(cs);
+        if (e != hipSuccess || e2 != hipSuccess || !g) {
+            if (g) (void)hipGraphDestroy(g);
+            return LB_E_HIP;
+        }
+        hipGraphExec_t ex = nullptr;
+        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return LB_E_HIP;
+        b->gexec[parity] = ex;
+    }
+    *out = b->gexec[parity];
+    return LB_OK;
+}
+
+lb_status batch_extract(lb_batch* b, int32_t slot) {
+    const lb_config& c = b->slot[slot].cfg;
+    std::vector<WorkItem> it64;
+    build_items(slot, c.nx, c.ny, 64, 64, it64);
+    if ((int)it64.size() > b->max_items64) return LB_E_WORKSPACE;
+    HIPC(hipMemcpyAsync(b->d_items64, it64.data(), it64.size() * sizeof(WorkItem),
+                        hipMemcpyHostToDevice, b->s));
+    HIPC(launch_extract(b->prec, MODE_FIELDS, b->d_descs, b->d_items64, (int)it64.size(), b->parity, b->s));
+    return LB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lb_status lb_batch_workspace_bytes(int32_t slots, int64_t node_capacity, int32_t precision,
+                                   uint64_t* bytes) {
+    if (!bytes || slots <= 0 || node_capacity < 64 || store_bytes(precision) == 0) return LB_E_INVALID_ARG;
+    *bytes = batch_layout(slots, node_capacity, precision).total;
+    return LB_OK;
+}
+
+lb_status lb_batch_create(int32_t slots, int64_t node_capacity, int32_t precision, int32_t tile_x,
+                          int32_t tile_h, void* dev_ws, uint64_t ws_bytes, void* stream,
+                          lb_batch** out) {
+    if (!out || !dev_ws || slots <= 0 || node_capacity < 64 || store_bytes(precision) == 0)
+        return LB_E_INVALID_ARG;
+    if (tile_x != 0 && tile_x != 64 && tile_x != 128 && tile_x != 256) return LB_E_INVALID_ARG;
+    if (tile_h < 0 || (tile_h > 0 && tile_h < kMinH)) return LB_E_INVALID_ARG;
+    *out = nullptr;
+    const BatchLayout L = batch_layout(slots, node_capacity, precision);
+    if (ws_bytes < L.total || ((uintptr_t)dev_ws % kAlign)) return LB_E_WORKSPACE;
+    lb_batch* b = new lb_batch();
+    b->prec = precision;
+    b->nslots = slots;
+    b->sbytes = store_bytes(precision);
+    b->capacity = node_capacity;
+    b->s = (hipStream_t)stream;
+    b->ws = (char*)dev_ws;
+    b->ws_bytes = ws_bytes;
+    b->d_descs = (LatDesc*)(b->ws + L.descs);
+    b->hdescs.resize(slots);
+    std::memset(b->hdescs.data(), 0, sizeof(LatDesc) * slots);
+    b->d_items = (WorkItem*)(b->ws + L.items);
+    b->max_items = L.max_items;
+    b->d_items64 = (WorkItem*)(b->ws + L.items64);
+    b->max_items64 = L.max_items64;
+    b->d_part = (double*)(b->ws + L.part);
+    b->max_ny = L.max_ny;
+    b->d_dout = (double*)(b->ws + L.dout);
+    b->d_fields = (double*)(b->ws + L.fields);
+    b->pool = b->ws + L.pool;
+    b->pool_bytes = L.total - L.pool;
+    b->free_list.push_back({0, b->pool_bytes});
+    b->slot.resize(slots);
+    b->fixed_tile = tile_x != 0 && tile_h != 0;
+    b->tx = tile_x ? tile_x : 64;
+    b->th = tile_h ? tile_h : 64;
+    if (hipEventCreate(&b->t0) != hipSuccess || hipEventCreate(&b->t1) != hipSuccess) {
+        lb_batch_destroy(b);
+        return LB_E_HIP;
+    }
+    *out = b;
+    return LB_OK;
+}
+
+lb_status lb_batch_add(lb_batch* b, const lb_config* cfg, const double* phi0, int32_t* slot) {
+    if (!b || !cfg || !phi0 || !slot) return LB_E_INVALID_ARG;
+    lb_status st = validate(cfg);
+    if (st != LB_OK) return st;
+    if (cfg->precision != b->prec) return LB_E_INVALID_ARG;
+    if (cfg->ny > b->max_ny || (int64_t)cfg->nx * cfg->ny > b->capacity) return LB_E_WORKSPACE;
+    int free_slot = -1;
+    for (int i = 0; i < b->nslots; ++i)
+        if (!b->slot[i].used) { free_slot = i; break; }
+    if (free_slot < 0) return LB_E_WORKSPACE;
+    const int64_t P = plane_elems(cfg->nx, cfg->ny);
+    const uint64_t one = align_up((uint64_t)18 * P * b->sbytes);
+    uint64_t off;
+    if (!pool_alloc(b, 2 * one, &off)) return LB_E_WORKSPACE;
+    BatchSlot& S = b->slot[free_slot];
+    S.used = true;
+    S.cfg = *cfg;
+    S.add_step = b->gstep;
+    S.off = off;
+    S.bytes = 2 * one;
+    S.plane = P;
+    LatDesc& D = b->hdescs[free_slot];
+    fill_desc(cfg, D, b->pool + off, b->pool + off + one, P, b->d_fields);
+    auto undo = [&](lb_status s) {
+        S.used = false;
+        pool_free(b, off, 2 * one);
+        return s;
+    };
+    if (hipMemcpyAsync(b->d_descs + free_slot, &D, sizeof(LatDesc), hipMemcpyHostToDevice, b->s) != hipSuccess)
+        return undo(LB_E_HIP);
+    const int64_t N = (int64_t)cfg->nx * cfg->ny;
+    if (hipMemcpyAsync(b->d_fields, phi0, N * sizeof(double), hipMemcpyHostToDevice, b->s) != hipSuccess)
+        return undo(LB_E_HIP);
+    // the lattice starts in the buffer the batch's current parity reads
+    if (launch_state_op(b->prec, 0, b->d_descs + free_slot, b->d_fields, 0, 0, b->parity, N, b->s) != hipSuccess)
+        return undo(LB_E_HIP);
+    if (hipStreamSynchronize(b->s) != hipSuccess) return undo(LB_E_HIP);
+    b->dirty = true;
+    *slot = free_slot;
+    return LB_OK;
+}
+
+lb_status lb_batch_remove(lb_batch* b, int32_t slot) {
+    if (!b || slot < 0 || slot >= b->nslots || !b->slot[slot].used) return LB_E_INVALID_ARG;
+    HIPC(hipStreamSynchronize(b->s));
+    pool_free(b, b->slot[slot].off, b->slot[slot].bytes);
+    b->slot[slot].used = false;
+    b->dirty = true;
+    return LB_OK;
+}
+
+lb_status lb_batch_step(lb_batch* b, int64_t n, int32_t use_graph) {
+    if (!b || n < 0) return LB_E_INVALID_ARG;
+    if (b->dirty) {
+        lb_status st = b->fixed_tile ? batch_rebuild(b, b->tx, b->th, 1) : batch_autotune(b);
+        if (st != LB_OK) return st;
+        b->dirty = false;
+    }
+    if (b->timing) HIPC(hipEventRecord(b->t0, b->s));
+    int64_t left = n;
+    if (b->n_items > 0) {
+        if (use_graph && left >= b->glen) {
+            const int64_t reps = left / b->glen;
+            for (int64_t r = 0; r < reps; ++r) {
+                hipGraphExec_t ex;
+                lb_status st = batch_graph(b, b->parity, &ex);
+                if (st != LB_OK) return st;
+                HIPC(hipGraphLaunch(ex, b->s));
+            }
+            left -= reps * b->glen;  // glen is even: parity unchanged
+        }
+        for (int64_t i = 0; i < left; ++i) {
+            HIPC(launch_step(b->prec, b->tx, b->d_descs, b->d_items, b->n_items, b->grid, b->parity, b->s));
+            b->parity ^= 1;
+        }
+    } else if (n & 1) {
+        b->parity ^= 1;
+    }
+    b->gstep += n;
+    if (b->timing) {
+        HIPC(hipEventRecord(b->t1, b->s));
+        b->last_steps = n;
+    }
+    return LB_OK;
+}
+
+lb_status lb_batch_get_fields(lb_batch* b, int32_t slot, double* phi, double* p, double* ux, double* uy) {
+    if (!b || slot < 0 || slot >= b->nslots || !b->slot[slot].used) return LB_E_INVALID_ARG;
+    lb_status st = batch_extract(b, slot);
+    if (st != LB_OK) return st;
+    const int64_t N = (int64_t)b->slot[slot].cfg.nx * b->slot[slot].cfg.ny;
+    double* outs[4] = {phi, p, ux, uy};
+    for (int i = 0; i < 4; ++i)
+        if (outs[i])
+            HIPC(hipMemcpyAsync(outs[i], b->d_fields + i * N, N * sizeof(double), hipMemcpyDeviceToHost, b->s));
+    HIPC(hipStreamSynchronize(b->s));
+    return LB_OK;
+}
+
+lb_status lb_batch_diagnostics(lb_batch* b, int32_t slot, lb_diag* out) {
+    if (!b || !out || slot < 0 || slot >= b->nslots || !b->slot[slot].used) return LB_E_INVALID_ARG;
+    lb_status st = batch_extract(b, slot);
+    if (st != LB_OK) return st;
+    const lb_config& c = b->slot[slot].cfg;
+    const double umax = c.u_max > 0 ? c.u_max : 0.3;
+    HIPC(launch_diag(b->d_descs + slot, b->d_fields, b->d_part, b->d_dout, c.ny,
+                     (double)(b->gstep - b->slot[slot].add_step), umax, b->s));
+    double tmp[16];
+    HIPC(hipMemcpyAsync(tmp, b->d_dout, 16 * sizeof(double), hipMemcpyDeviceToHost, b->s));
+    HIPC(hipStreamSynchronize(b->s));
+    std::memcpy(out, tmp, sizeof(lb_diag));
+    return LB_OK;
+}
+
+lb_status lb_batch_get_step(lb_batch* b, int32_t slot, int64_t* step) {
+    if (!b || !step || slot < 0 || slot >= b->nslots || !b->slot[slot].used) return LB_E_INVALID_ARG;
+    *step = b->gstep - b->slot[slot].add_step;
+    return LB_OK;
+}
+
+lb_status lb_batch_usage(lb_batch* b, int32_t* used_slots, int64_t* used_nodes) {
+    if (!b || !used_slots || !used_nodes) return LB_E_INVALID_ARG;
+    int32_t u = 0;
+    int64_t n = 0;
+    for (auto& s : b->slot)
+        if (s.used) { ++u; n += (int64_t)s.cfg.nx * s.cfg.ny; }
+    *used_slots = u;
+    *used_nodes = n;
+    return LB_OK;
+}
+
+void lb_batch_destroy(lb_batch* b) {
+    if (!b) return;
+    if (b->s) (void)hipStreamSynchronize(b->s);
+    batch_drop_graphs(b);
+    if (b->t0) (void)hipEventDestroy(b->t0);
+    if (b->t1) (void)hipEventDestroy(b->t1);
+    delete b;
+}
+
+lb_status lb_batch_timing_enable(lb_batch* b, int32_t on) {
+    if (!b) return LB_E_INVALID_ARG;
+    b->timing = on != 0;
+    b->last_steps = 0;
+    return LB_OK;
+}
+
+lb_status lb_batch_timing_read(lb_batch* b, double* ms_per_step, int64_t* steps) {
+    if (!b || !ms_per_step || !steps) return LB_E_INVALID_ARG;
+    *steps = b->last_steps;
+    *ms_per_step = 0;
+    if (b->last_steps <= 0) return LB_OK;
+    HIPC(hipEventSynchronize(b->t1));
+    float ms = 0;
+    HIPC(hipEventElapsedTime(&ms, b->t0, b->t1));
+    *ms_per_step = ms / (double)b->last_steps;
+    return LB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,524 @@
+// lb_device.hpp -- device side of the fused stream-collide step for the coupled
+// D2Q9 cascaded central-moment schemes (arXiv:1909.04166, Secs. 2-5), gfx950.
+//
+// Data layout (HBM): one lattice = two buffers (ping-pong) of 18 planes,
+// planes 0..8 hold f_a, planes 9..17 hold gbar_a, each plane [y][x] with x
+// contiguous and a plane stride rounded up to 64 elements.  A buffer holds the
+// POST-COLLISION values of the previous step; the kernel pulls them
+// (f_a(x) = f~_a(x - e_a)), so streaming costs nothing extra.
+//
+// One workgroup owns a strip of TX columns and a run of rows of one lattice
+// (a work item) and marches upward one row per iteration, one node per lane:
+//   A  pull f at the leading row L           -> phi(L)      (LDS ring, halo 2)
+//   B  pull gbar at row L-1                  -> pbar(L-1)   (LDS ring, halo 1)
+//   D  grad phi, |grad phi|^2, n (or mu_phi) at row L-1     (LDS ring, halo 1)
+//   F  collide row L-2: div n (or grad mu), forces, u, p, both cascaded
+//      collisions, store the 18 post-collision values
+// The pulled f and gbar of a lane stay in registers until their row is
+// collided, so each stored value is read from HBM once per step; the halo
+// columns are recomputed by four helper lanes.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cmlb {
+
+// ------------------------------------------------------------------ storage
+
+struct StF64 {
+    using T = double;
+    using R = double;
+    static __device__ __forceinline__ R ld(T v) { return v; }
+    static __device__ __forceinline__ T st(R v) { return v; }
+};
+struct StF32 {
+    using T = float;
+    using R = float;
+    static __device__ __forceinline__ R ld(T v) { return v; }
+    static __device__ __forceinline__ T st(R v) { return v; }
+};
+struct StF16 {
+    using T = _Float16;
+    using R = float;
+    static __device__ __forceinline__ R ld(T v) { return (float)v; }
+    static __device__ __forceinline__ T st(R v) { return (_Float16)v; }  // round to nearest even
+};
+struct StBF16 {
+    using T = uint16_t;
+    using R = float;
+    static __device__ __forceinline__ R ld(T v) { return __uint_as_float(((uint32_t)v) << 16); }
+    static __device__ __forceinline__ T st(R v) {
+        uint32_t u = __float_as_uint(v);
+        if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu))  // NaN stays NaN
+            return (T)((u >> 16) | 0x0040u);
+        u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+        return (T)(u >> 16);
+    }
+};
+
+// ---------------------------------------------------------------- descriptors
+
+// Per-lattice parameters, precomputed on the host.  Lives in device memory.
+struct alignas(16) LatDesc {
+    int32_t nx, ny;
+    int32_t wall_y;     // 0 periodic, 1 halfway bounce-back at y = -1/2, ny - 1/2
+    int32_t st_form;    // 0 geometric (+ Marangoni), 1 chemical potential
+    int64_t plane;      // element stride between planes
+    int64_t pad0;
+    void* buf[2];       // 18 planes each
+    double* fields;     // FP64 output planes (phi, p, ux, uy or the 9 coupling planes)
+    double* pad1;
+    double rhoB, dRho;  // rho(phi) = rhoB + phi dRho
+    double muB, dMu;    // mu(phi)  = muB + phi dMu
+    double kt_a, kt_b;  // kappa~(y) = kt_a + kt_b y = 1.5 W sigma(y)
+    double be_a, be_b;  // beta(y)  = 12 sigma(y) / W   (chemical-potential form)
+    double ka_a, ka_b;  // kappa(y) = 1.5 W sigma(y)
+    double four_W;      // 4 / W
+    double M, omphi;    // mobility, first-order ACE rate 1 / (1/2 + 3 M)
+    double gx, gy, rho_ref;
+    double shift_f, shift_g;
+};
+
+struct WorkItem {
+    int32_t inst;  // index into the descriptor array
+    int32_t x0;    // first column of the strip
+    int32_t y0;    // first row collided
+    int32_t y1;    // one past the last row collided
+};
+
+enum { MODE_STEP = 0, MODE_FIELDS = 1, MODE_COUPLING = 2 };
+
+// D2Q9 weights and velocities in the order 0 rest, 1 +x, 2 +y, 3 -x, 4 -y,
+// 5 (+,+), 6 (-,+), 7 (-,-), 8 (+,-).
+__device__ __forceinline__ double wgt(int a) {
+    return a == 0 ? 4.0 / 9.0 : (a < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+}
+
+__device__ __forceinline__ int map_row(int L, int ny, int wall) {
+    if (wall) return L < 0 ? -1 - L : (L >= ny ? 2 * ny - 1 - L : L);
+    return L < 0 ? L + ny : (L >= ny ? L - ny : L);
+}
+
+// Pull the nine values arriving at (x, r): f_a(x, r) = f~_a(x - e_a); a source
+// beyond a halfway wall is replaced by the opposite direction at the same node.
+template <class ST>
+__device__ __forceinline__ void pull9(const typename ST::T* __restrict__ base, int64_t P, int nx,
+                                      int ny, int wall, int x, int r, typename ST::R sh,
+                                      typename ST::R out[9]) {
+    using R = typename ST::R;
+    const int xm = x == 0 ? nx - 1 : x - 1;
+    const int xp = x == nx - 1 ? 0 : x + 1;
+    const bool bot = wall && r == 0;       // sources of 2, 5, 6 lie below the wall
+    const bool top = wall && r == ny - 1;  // sources of 4, 7, 8 lie above the wall
+    const int rb = r == 0 ? ny - 1 : r - 1;
+    const int rt = r == ny - 1 ? 0 : r + 1;
+    const int64_t o = (int64_t)r * nx, ob = (int64_t)rb * nx, ot = (int64_t)rt * nx;
+    const R w0 = R(4.0 / 9.0) * sh, w1 = R(1.0 / 9.0) * sh, w5 = R(1.0 / 36.0) * sh;
+    out[0] = ST::ld(base[0 * P + o + x]) + w0;
+    out[1] = ST::ld(base[1 * P + o + xm]) + w1;
+    out[3] = ST::ld(base[3 * P + o + xp]) + w1;
+    if (!bot) {
+        out[2] = ST::ld(base[2 * P + ob + x]) + w1;
+        out[5] = ST::ld(base[5 * P + ob + xm]) + w5;
+        out[6] = ST::ld(base[6 * P + ob + xp]) + w5;
+    } else {
+        out[2] = ST::ld(base[4 * P + o + x]) + w1;
+        out[5] = ST::ld(base[7 * P + o + x]) + w5;
+        out[6] = ST::ld(base[8 * P + o + x]) + w5;
+    }
+    if (!top) {
+        out[4] = ST::ld(base[4 * P + ot + x]) + w1;
+        out[7] = ST::ld(base[7 * P + ot + xp]) + w5;
+        out[8] = ST::ld(base[8 * P + ot + xm]) + w5;
+    } else {
+        out[4] = ST::ld(base[2 * P + o + x]) + w1;
+        out[7] = ST::ld(base[5 * P + o + x]) + w5;
+        out[8] = ST::ld(base[6 * P + o + x]) + w5;
+    }
+}
+
+template <class R>
+__device__ __forceinline__ R sum9(const R v[9]) {
+    R s = v[0];
+#pragma unroll
+    for (int a = 1; a < 9; ++a) s += v[a];
+    return s;
+}
+
+// Isotropic D2Q9 gradient (1/c^2) sum_a w_a e_a q(x + e_a) from a 3x3 patch:
+// rows s (y-1), m (y), n (y+1); columns c-1, c, c+1.
+template <class R>
+__device__ __forceinline__ void grad3x3(const R* s, const R* m, const R* n, int c, R& gx, R& gy) {
+    const R k1 = R(1.0 / 3.0), k2 = R(1.0 / 12.0);
+    gx = k1 * (m[c + 1] - m[c - 1]) + k2 * ((n[c + 1] - n[c - 1]) + (s[c + 1] - s[c - 1]));
+    gy = k1 * (n[c] - s[c]) + k2 * ((n[c + 1] + n[c - 1]) - (s[c + 1] + s[c - 1]));
+}
+
+// Isotropic D2Q9 Laplacian (2/c^2) sum_a w_a (q(x + e_a) - q(x)).
+template <class R>
+__device__ __forceinline__ R lap3x3(const R* s, const R* m, const R* n, int c) {
+    const R axis = (m[c + 1] + m[c - 1]) + (n[c] + s[c]);
+    const R diag = (n[c + 1] + n[c - 1]) + (s[c + 1] + s[c - 1]);
+    return R(2.0 / 3.0) * axis + R(1.0 / 6.0) * diag - R(10.0 / 3.0) * m[c];
+}
+
+// ------------------------------------------------------ per-node physics
+
+template <class R>
+struct NodeIn {
+    R phi, pbar;
+    R dphx, dphy, m2, nx, ny;  // grad phi, |grad phi|^2, unit normal (0 where undefined)
+    R divn;                    // div n (geometric form)
+    R dmux, dmuy;              // grad mu_phi (chemical-potential form)
+    R dpx, dpy;                // grad pbar
+    R y;                       // row coordinate
+};
+
+template <class R>
+struct NodeOut {
+    R rho, omv, ux, uy, p, psi, Ftx, Fty, Fpx, Fpy;
+};
+
+// Properties, forces, velocity and pressure of one node (Eqs.
+// sfluidpropertiesinterpolation, surfacetensiongeometricsurfactantsxcomp/ycomp,
+// surfacetensionthermodynamic, netgradientpressureforce, hydrodynamicfields,
+// fluidviscosity).
+template <class R>
+__device__ __forceinline__ NodeOut<R> node_macro(const LatDesc& D, const NodeIn<R>& in,
+                                                 const R g[9]) {
+    NodeOut<R> o;
+    const R rho = R(D.rhoB) + in.phi * R(D.dRho);
+    const R mu = R(D.muB) + in.phi * R(D.dMu);
+    const R den = R(0.5) * rho + R(3) * mu;  // rho (1/omega_nu) with nu = mu / rho
+    const R rr = R(1) / (rho * den);
+    const R inv_rho = den * rr;
+    o.rho = rho;
+    o.omv = rho * rho * rr;
+    R Fsx, Fsy;
+    if (D.st_form == 0) {
+        const R kt = R(D.kt_a) + R(D.kt_b) * in.y;
+        const R dkt = R(D.kt_b);
+        const R a = in.m2 * kt * in.divn;
+        const R b = in.m2 * dkt;
+        Fsx = -a * in.nx - b * in.nx * in.ny;
+        Fsy = -a * in.ny + b * (R(1) - in.ny * in.ny);
+    } else {
+        Fsx = -in.phi * in.dmux;
+        Fsy = -in.phi * in.dmuy;
+    }
+    const R bf = rho - R(D.rho_ref);
+    o.Ftx = Fsx + bf * R(D.gx);
+    o.Fty = Fsy + bf * R(D.gy);
+    const R jx = (g[1] - g[3]) + (g[5] - g[6]) + (g[8] - g[7]);
+    const R jy = (g[2] - g[4]) + (g[5] + g[6]) - (g[7] + g[8]);
+    o.ux = (R(3) * jx + R(0.5) * o.Ftx) * inv_rho;
+    o.uy = (R(3) * jy + R(0.5) * o.Fty) * inv_rho;
+    const R c2dr = R(D.dRho) * R(1.0 / 3.0);
+    o.Fpx = -in.dpx + c2dr * in.dphx;
+    o.Fpy = -in.dpy + c2dr * in.dphy;
+    o.p = in.pbar + R(0.5) * (o.Fpx * o.ux + o.Fpy * o.uy);
+    o.psi = o.p - rho * R(1.0 / 3.0);
+    return o;
+}
+
+// Adds K c to v (the nine rows of the expansion of K . c).
+template <class R>
+__device__ __forceinline__ void add_Kc(R v[9], R c0, R c1, R c2, R c3, R c4, R c5, R c6, R c7,
+                                       R c8) {
+    const R A = c0 - c3 - R(2) * c8;
+    const R B = c0 + R(2) * c3 + c8;
+    const R x1 = c1 + R(2) * c7, y1 = c2 + R(2) * c6;
+    const R x2 = c1 - c7, y2 = c2 - c6;
+    v[0] += c0 - R(4) * c3 + R(4) * c8;
+    v[1] += (A + c4) + x1;
+    v[3] += (A + c4) - x1;
+    v[2] += (A - c4) + y1;
+    v[4] += (A - c4) - y1;
+    v[5] += (B + c5) + (x2 + y2);
+    v[7] += (B + c5) - (x2 + y2);
+    v[6] += (B - c5) + (y2 - x2);
+    v[8] += (B - c5) - (y2 - x2);
+}
+
+// Pressure-based cascaded collision with its cumulative source (Sec. 4), with
+// omega_0..3 = omega_6..8 = 1 and omega_4 = omega_5 = omv.  The source term
+// K^{-1}(I - Lambda/2) K S and the collision K h are folded into one K c with
+// c_j = h_j + m^s'_j / |K_j|^2 (for j = 0, 1, 2 the omega dependence cancels).
+template <class R>
+__device__ __forceinline__ void hydro_collide(R g[9], const NodeOut<R>& o) {
+    const R ux = o.ux, uy = o.uy, ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy;
+    const R third = R(1.0 / 3.0);
+    const R Gam = o.Fpx * ux + o.Fpy * uy;
+    // raw source moments sigma'_mn (third and fourth order are zero)
+    const R Sx = o.Ftx + o.Fpx, Sy = o.Fty + o.Fpy;
+    const R s20 = R(2.0 / 3.0) * Sx * ux + third * Gam;
+    const R s02 = R(2.0 / 3.0) * Sy * uy + third * Gam;
+    const R s11 = third * (Sx * uy + Sy * ux);
+    const R hw = R(1) - R(0.5) * o.omv;
+    // raw moments of gbar
+    const R d = (g[5] + g[6]) + (g[7] + g[8]);
+    const R e20 = (g[1] + g[3]) + d;
+    const R e02 = (g[2] + g[4]) + d;
+    const R e11 = (g[5] - g[6]) + (g[7] - g[8]);
+    const R e21 = (g[5] + g[6]) - (g[7] + g[8]);
+    const R e12 = (g[5] - g[6]) + (g[8] - g[7]);
+    const R e22 = d;
+    const R rc2 = o.rho * third, p = o.p, psi = o.psi;
+    const R q4 = R(0.25) * o.omv;
+    const R h3 = R(1.0 / 12.0) * (R(2.0 / 3.0) * p + rc2 * (ux2 + uy2) - (e20 + e02));
+    const R h4 = q4 * (rc2 * (ux2 - uy2) - (e20 - e02));
+    const R h5 = q4 * (rc2 * uxy - e11);
+    const R h6 = R(0.25) * (psi * (third + ux2) * uy + e21 - uy * e20 - R(2) * ux * e11 +
+                            o.rho * ux2 * uy - ux2 * uy * p) -
+                 uy * (R(1.5) * h3 + R(0.5) * h4) - R(2) * ux * h5;
+    const R h7 = R(0.25) * (psi * (third + uy2) * ux + e12 - R(2) * uy * e11 - ux * e02 +
+                            o.rho * ux * uy2 - ux * uy2 * p) -
+                 ux * (R(1.5) * h3 - R(0.5) * h4) - R(2) * uy * h5;
+    const R ux2uy2 = ux2 * uy2;
+    const R h8 = R(0.25) * (o.rho * R(1.0 / 27.0) + psi * (third + ux2) * (third + uy2) - e22 +
+                            R(2) * (uy * e21 + ux * e12) - (uy2 * e20 + ux2 * e02) -
+                            R(4) * uxy * e11 + R(4.0 / 3.0) * o.rho * ux2uy2 - ux2uy2 * p) -
+                 R(2) * h3 - R(0.5) * uy2 * (R(3) * h3 + h4) - R(0.5) * ux2 * (R(3) * h3 - h4) -
+                 R(4) * uxy * h5 - R(2) * uy * h6 - R(2) * ux * h7;
+    const R c0 = Gam * R(1.0 / 9.0);
+    const R c1 = o.Ftx * R(1.0 / 18.0);
+    const R c2 = o.Fty * R(1.0 / 18.0);
+    const R c3 = h3 + R(1.0 / 72.0) * (R(3) * (s20 + s02) - R(4) * Gam);
+    const R c4 = h4 + R(0.25) * hw * (s20 - s02);
+    const R c5 = h5 + R(0.25) * hw * s11;
+    const R c6 = h6 + o.Fty * R(1.0 / 36.0);
+    const R c7 = h7 + o.Ftx * R(1.0 / 36.0);
+    const R c8 = h8 + R(1.0 / 72.0) * (R(4) * Gam - R(6) * (s20 + s02));
+    add_Kc(g, c0, c1, c2, c3, c4, c5, c6, c7, c8);
+}
+
+// Conservative Allen-Cahn cascaded collision (Sec. 5) with omega_1 = omega_2 =
+// omphi and the other rates 1; the first-order equilibria carry M theta n.
+template <class R>
+__device__ __forceinline__ void ace_collide(R f[9], R phi, R ux, R uy, R Mth_x, R Mth_y,
+                                            R omphi) {
+    const R ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy;
+    const R k10 = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+    const R k01 = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+    const R d = (f[5] + f[6]) + (f[7] + f[8]);
+    const R k20 = (f[1] + f[3]) + d;
+    const R k02 = (f[2] + f[4]) + d;
+    const R k11 = (f[5] - f[6]) + (f[7] - f[8]);
+    const R k21 = (f[5] + f[6]) - (f[7] + f[8]);
+    const R k12 = (f[5] - f[6]) + (f[8] - f[7]);
+    const R k22 = d;
+    const R w6 = omphi * R(1.0 / 6.0);
+    const R G1 = w6 * (phi * ux + Mth_x - k10);
+    const R G2 = w6 * (phi * uy + Mth_y - k01);
+    const R G3 = R(1.0 / 12.0) * (R(2.0 / 3.0) * phi - (ux2 + uy2) * phi - (k20 + k02) +
+                                  R(2) * (ux * k10 + uy * k01)) +
+                 ux * G1 + uy * G2;
+    const R G4 = R(0.25) * (-(ux2 - uy2) * phi - (k20 - k02) + R(2) * (ux * k10 - uy * k01)) +
+                 R(3) * (ux * G1 - uy * G2);
+    const R G5 = R(0.25) * (-uxy * phi - k11 + (ux * k01 + uy * k10)) + R(1.5) * (ux * G2 + uy * G1);
+    const R G6 = R(0.25) * (-ux2 * uy * phi + k21 - uy * k20 - R(2) * ux * k11 +
+                            R(2) * uxy * k10 + ux2 * k01) +
+                 R(3) * uxy * G1 + (R(1.5) * ux2 + R(1)) * G2 - R(1.5) * uy * G3 -
+                 R(0.5) * uy * G4 - R(2) * ux * G5;
+    const R G7 = R(0.25) * (-ux * uy2 * phi + k12 - ux * k02 - R(2) * uy * k11 +
+                            R(2) * uxy * k01 + uy2 * k10) +
+                 (R(1.5) * uy2 + R(1)) * G1 + R(3) * uxy * G2 - R(1.5) * ux * G3 +
+                 R(0.5) * ux * G4 - R(2) * uy * G5;
+    const R G8 = R(0.25) * (phi * R(1.0 / 9.0) - k22 + R(2) * (ux * k12 + uy * k21) -
+                            (uy2 * k20 + ux2 * k02) - R(4) * uxy * k11 +
+                            R(2) * (ux * uy2 * k10 + ux2 * uy * k01) - ux2 * uy2 * phi) +
+                 (R(2) * ux + R(3) * ux * uy2) * G1 + (R(2) * uy + R(3) * ux2 * uy) * G2 -
+                 (R(2) + R(1.5) * (ux2 + uy2)) * G3 + R(0.5) * (ux2 - uy2) * G4 -
+                 R(4) * uxy * G5 - R(2) * uy * G6 - R(2) * ux * G7;
+    add_Kc(f, R(0), G1, G2, G3, G4, G5, G6, G7, G8);
+}
+
+// ------------------------------------------------------------- fused kernel
+
+template <class ST, int TX, int MODE>
+__global__ void __launch_bounds__(TX) lb_fused(const LatDesc* __restrict__ descs,
+                                               const WorkItem* __restrict__ items, int n_items,
+                                               int parity) {
+    using R = typename ST::R;
+    using T = typename ST::T;
+    constexpr int LW = TX + 4;
+    __shared__ R s_phi[4][LW];
+    __shared__ R s_pb[4][LW];
+    __shared__ R s_na[4][LW];  // n_x (geometric) or mu_phi (chemical potential)
+    __shared__ R s_nb[4][LW];  // n_y (geometric)
+    const int t = threadIdx.x;
+
+    for (int wi = blockIdx.x; wi < n_items; wi += gridDim.x) {
+        const WorkItem it = items[wi];
+        const LatDesc& D = descs[it.inst];
+        const int nx = D.nx, ny = D.ny, wall = D.wall_y, chem = D.st_form;
+        const int64_t P = D.plane;
+        const T* __restrict__ src = reinterpret_cast<const T*>(D.buf[parity]);
+        T* __restrict__ dst = reinterpret_cast<T*>(D.buf[parity ^ 1]);
+        const T* __restrict__ srcg = src + 9 * P;
+        T* __restrict__ dstg = dst + 9 * P;
+        const R shf = R(D.shift_f), shg = R(D.shift_g);
+        const int x0 = it.x0;
+        const int wdt = min(TX, nx - x0);
+        const bool act = t < wdt;
+        const int x = x0 + (act ? t : 0);
+        const int c = t + 2;
+        // helper lanes: phi at the two halo columns on each side; pbar / n at one
+        int hcell = -1, hx = 0;
+        if (t == 0) { hcell = 0; hx = x0 - 2; }
+        else if (t == 1) { hcell = 1; hx = x0 - 1; }
+        else if (t == TX - 2) { hcell = wdt + 2; hx = x0 + wdt; }
+        else if (t == TX - 1) { hcell = wdt + 3; hx = x0 + wdt + 1; }
+        hx = ((hx % nx) + nx) % nx;
+        const bool hphi = hcell >= 0;
+        const bool hn = hcell == 1 || hcell == wdt + 2;  // pbar and n halo cells
+
+        R f0[9], f1[9], f2[9], g0[9], g1[9];
+        R cdx = 0, cdy = 0, cm2 = 0, cnx = 0, cny = 0;  // centre grad/normal at row L-1
+        R pdx = 0, pdy = 0, pm2 = 0, pnx = 0, pny = 0;  // same, one row below (row L-2)
+#pragma unroll
+        for (int a = 0; a < 9; ++a) { f0[a] = f1[a] = f2[a] = g0[a] = g1[a] = R(0); }
+
+        const int H = it.y1 - it.y0;
+        for (int k = 0; k < H + 4; ++k) {
+            const int L = it.y0 - 2 + k;
+            // ---- A: phi at the leading row
+            {
+                const int Lr = map_row(L, ny, wall);
+                R* sp = s_phi[L & 3];
+                if (act) {
+                    pull9<ST>(src, P, nx, ny, wall, x, Lr, shf, f0);
+                    sp[c] = sum9(f0);
+                }
+                if (hphi) {
+                    R tmp[9];
+                    pull9<ST>(src, P, nx, ny, wall, hx, Lr, shf, tmp);
+                    sp[hcell] = sum9(tmp);
+                }
+            }
+            // ---- B: pbar one row behind
+            if (k >= 2) {
+                const int Lg = L - 1;
+                const int Lgr = map_row(Lg, ny, wall);
+                R* sp = s_pb[Lg & 3];
+                if (act) {
+                    pull9<ST>(srcg, P, nx, ny, wall, x, Lgr, shg, g0);
+                    sp[c] = sum9(g0);
+                }
+                if (hn) {
+                    R tmp[9];
+                    pull9<ST>(srcg, P, nx, ny, wall, hx, Lgr, shg, tmp);
+                    sp[hcell] = sum9(tmp);
+                }
+            }
+            __syncthreads();
+            // ---- D: gradient, normal or chemical potential at row L-1
+            if (k >= 2) {
+                const int Ln = L - 1;
+                const R* rs = s_phi[(Ln - 1) & 3];
+                const R* rm = s_phi[Ln & 3];
+                const R* rn = s_phi[(Ln + 1) & 3];
+                R* na = s_na[Ln & 3];
+                R* nb = s_nb[Ln & 3];
+                R yrow = R(0);
+                if (chem) yrow = R(map_row(Ln, ny, wall));
+#pragma unroll
+                for (int pass = 0; pass < 2; ++pass) {
+                    const bool on = pass == 0 ? act : hn;
+                    const int cc = pass == 0 ? c : hcell;
+                    if (on) {
+                        R gx, gy;
+                        grad3x3(rs, rm, rn, cc, gx, gy);
+                        const R m2 = gx * gx + gy * gy;
+                        // unit normal; zero where |grad phi| < 1e-12
+                        const R m = sqrt(m2);
+                        R ix = R(0), iy = R(0);
+                        if (!(m < R(1e-12))) {
+                            const R im = R(1) / m;
+                            ix = gx * im;
+                            iy = gy * im;
+                        }
+                        if (chem) {
+                            const R ph = rm[cc];
+                            const R beta = R(D.be_a) + R(D.be_b) * yrow;
+                            const R kap = R(D.ka_a) + R(D.ka_b) * yrow;
+                            na[cc] = R(4) * beta * (ph - R(1)) * ph * (ph - R(0.5)) -
+                                     kap * lap3x3(rs, rm, rn, cc);
+                        } else {
+                            na[cc] = ix;
+                            nb[cc] = iy;
+                        }
+                        if (pass == 0) { cdx = gx; cdy = gy; cm2 = m2; cnx = ix; cny = iy; }
+                    }
+                }
+            }
+            __syncthreads();
+            // ---- F: collide row C = L - 2
+            if (k >= 4 && act) {
+                const int C = L - 2;
+                NodeIn<R> in;
+                in.phi = s_phi[C & 3][c];
+                in.pbar = s_pb[C & 3][c];
+                in.dphx = pdx; in.dphy = pdy; in.m2 = pm2; in.nx = pnx; in.ny = pny;
+                in.y = R(C);
+                in.divn = R(0); in.dmux = R(0); in.dmuy = R(0);
+                {
+                    R gx, gy;
+                    grad3x3(s_pb[(C - 1) & 3], s_pb[C & 3], s_pb[(C + 1) & 3], c, gx, gy);
+                    in.dpx = gx; in.dpy = gy;
+                }
+                if (chem) {
+                    R gx, gy;
+                    grad3x3(s_na[(C - 1) & 3], s_na[C & 3], s_na[(C + 1) & 3], c, gx, gy);
+                    in.dmux = gx; in.dmuy = gy;
+                } else {
+                    R a1, a2, b1, b2;
+                    grad3x3(s_na[(C - 1) & 3], s_na[C & 3], s_na[(C + 1) & 3], c, a1, a2);
+                    grad3x3(s_nb[(C - 1) & 3], s_nb[C & 3], s_nb[(C + 1) & 3], c, b1, b2);
+                    in.divn = a1 + b2;
+                }
+                const NodeOut<R> o = node_macro<R>(D, in, g1);
+                const int64_t idx = (int64_t)C * nx + x;
+                if constexpr (MODE == MODE_STEP) {
+                    hydro_collide<R>(g1, o);
+                    const R th = R(D.four_W) * in.phi * (R(1) - in.phi);
+                    const R Mth = R(D.M) * th;
+                    ace_collide<R>(f2, in.phi, o.ux, o.uy, Mth * in.nx, Mth * in.ny, R(D.omphi));
+                    const R w0 = R(4.0 / 9.0), w1 = R(1.0 / 9.0), w5 = R(1.0 / 36.0);
+#pragma unroll
+                    for (int a = 0; a < 9; ++a) {
+                        const R wa = a == 0 ? w0 : (a < 5 ? w1 : w5);
+                        dst[a * P + idx] = ST::st(f2[a] - wa * shf);
+                        dstg[a * P + idx] = ST::st(g1[a] - wa * shg);
+                    }
+                } else if constexpr (MODE == MODE_FIELDS) {
+                    double* F = D.fields;
+                    const int64_t N = (int64_t)nx * ny;
+                    F[idx] = (double)in.phi;
+                    F[N + idx] = (double)o.p;
+                    F[2 * N + idx] = (double)o.ux;
+                    F[3 * N + idx] = (double)o.uy;
+                } else {
+                    double* F = D.fields;
+                    const int64_t N = (int64_t)nx * ny;
+                    F[idx] = (double)in.dphx;
+                    F[N + idx] = (double)in.dphy;
+                    F[2 * N + idx] = (double)in.nx;
+                    F[3 * N + idx] = (double)in.ny;
+                    F[4 * N + idx] = (double)in.divn;
+                    F[5 * N + idx] = (double)o.Ftx;
+                    F[6 * N + idx] = (double)o.Fty;
+                    F[7 * N + idx] = (double)o.Fpx;
+                    F[8 * N + idx] = (double)o.Fpy;
+                }
+            }
+            // ---- rotate the register pipeline
+#pragma unroll
+            for (int a = 0; a < 9; ++a) { f2[a] = f1[a]; f1[a] = f0[a]; g1[a] = g0[a]; }
+            pdx = cdx; pdy = cdy; pm2 = cm2; pnx = cnx; pny = cny;
+        }
+        __syncthreads();  // the rings are reused by the next work item
+    }
+}
+
+}  // namespace cmlb

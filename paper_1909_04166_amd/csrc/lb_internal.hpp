@@ -1,0 +1,22 @@
+// lb_internal.hpp -- declarations shared by the kernels and the host runtime.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/cmlb.h"
+#include "lb_device.hpp"
+
+namespace cmlb {
+
+hipError_t launch_step(int prec, int tx, const LatDesc* d, const WorkItem* items, int n_items,
+                       int grid, int parity, hipStream_t s);
+hipError_t launch_extract(int prec, int mode, const LatDesc* d, const WorkItem* items64,
+                          int n_items, int parity, hipStream_t s);
+// op 0: init from phi0 plane; 1: set stored plane from staged plane a; 2: get plane a
+hipError_t launch_state_op(int prec, int op, const LatDesc* d, double* plane, int a, int which,
+                           int cur, int64_t N, hipStream_t s);
+hipError_t launch_diag(const LatDesc* d, const double* fields, double* part, double* out, int ny,
+                       double step, double u_max, hipStream_t s);
+hipError_t launch_copy(void* dst, const void* src, uint64_t n, hipStream_t s);
+
+}  // namespace cmlb

@@ -1,0 +1,78 @@
+"""The C-ABI library loads, exports every function declared in include/cmlb.h,
+and its host-side validation rejects bad configurations (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1909_04166_amd import lb, workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "cmlb.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lb_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(lb.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 30
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    # and the binding covers each of them
+    assert set(names) <= set(lb._SIGS)
+
+
+def test_struct_layout_matches_binding():
+    lb.lib()  # raises on mismatch
+
+
+def test_workspace_bytes_and_validation():
+    case, _ = W.config("droplet128")
+    cfg = lb.config_from_case(case, "fp64")
+    n64 = lb.lb_workspace_bytes(cfg)
+    # two copies of 18 planes of 8-byte values dominate
+    assert n64 >= 2 * 18 * 8 * 128 * 128
+    cfg16 = lb.config_from_case(case, "bf16")
+    assert lb.lb_workspace_bytes(cfg16) < n64
+    bad = [dict(nx=4), dict(nu_A=0.0), dict(W=-1.0), dict(M=0.0), dict(rho_B=-1.0)]
+    for b in bad:
+        c = dict(case)
+        c.update(b)
+        with pytest.raises(lb.LBError) as e:
+            lb.lb_workspace_bytes(lb.config_from_case(c, "fp64"))
+        assert e.value.code == lb.LB_E_INVALID_ARG
+    c = lb.config_from_case(case, "fp64")
+    c.bc_x = lb.LB_HALFWAY_BB
+    with pytest.raises(lb.LBError) as e:
+        lb.lb_workspace_bytes(c)
+    assert e.value.code == lb.LB_E_UNSUPPORTED
+    c = lb.config_from_case(case, "fp64")
+    c.tile_x = 96
+    with pytest.raises(lb.LBError):
+        lb.lb_workspace_bytes(c)
+
+
+def test_create_rejects_small_or_misaligned_workspace():
+    case, _ = W.config("droplet128")
+    cfg = lb.config_from_case(case, "fp64")
+    n = lb.lb_workspace_bytes(cfg)
+    with pytest.raises(lb.LBError) as e:
+        lb.lb_create(cfg, 1 << 20, n - 1, 0)
+    assert e.value.code == lb.LB_E_WORKSPACE
+    with pytest.raises(lb.LBError) as e:
+        lb.lb_create(cfg, (1 << 20) + 8, n, 0)
+    assert e.value.code == lb.LB_E_WORKSPACE
+
+
+def test_batch_workspace_bytes():
+    a = lb.lb_batch_workspace_bytes(4, 1 << 16, "fp32")
+    b = lb.lb_batch_workspace_bytes(4, 1 << 17, "fp32")
+    assert b > a > 2 * 18 * 4 * (1 << 16)
+    with pytest.raises(lb.LBError):
+        lb.lb_batch_workspace_bytes(0, 1 << 16, "fp32")
