@@ -102,6 +102,9 @@ def main():
     ap.add_argument("--tile", default="0,0")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--extra", action="store_true", help="also time the other precisions and workloads")
+    ap.add_argument("--copy-ref", type=int, default=0, metavar="MIB",
+                    help="only run the library's device copy kernel over MIB MiB (bandwidth and "
+                         "counter reference) and print its GB/s")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -114,6 +117,24 @@ def main():
         raise SystemExit("bench.py needs a HIP device")
     lb.lib()
     tile = tuple(int(v) for v in args.tile.split(","))
+    if args.copy_ref:
+        n = args.copy_ref << 20
+        a = torch.empty(n, dtype=torch.uint8, device="cuda")
+        b = torch.empty(n, dtype=torch.uint8, device="cuda")
+        stream = torch.cuda.current_stream().cuda_stream
+        for _ in range(3):
+            lb.lb_copy_kernel(b.data_ptr(), a.data_ptr(), n, stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        reps = 20
+        for _ in range(reps):
+            lb.lb_copy_kernel(b.data_ptr(), a.data_ptr(), n, stream)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        print(json.dumps({"copy_kernel_bytes_read": n, "bytes_written": n, "ms": ms,
+                          "GBs": 2 * n / (ms * 1e-3) / 1e9}), flush=True)
+        return
 
     case, phi0, desc = make_workload(args.workload)
     N = case["nx"] * case["ny"]

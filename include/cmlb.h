@@ -80,8 +80,9 @@ typedef struct lb_config {
     double gx, gy;           /* body-force acceleration */
     double shift_f, shift_g; /* 16-bit storage stores f_a - w_a shift_f and g_a - w_a shift_g */
     double u_max;            /* stability limit for diagnostics (0: 0.3) */
-    int32_t tile_x;          /* strip width in nodes (64, 128 or 256); 0: autotuned */
-    int32_t tile_h;          /* rows per work item; 0: autotuned */
+    int32_t tile_x;          /* workgroup width in lanes (64, 128 or 256; strips of tile_x - 4
+                                columns); 0: autotuned */
+    int32_t tile_h;          /* rows per work item (>= 8); 0: autotuned */
 } lb_config;
 
 typedef struct lb_diag {
@@ -211,8 +212,11 @@ lb_status lb_timing_read(lb_handle* h, double* ms_per_step, int64_t* steps);
 lb_status lb_batch_timing_enable(lb_batch* b, int32_t on);
 lb_status lb_batch_timing_read(lb_batch* b, double* ms_per_step, int64_t* steps);
 
-/* Tile shape chosen for the handle (after autotuning when tile_x/tile_h were 0). */
-lb_status lb_get_tile(lb_handle* h, int32_t* tile_x, int32_t* tile_h);
+/* Schedule chosen for the handle (after autotuning when tile_x/tile_h were 0):
+ * workgroup width tile_x (lanes; the strip is tile_x - 4 columns), rows per work
+ * item (or per persistent segment), and the persistent grid size (0 when every
+ * work item gets its own workgroup). */
+lb_status lb_get_schedule(lb_handle* h, int32_t* tile_x, int32_t* rows, int32_t* grid);
 
 /* sizeof(lb_config) and sizeof(lb_diag) as compiled, for binding checks. */
 lb_status lb_struct_sizes(uint64_t* config_bytes, uint64_t* diag_bytes);

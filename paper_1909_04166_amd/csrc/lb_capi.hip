@@ -40,7 +40,8 @@ bool finite_pos(double v) { return std::isfinite(v) && v > 0; }
 lb_status validate(const lb_config* c) {
     if (!c) return LB_E_INVALID_ARG;
     if (c->nx < 8 || c->ny < 8 || c->nx > (1 << 20) || c->ny > (1 << 20)) return LB_E_INVALID_ARG;
-    if ((int64_t)c->nx * c->ny > ((int64_t)1 << 31)) return LB_E_INVALID_ARG;
+    // every plane (storage type) and every FP64 field plane must be < 4 GiB
+    if ((uint64_t)c->nx * c->ny * 8 >= ((uint64_t)1 << 32)) return LB_E_INVALID_ARG;
     if (c->bc_x != LB_PERIODIC) return c->bc_x == LB_HALFWAY_BB ? LB_E_UNSUPPORTED : LB_E_INVALID_ARG;
     if (c->bc_y != LB_PERIODIC && c->bc_y != LB_HALFWAY_BB) return LB_E_INVALID_ARG;
     if (c->force_ref < LB_FREF_MEAN || c->force_ref > LB_FREF_NONE) return LB_E_INVALID_ARG;
@@ -109,11 +110,60 @@ void fill_desc(const lb_config* c, LatDesc& D, void* b0, void* b1, int64_t plane
     D.shift_g = half ? c->shift_g : 0.0;
 }
 
-// Work items of one lattice: strips of tx columns, runs of th rows; strip-major
-// so that consecutive items are vertically adjacent (they share halo rows).
+// Strip width of a TX-lane workgroup: two halo lanes on each side.
+inline int strip_w(int tx) { return tx - 4; }
+
+// Work items of one lattice: strips of tx - 4 columns, runs of th rows;
+// strip-major so that consecutive items are vertically adjacent (they share
+// halo rows).
 void build_items(int inst, int nx, int ny, int tx, int th, std::vector<WorkItem>& out) {
-    for (int x0 = 0; x0 < nx; x0 += tx)
+    for (int x0 = 0; x0 < nx; x0 += strip_w(tx))
         for (int y0 = 0; y0 < ny; y0 += th) out.push_back({inst, x0, y0, std::min(ny, y0 + th)});
+}
+
+struct LatShape {
+    int inst, nx, ny;
+};
+
+// Balanced persistent schedule: the rows of every strip of every lattice, in
+// order, are cut into G contiguous segments of nearly equal length; block b
+// runs segment b as the items at positions b, b + G, b + 2G, ... (padding
+// items are empty).  Returns false if more than max_items slots are needed.
+bool build_segments(const std::vector<LatShape>& lats, int tx, int G, int max_items,
+                    std::vector<WorkItem>& out, int* nblocks) {
+    *nblocks = 0;
+    struct Strip { int inst, x0, ny; };
+    std::vector<Strip> strips;
+    int64_t total = 0;
+    for (const auto& l : lats)
+        for (int x0 = 0; x0 < l.nx; x0 += strip_w(tx)) {
+            strips.push_back({l.inst, x0, l.ny});
+            total += l.ny;
+        }
+    if (total == 0 || G <= 0) { out.clear(); return true; }
+    const int64_t per = std::max<int64_t>(8, (total + G - 1) / G);
+    const int nb = (int)std::min<int64_t>(G, (total + per - 1) / per);
+    std::vector<std::vector<WorkItem>> blocks(nb);
+    int b = 0;
+    int64_t used = 0;
+    for (const auto& st : strips) {
+        int y = 0;
+        while (y < st.ny) {
+            const int take = (int)std::min<int64_t>(st.ny - y, per - used);
+            blocks[b].push_back({st.inst, st.x0, y, y + take});
+            y += take;
+            used += take;
+            if (used == per && b + 1 < nb) { ++b; used = 0; }
+        }
+    }
+    size_t maxj = 0;
+    for (auto& bl : blocks) maxj = std::max(maxj, bl.size());
+    if ((int64_t)maxj * nb > max_items) return false;
+    out.assign(maxj * nb, WorkItem{0, 0, 0, 0});
+    for (int i = 0; i < nb; ++i)
+        for (size_t j = 0; j < blocks[i].size(); ++j) out[j * nb + i] = blocks[i][j];
+    *nblocks = nb;
+    return true;
 }
 
 // Blocks are dispatched round-robin over the 8 XCDs (block b -> XCD b % 8).
@@ -136,7 +186,10 @@ void xcd_permute(std::vector<WorkItem>& items, int grid) {
     items.swap(out);
 }
 
-int max_items_for(int nx, int ny) { return ((nx + 63) / 64) * ((ny + kMinH - 1) / kMinH); }
+constexpr int kMaxGrid = 16384;
+int max_items_for(int nx, int ny) {
+    return ((nx + 59) / 60) * ((ny + kMinH - 1) / kMinH) + 3 * kMaxGrid;
+}
 
 int cu_count() {
     static int n = -1;
@@ -151,13 +204,48 @@ int cu_count() {
     return n;
 }
 
-void default_tile(int nx, int ny, int& tx, int& th) {
-    tx = nx >= 2048 ? 256 : (nx >= 512 ? 128 : 64);
-    const int strips = (nx + tx - 1) / tx;
-    const int target = 4 * cu_count();  // items wanted
-    th = 256;
-    while (th > 16 && (int64_t)strips * ((ny + th - 1) / th) < target) th /= 2;
-    if (th > ny) th = ny < kMinH ? kMinH : ny;
+// How a step is spread over workgroups.
+//   mode 0: one work item of th rows per workgroup, grid = number of items,
+//           items ordered so that each XCD gets vertically adjacent ones;
+//   mode 1: persistent grid of mult * (resident workgroups per CU) * CUs, each
+//           workgroup one balanced segment of the concatenated strip rows.
+struct Sched {
+    int tx = 64, th = 64, mode = 0, mult = 1;
+    int grid = 0, n_items = 0, rows = 0;
+};
+
+bool build_schedule(const std::vector<LatShape>& lats, int prec, Sched& sc, int max_items,
+                    std::vector<WorkItem>& items) {
+    items.clear();
+    if (sc.mode == 0) {
+        for (const auto& l : lats) build_items(l.inst, l.nx, l.ny, sc.tx, sc.th, items);
+        if ((int64_t)items.size() > max_items) return false;
+        sc.grid = (int)items.size();
+        sc.rows = sc.th;
+        xcd_permute(items, sc.grid);
+    } else {
+        int G = sc.mult * std::max(1, fused_occupancy(prec, sc.tx)) * cu_count();
+        G = std::min(G, kMaxGrid);
+        int nb = 0;
+        if (!build_segments(lats, sc.tx, G, max_items, items, &nb)) return false;
+        sc.grid = nb;
+        int64_t total = 0;
+        for (const auto& l : lats) total += (int64_t)((l.nx + strip_w(sc.tx) - 1) / strip_w(sc.tx)) * l.ny;
+        sc.rows = nb ? (int)((total + nb - 1) / nb) : 0;
+    }
+    sc.n_items = (int)items.size();
+    return true;
+}
+
+Sched default_sched(int nx, int ny) {
+    Sched sc;
+    sc.tx = nx >= 1024 ? 256 : (nx >= 256 ? 128 : 64);
+    sc.mode = 0;
+    const int strips = (nx + strip_w(sc.tx) - 1) / strip_w(sc.tx);
+    const int target = 2 * cu_count();
+    sc.th = 256;
+    while (sc.th > 16 && (int64_t)strips * ((ny + sc.th - 1) / sc.th) < target) sc.th /= 2;
+    return sc;
 }
 
 struct TuneKey {
@@ -167,7 +255,7 @@ struct TuneKey {
     }
 };
 std::mutex g_tune_mu;
-std::map<TuneKey, std::pair<int, int>> g_tune;
+std::map<TuneKey, Sched> g_tune;
 
 #define HIPC(x)                                 \
     do {                                        \
@@ -199,7 +287,7 @@ struct lb_handle {
     int sbytes = 0;
     int parity = 0;
     int64_t step = 0;
-    int tx = 0, th = 0;
+    Sched sc;
     bool tuned = false;
     // diagnostics
     double* h_diag = nullptr;  // pinned, 16 doubles
@@ -230,7 +318,7 @@ Layout layout_of(const lb_config* c) {
     L.desc = o; o += align_up(sizeof(LatDesc));
     L.desc_cp = o; o += align_up(sizeof(LatDesc));
     L.items = o; o += align_up((uint64_t)max_items_for(c->nx, c->ny) * sizeof(WorkItem));
-    L.items64 = o; o += align_up((uint64_t)((c->nx + 63) / 64) * ((c->ny + 63) / 64) * sizeof(WorkItem));
+    L.items64 = o; o += align_up((uint64_t)((c->nx + 59) / 60) * ((c->ny + 63) / 64) * sizeof(WorkItem));
     L.part = o; o += align_up((uint64_t)4 * c->ny * sizeof(double));
     L.dout = o; o += align_up(16 * sizeof(double));
     L.fields = o; o += align_up((uint64_t)4 * N * sizeof(double));
@@ -240,17 +328,15 @@ Layout layout_of(const lb_config* c) {
     return L;
 }
 
-lb_status set_items(lb_handle* h, int tx, int th) {
+lb_status set_sched(lb_handle* h, Sched sc) {
     std::vector<WorkItem> items;
-    build_items(0, h->cfg.nx, h->cfg.ny, tx, th, items);
-    if ((int)items.size() > h->max_items) return LB_E_INVALID_ARG;
-    xcd_permute(items, (int)items.size());
+    if (!build_schedule({{0, h->cfg.nx, h->cfg.ny}}, h->cfg.precision, sc, h->max_items, items))
+        return LB_E_INVALID_ARG;
     HIPC(hipMemcpyAsync(h->d_items, items.data(), items.size() * sizeof(WorkItem),
                         hipMemcpyHostToDevice, h->s));
     HIPC(hipStreamSynchronize(h->s));
-    h->n_items = (int)items.size();
-    h->tx = tx;
-    h->th = th;
+    h->n_items = sc.n_items;
+    h->sc = sc;
     for (int p = 0; p < 2; ++p)
         if (h->gexec[p]) { (void)hipGraphExecDestroy(h->gexec[p]); h->gexec[p] = nullptr; }
     return LB_OK;
@@ -258,7 +344,7 @@ lb_status set_items(lb_handle* h, int tx, int th) {
 
 lb_status launch_steps_eager(lb_handle* h, int64_t n) {
     for (int64_t i = 0; i < n; ++i) {
-        HIPC(launch_step(h->cfg.precision, h->tx, h->d_desc, h->d_items, h->n_items, h->n_items,
+        HIPC(launch_step(h->cfg.precision, h->sc.tx, h->d_desc, h->d_items, h->n_items, h->sc.grid,
                          h->parity, h->s));
         h->parity ^= 1;
         h->step += 1;
@@ -275,7 +361,7 @@ lb_status graph_for(lb_handle* h, int parity, hipGraphExec_t* out) {
         hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         int p = parity;
         for (int i = 0; i < h->glen && e == hipSuccess; ++i) {
-            e = launch_step(h->cfg.precision, h->tx, h->d_desc, h->d_items, h->n_items, h->n_items,
+            e = launch_step(h->cfg.precision, h->sc.tx, h->d_desc, h->d_items, h->n_items, h->sc.grid,
                             p, cs);
             p ^= 1;
         }
@@ -323,37 +409,52 @@ double time_candidate(int prec, int tx, const LatDesc* d, const WorkItem* items,
     return ms_out;
 }
 
+// Candidate schedules for one lattice shape.
+std::vector<Sched> candidates(int nx, int ny) {
+    std::vector<Sched> out;
+    for (int tx : {64, 128, 256}) {
+        if (tx > 64 && nx <= strip_w(tx / 2)) continue;
+        for (int th : {16, 32, 64, 128, 256}) {
+            if (th > ny && th != 16) continue;
+            Sched sc;
+            sc.tx = tx; sc.th = th; sc.mode = 0;
+            out.push_back(sc);
+        }
+        for (int m : {1, 2}) {
+            Sched sc;
+            sc.tx = tx; sc.mode = 1; sc.mult = m;
+            out.push_back(sc);
+        }
+    }
+    return out;
+}
+
 lb_status autotune_single(lb_handle* h) {
     const TuneKey key{h->cfg.precision, h->cfg.nx, h->cfg.ny, h->hdesc.wall_y, h->cfg.st_form, 0};
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune.find(key);
-        if (it != g_tune.end()) return set_items(h, it->second.first, it->second.second);
+        if (it != g_tune.end()) return set_sched(h, it->second);
     }
-    int best_tx = h->tx, best_th = h->th;
+    Sched best_sc = h->sc;
     double best = 1e30;
     const int64_t N = (int64_t)h->cfg.nx * h->cfg.ny;
     const int reps = N >= (1 << 22) ? 3 : 10;
-    for (int tx : {64, 128, 256}) {
-        if (tx > 64 && h->cfg.nx < tx) continue;
-        for (int th : {16, 32, 64, 128, 256}) {
-            if (th > h->cfg.ny && th != 16) continue;
-            std::vector<WorkItem> items;
-            build_items(0, h->cfg.nx, h->cfg.ny, tx, th, items);
-            if ((int)items.size() > h->max_items) continue;
-            xcd_permute(items, (int)items.size());
-            HIPC(hipMemcpyAsync(h->d_items, items.data(), items.size() * sizeof(WorkItem),
-                                hipMemcpyHostToDevice, h->s));
-            const double ms = time_candidate(h->cfg.precision, tx, h->d_desc, h->d_items,
-                                             (int)items.size(), (int)items.size(), h->parity, h->s, reps);
-            if (ms < best) { best = ms; best_tx = tx; best_th = th; }
-        }
+    for (Sched sc : candidates(h->cfg.nx, h->cfg.ny)) {
+        std::vector<WorkItem> items;
+        if (!build_schedule({{0, h->cfg.nx, h->cfg.ny}}, h->cfg.precision, sc, h->max_items, items))
+            continue;
+        HIPC(hipMemcpyAsync(h->d_items, items.data(), items.size() * sizeof(WorkItem),
+                            hipMemcpyHostToDevice, h->s));
+        const double ms = time_candidate(h->cfg.precision, sc.tx, h->d_desc, h->d_items, sc.n_items,
+                                         sc.grid, h->parity, h->s, reps);
+        if (ms < best) { best = ms; best_sc = sc; }
     }
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune[key] = {best_tx, best_th};
+        g_tune[key] = best_sc;
     }
-    return set_items(h, best_tx, best_th);
+    return set_sched(h, best_sc);
 }
 
 }  // namespace
@@ -423,12 +524,11 @@ lb_status lb_create(const lb_config* cfg, void* dev_ws, uint64_t ws_bytes, void*
     if (hipMemcpyAsync(h->d_items64, it64.data(), it64.size() * sizeof(WorkItem),
                        hipMemcpyHostToDevice, h->s) != hipSuccess)
         return fail(LB_E_HIP);
-    int tx, th;
-    default_tile(cfg->nx, cfg->ny, tx, th);
-    if (cfg->tile_x) tx = cfg->tile_x;
-    if (cfg->tile_h) th = cfg->tile_h;
+    Sched sc = default_sched(cfg->nx, cfg->ny);
+    if (cfg->tile_x) sc.tx = cfg->tile_x;
+    if (cfg->tile_h) sc.th = cfg->tile_h;
     h->tuned = (cfg->tile_x != 0 && cfg->tile_h != 0) || (int64_t)cfg->nx * cfg->ny < (1 << 16);
-    st = set_items(h, tx, th);
+    st = set_sched(h, sc);
     if (st != LB_OK) return fail(st);
     *out = h;
     return LB_OK;
@@ -637,10 +737,11 @@ lb_status lb_timing_read(lb_handle* h, double* ms_per_step, int64_t* steps) {
     return LB_OK;
 }
 
-lb_status lb_get_tile(lb_handle* h, int32_t* tile_x, int32_t* tile_h) {
-    if (!h || !tile_x || !tile_h) return LB_E_INVALID_ARG;
-    *tile_x = h->tx;
-    *tile_h = h->th;
+lb_status lb_get_schedule(lb_handle* h, int32_t* tile_x, int32_t* rows, int32_t* grid) {
+    if (!h || !tile_x || !rows || !grid) return LB_E_INVALID_ARG;
+    *tile_x = h->sc.tx;
+    *rows = h->sc.rows;
+    *grid = h->sc.mode == 1 ? h->sc.grid : 0;
     return LB_OK;
 }
 
@@ -691,9 +792,8 @@ struct lb_batch {
     std::vector<BatchSlot> slot;
     int64_t gstep = 0;
     int parity = 0;
-    int tx = 64, th = 64;
+    Sched sc;
     bool fixed_tile = false;
-    int grid = 0;
     bool dirty = true;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     int glen = 16;
@@ -712,8 +812,8 @@ struct BatchLayout {
 BatchLayout batch_layout(int32_t slots, int64_t cap, int prec) {
     BatchLayout L;
     const int sb = store_bytes(prec);
-    L.max_items = (int)std::min<int64_t>((int64_t)1 << 30, cap / 64 + 4 * (int64_t)slots);
-    L.max_items64 = (int)std::min<int64_t>((int64_t)1 << 30, cap / 256 + 4 * (int64_t)slots);
+    L.max_items = (int)std::min<int64_t>((int64_t)1 << 30, cap / 32 + 4 * (int64_t)slots + 3 * kMaxGrid);
+    L.max_items64 = (int)std::min<int64_t>((int64_t)1 << 30, cap / 128 + 4 * (int64_t)slots);
     L.max_ny = (int)std::min<int64_t>(cap / 8, 1 << 20);
     uint64_t o = 0;
     L.descs = o; o += align_up((uint64_t)slots * sizeof(LatDesc));
@@ -764,50 +864,45 @@ void batch_drop_graphs(lb_batch* b) {
         if (b->gexec[p]) { (void)hipGraphExecDestroy(b->gexec[p]); b->gexec[p] = nullptr; }
 }
 
-int persistent_grid(int prec, int tx) {
-    // enough resident workgroups to fill every CU twice over
-    (void)prec;
-    const int per_cu = tx == 64 ? 8 : (tx == 128 ? 4 : 2);
-    return cu_count() * per_cu;
+std::vector<LatShape> batch_shapes(lb_batch* b) {
+    std::vector<LatShape> lats;
+    for (int i = 0; i < b->nslots; ++i)
+        if (b->slot[i].used) lats.push_back({i, b->slot[i].cfg.nx, b->slot[i].cfg.ny});
+    return lats;
 }
 
-lb_status batch_rebuild(lb_batch* b, int tx, int th, int grid_mode) {
+lb_status batch_set_sched(lb_batch* b, Sched sc) {
     std::vector<WorkItem> items;
-    for (int i = 0; i < b->nslots; ++i)
-        if (b->slot[i].used) build_items(i, b->slot[i].cfg.nx, b->slot[i].cfg.ny, tx, th, items);
-    if ((int)items.size() > b->max_items) return LB_E_WORKSPACE;
-    int grid = (int)items.size();
-    if (grid_mode == 1) grid = std::min(grid, persistent_grid(b->prec, tx));
-    xcd_permute(items, grid);
+    if (!build_schedule(batch_shapes(b), b->prec, sc, b->max_items, items)) return LB_E_WORKSPACE;
     if (!items.empty())
         HIPC(hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(WorkItem),
                             hipMemcpyHostToDevice, b->s));
     HIPC(hipStreamSynchronize(b->s));
-    b->n_items = (int)items.size();
-    b->grid = grid;
-    b->tx = tx;
-    b->th = th;
+    b->n_items = sc.n_items;
+    b->sc = sc;
     batch_drop_graphs(b);
     return LB_OK;
 }
 
 lb_status batch_autotune(lb_batch* b) {
-    int best_tx = b->tx, best_th = b->th, best_mode = 0;
+    std::vector<LatShape> lats = batch_shapes(b);
+    if (lats.empty()) return batch_set_sched(b, b->sc);
+    int min_nx = 1 << 30;
+    int max_ny = 0;
+    for (auto& l : lats) { min_nx = std::min(min_nx, l.nx); max_ny = std::max(max_ny, l.ny); }
+    Sched best_sc = b->sc;
     double best = 1e30;
-    for (int tx : {64, 128}) {
-        for (int th : {16, 32, 64, 128}) {
-            for (int mode : {0, 1}) {
-                lb_status st = batch_rebuild(b, tx, th, mode);
-                if (st == LB_E_WORKSPACE) continue;
-                if (st != LB_OK) return st;
-                if (b->n_items == 0) return LB_OK;
-                const double ms = time_candidate(b->prec, tx, b->d_descs, b->d_items, b->n_items,
-                                                 b->grid, b->parity, b->s, 3);
-                if (ms < best) { best = ms; best_tx = tx; best_th = th; best_mode = mode; }
-            }
-        }
+    for (Sched sc : candidates(min_nx, max_ny)) {
+        if (sc.tx > 128) continue;
+        std::vector<WorkItem> items;
+        if (!build_schedule(lats, b->prec, sc, b->max_items, items)) continue;
+        HIPC(hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(WorkItem),
+                            hipMemcpyHostToDevice, b->s));
+        const double ms = time_candidate(b->prec, sc.tx, b->d_descs, b->d_items, sc.n_items, sc.grid,
+                                         b->parity, b->s, 3);
+        if (ms < best) { best = ms; best_sc = sc; }
     }
-    return batch_rebuild(b, best_tx, best_th, best_mode);
+    return batch_set_sched(b, best_sc);
 }
 
 lb_status batch_graph(lb_batch* b, int parity, hipGraphExec_t* out) {
@@ -818,7 +913,7 @@ lb_status batch_graph(lb_batch* b, int parity, hipGraphExec_t* out) {
         hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         int p = parity;
         for (int i = 0; i < b->glen && e == hipSuccess; ++i) {
-            e = launch_step(b->prec, b->tx, b->d_descs, b->d_items, b->n_items, b->grid, p, cs);
+            e = launch_step(b->prec, b->sc.tx, b->d_descs, b->d_items, b->n_items, b->sc.grid, p, cs);
             p ^= 1;
         }
         hipError_t e2 = hipStreamEndCapture(cs, &g);
@@ -893,8 +988,9 @@ lb_status lb_batch_create(int32_t slots, int64_t node_capacity, int32_t precisio
     b->free_list.push_back({0, b->pool_bytes});
     b->slot.resize(slots);
     b->fixed_tile = tile_x != 0 && tile_h != 0;
-    b->tx = tile_x ? tile_x : 64;
-    b->th = tile_h ? tile_h : 64;
+    b->sc.tx = tile_x ? tile_x : 64;
+    b->sc.th = tile_h ? tile_h : 64;
+    b->sc.mode = 0;
     if (hipEventCreate(&b->t0) != hipSuccess || hipEventCreate(&b->t1) != hipSuccess) {
         lb_batch_destroy(b);
         return LB_E_HIP;
@@ -957,7 +1053,7 @@ lb_status lb_batch_remove(lb_batch* b, int32_t slot) {
 lb_status lb_batch_step(lb_batch* b, int64_t n, int32_t use_graph) {
     if (!b || n < 0) return LB_E_INVALID_ARG;
     if (b->dirty) {
-        lb_status st = b->fixed_tile ? batch_rebuild(b, b->tx, b->th, 1) : batch_autotune(b);
+        lb_status st = b->fixed_tile ? batch_set_sched(b, b->sc) : batch_autotune(b);
         if (st != LB_OK) return st;
         b->dirty = false;
     }
@@ -975,7 +1071,7 @@ lb_status lb_batch_step(lb_batch* b, int64_t n, int32_t use_graph) {
             left -= reps * b->glen;  // glen is even: parity unchanged
         }
         for (int64_t i = 0; i < left; ++i) {
-            HIPC(launch_step(b->prec, b->tx, b->d_descs, b->d_items, b->n_items, b->grid, b->parity, b->s));
+            HIPC(launch_step(b->prec, b->sc.tx, b->d_descs, b->d_items, b->n_items, b->sc.grid, b->parity, b->s));
             b->parity ^= 1;
         }
     } else if (n & 1) {

@@ -7,16 +7,18 @@
 // POST-COLLISION values of the previous step; the kernel pulls them
 // (f_a(x) = f~_a(x - e_a)), so streaming costs nothing extra.
 //
-// One workgroup owns a strip of TX columns and a run of rows of one lattice
-// (a work item) and marches upward one row per iteration, one node per lane:
-//   A  pull f at the leading row L           -> phi(L)      (LDS ring, halo 2)
-//   B  pull gbar at row L-1                  -> pbar(L-1)   (LDS ring, halo 1)
-//   D  grad phi, |grad phi|^2, n (or mu_phi) at row L-1     (LDS ring, halo 1)
-//   F  collide row L-2: div n (or grad mu), forces, u, p, both cascaded
-//      collisions, store the 18 post-collision values
+// One workgroup of TX lanes owns a strip of TX - 4 columns and a run of rows of
+// one lattice (a work item); lane t sits on column x0 - 2 + t, so the two halo
+// columns on each side are ordinary lanes.  The workgroup marches upward one
+// row per iteration:
+//   A  every lane: pull f at the leading row L        -> phi(L)    (LDS ring)
+//   B  lanes 1..w+2: pull gbar at row L-1             -> pbar(L-1) (LDS ring)
+//   D  lanes 1..w+2: grad phi, n (or mu_phi) at row L-1           (LDS ring)
+//   F  lanes 2..w+1: collide row L-2: div n (or grad mu), forces, u, p, both
+//      cascaded collisions, store the 18 post-collision values
 // The pulled f and gbar of a lane stay in registers until their row is
-// collided, so each stored value is read from HBM once per step; the halo
-// columns are recomputed by four helper lanes.
+// collided, so each stored value is read from HBM once per step (halo columns
+// and the rows shared by neighbouring work items come from L2 / MALL).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -99,41 +101,56 @@ __device__ __forceinline__ int map_row(int L, int ny, int wall) {
     return L < 0 ? L + ny : (L >= ny ? L - ny : L);
 }
 
+// Element access through a uniform plane base and a 32-bit byte offset (every
+// plane is < 4 GiB), so addresses are one VALU add on top of a scalar base.
+template <class ST>
+__device__ __forceinline__ typename ST::R ldo(const typename ST::T* plane, uint32_t e) {
+    using T = typename ST::T;
+    return ST::ld(*reinterpret_cast<const T*>(reinterpret_cast<const char*>(plane) +
+                                              e * (uint32_t)sizeof(T)));
+}
+template <class ST>
+__device__ __forceinline__ void sto(typename ST::T* plane, uint32_t e, typename ST::R v) {
+    using T = typename ST::T;
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(plane) + e * (uint32_t)sizeof(T)) = ST::st(v);
+}
+
 // Pull the nine values arriving at (x, r): f_a(x, r) = f~_a(x - e_a); a source
 // beyond a halfway wall is replaced by the opposite direction at the same node.
+// base points at plane 0 of the nine (f or gbar); xm, xp are the periodic
+// neighbours of x.
 template <class ST>
 __device__ __forceinline__ void pull9(const typename ST::T* __restrict__ base, int64_t P, int nx,
-                                      int ny, int wall, int x, int r, typename ST::R sh,
-                                      typename ST::R out[9]) {
+                                      int ny, int wall, int x, int xm, int xp, int r,
+                                      typename ST::R sh, typename ST::R out[9]) {
     using R = typename ST::R;
-    const int xm = x == 0 ? nx - 1 : x - 1;
-    const int xp = x == nx - 1 ? 0 : x + 1;
     const bool bot = wall && r == 0;       // sources of 2, 5, 6 lie below the wall
     const bool top = wall && r == ny - 1;  // sources of 4, 7, 8 lie above the wall
     const int rb = r == 0 ? ny - 1 : r - 1;
     const int rt = r == ny - 1 ? 0 : r + 1;
-    const int64_t o = (int64_t)r * nx, ob = (int64_t)rb * nx, ot = (int64_t)rt * nx;
+    const uint32_t o = (uint32_t)r * (uint32_t)nx, ob = (uint32_t)rb * (uint32_t)nx,
+                   ot = (uint32_t)rt * (uint32_t)nx;
     const R w0 = R(4.0 / 9.0) * sh, w1 = R(1.0 / 9.0) * sh, w5 = R(1.0 / 36.0) * sh;
-    out[0] = ST::ld(base[0 * P + o + x]) + w0;
-    out[1] = ST::ld(base[1 * P + o + xm]) + w1;
-    out[3] = ST::ld(base[3 * P + o + xp]) + w1;
+    out[0] = ldo<ST>(base, o + x) + w0;
+    out[1] = ldo<ST>(base + P, o + xm) + w1;
+    out[3] = ldo<ST>(base + 3 * P, o + xp) + w1;
     if (!bot) {
-        out[2] = ST::ld(base[2 * P + ob + x]) + w1;
-        out[5] = ST::ld(base[5 * P + ob + xm]) + w5;
-        out[6] = ST::ld(base[6 * P + ob + xp]) + w5;
+        out[2] = ldo<ST>(base + 2 * P, ob + x) + w1;
+        out[5] = ldo<ST>(base + 5 * P, ob + xm) + w5;
+        out[6] = ldo<ST>(base + 6 * P, ob + xp) + w5;
     } else {
-        out[2] = ST::ld(base[4 * P + o + x]) + w1;
-        out[5] = ST::ld(base[7 * P + o + x]) + w5;
-        out[6] = ST::ld(base[8 * P + o + x]) + w5;
+        out[2] = ldo<ST>(base + 4 * P, o + x) + w1;
+        out[5] = ldo<ST>(base + 7 * P, o + x) + w5;
+        out[6] = ldo<ST>(base + 8 * P, o + x) + w5;
     }
     if (!top) {
-        out[4] = ST::ld(base[4 * P + ot + x]) + w1;
-        out[7] = ST::ld(base[7 * P + ot + xp]) + w5;
-        out[8] = ST::ld(base[8 * P + ot + xm]) + w5;
+        out[4] = ldo<ST>(base + 4 * P, ot + x) + w1;
+        out[7] = ldo<ST>(base + 7 * P, ot + xp) + w5;
+        out[8] = ldo<ST>(base + 8 * P, ot + xm) + w5;
     } else {
-        out[4] = ST::ld(base[2 * P + o + x]) + w1;
-        out[7] = ST::ld(base[5 * P + o + x]) + w5;
-        out[8] = ST::ld(base[6 * P + o + x]) + w5;
+        out[4] = ldo<ST>(base + 2 * P, o + x) + w1;
+        out[7] = ldo<ST>(base + 5 * P, o + x) + w5;
+        out[8] = ldo<ST>(base + 6 * P, o + x) + w5;
     }
 }
 
@@ -164,6 +181,39 @@ __device__ __forceinline__ R lap3x3(const R* s, const R* m, const R* n, int c) {
 
 // ------------------------------------------------------ per-node physics
 
+// Per-lattice constants in the compute type, loaded once per work item.
+template <class R>
+struct KConst {
+    R rhoB, dRho, muB, dMu, kt_a, kt_b, be_a, be_b, ka_a, ka_b, four_W, M, omphi, gx, gy, rho_ref,
+        shf, shg, c2dr;
+};
+
+template <class R>
+__device__ __forceinline__ KConst<R> load_const(const LatDesc& D) {
+    KConst<R> k;
+    k.rhoB = R(D.rhoB); k.dRho = R(D.dRho); k.muB = R(D.muB); k.dMu = R(D.dMu);
+    k.kt_a = R(D.kt_a); k.kt_b = R(D.kt_b); k.be_a = R(D.be_a); k.be_b = R(D.be_b);
+    k.ka_a = R(D.ka_a); k.ka_b = R(D.ka_b); k.four_W = R(D.four_W); k.M = R(D.M);
+    k.omphi = R(D.omphi); k.gx = R(D.gx); k.gy = R(D.gy); k.rho_ref = R(D.rho_ref);
+    k.shf = R(D.shift_f); k.shg = R(D.shift_g); k.c2dr = R(D.dRho * (1.0 / 3.0));
+    return k;
+}
+
+// Reciprocal: correctly rounded in FP64, hardware v_rcp_f32 (1 ulp) in FP32.
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Unit normal from a gradient; zero where |grad phi| < 1e-12.
+__device__ __forceinline__ void unit_normal(double gx, double gy, double m2, double& nx, double& ny) {
+    const double m = sqrt(m2);
+    nx = 0.0; ny = 0.0;
+    if (!(m < 1e-12)) { const double im = 1.0 / m; nx = gx * im; ny = gy * im; }
+}
+__device__ __forceinline__ void unit_normal(float gx, float gy, float m2, float& nx, float& ny) {
+    nx = 0.0f; ny = 0.0f;
+    if (!(m2 < 1e-24f)) { const float im = __builtin_amdgcn_rsqf(m2); nx = gx * im; ny = gy * im; }
+}
+
 template <class R>
 struct NodeIn {
     R phi, pbar;
@@ -184,38 +234,36 @@ struct NodeOut {
 // surfacetensionthermodynamic, netgradientpressureforce, hydrodynamicfields,
 // fluidviscosity).
 template <class R>
-__device__ __forceinline__ NodeOut<R> node_macro(const LatDesc& D, const NodeIn<R>& in,
+__device__ __forceinline__ NodeOut<R> node_macro(const KConst<R>& K, int chem, const NodeIn<R>& in,
                                                  const R g[9]) {
     NodeOut<R> o;
-    const R rho = R(D.rhoB) + in.phi * R(D.dRho);
-    const R mu = R(D.muB) + in.phi * R(D.dMu);
+    const R rho = K.rhoB + in.phi * K.dRho;
+    const R mu = K.muB + in.phi * K.dMu;
     const R den = R(0.5) * rho + R(3) * mu;  // rho (1/omega_nu) with nu = mu / rho
-    const R rr = R(1) / (rho * den);
+    const R rr = rcp(rho * den);
     const R inv_rho = den * rr;
     o.rho = rho;
     o.omv = rho * rho * rr;
     R Fsx, Fsy;
-    if (D.st_form == 0) {
-        const R kt = R(D.kt_a) + R(D.kt_b) * in.y;
-        const R dkt = R(D.kt_b);
+    if (!chem) {
+        const R kt = K.kt_a + K.kt_b * in.y;
         const R a = in.m2 * kt * in.divn;
-        const R b = in.m2 * dkt;
+        const R b = in.m2 * K.kt_b;
         Fsx = -a * in.nx - b * in.nx * in.ny;
         Fsy = -a * in.ny + b * (R(1) - in.ny * in.ny);
     } else {
         Fsx = -in.phi * in.dmux;
         Fsy = -in.phi * in.dmuy;
     }
-    const R bf = rho - R(D.rho_ref);
-    o.Ftx = Fsx + bf * R(D.gx);
-    o.Fty = Fsy + bf * R(D.gy);
+    const R bf = rho - K.rho_ref;
+    o.Ftx = Fsx + bf * K.gx;
+    o.Fty = Fsy + bf * K.gy;
     const R jx = (g[1] - g[3]) + (g[5] - g[6]) + (g[8] - g[7]);
     const R jy = (g[2] - g[4]) + (g[5] + g[6]) - (g[7] + g[8]);
     o.ux = (R(3) * jx + R(0.5) * o.Ftx) * inv_rho;
     o.uy = (R(3) * jy + R(0.5) * o.Fty) * inv_rho;
-    const R c2dr = R(D.dRho) * R(1.0 / 3.0);
-    o.Fpx = -in.dpx + c2dr * in.dphx;
-    o.Fpy = -in.dpy + c2dr * in.dphy;
+    o.Fpx = -in.dpx + K.c2dr * in.dphx;
+    o.Fpy = -in.dpy + K.c2dr * in.dphy;
     o.p = in.pbar + R(0.5) * (o.Fpx * o.ux + o.Fpy * o.uy);
     o.psi = o.p - rho * R(1.0 / 3.0);
     return o;
@@ -275,7 +323,9 @@ __device__ __forceinline__ void hydro_collide(R g[9], const NodeOut<R>& o) {
                             o.rho * ux * uy2 - ux * uy2 * p) -
                  ux * (R(1.5) * h3 - R(0.5) * h4) - R(2) * uy * h5;
     const R ux2uy2 = ux2 * uy2;
-    const R h8 = R(0.25) * (o.rho * R(1.0 / 27.0) + psi * (third + ux2) * (third + uy2) - e22 +
+    // c^6 rho + psi (c^2 + ux^2)(c^2 + uy^2) written without its O(rho) cancellation
+    const R eq22 = p * (third + ux2) * (third + uy2) - rc2 * (third * (ux2 + uy2) + ux2 * uy2);
+    const R h8 = R(0.25) * (eq22 - e22 +
                             R(2) * (uy * e21 + ux * e12) - (uy2 * e20 + ux2 * e02) -
                             R(4) * uxy * e11 + R(4.0 / 3.0) * o.rho * ux2uy2 - ux2uy2 * p) -
                  R(2) * h3 - R(0.5) * uy2 * (R(3) * h3 + h4) - R(0.5) * ux2 * (R(3) * h3 - h4) -
@@ -341,41 +391,35 @@ __global__ void __launch_bounds__(TX) lb_fused(const LatDesc* __restrict__ descs
                                                int parity) {
     using R = typename ST::R;
     using T = typename ST::T;
-    constexpr int LW = TX + 4;
-    __shared__ R s_phi[4][LW];
-    __shared__ R s_pb[4][LW];
-    __shared__ R s_na[4][LW];  // n_x (geometric) or mu_phi (chemical potential)
-    __shared__ R s_nb[4][LW];  // n_y (geometric)
+    __shared__ R s_phi[4][TX];
+    __shared__ R s_pb[4][TX];
+    __shared__ R s_na[4][TX];  // n_x (geometric) or mu_phi (chemical potential)
+    __shared__ R s_nb[4][TX];  // n_y (geometric)
     const int t = threadIdx.x;
 
     for (int wi = blockIdx.x; wi < n_items; wi += gridDim.x) {
         const WorkItem it = items[wi];
+        if (it.y1 <= it.y0) continue;  // padding item (uniform over the block)
         const LatDesc& D = descs[it.inst];
         const int nx = D.nx, ny = D.ny, wall = D.wall_y, chem = D.st_form;
         const int64_t P = D.plane;
+        const KConst<R> K = load_const<R>(D);
         const T* __restrict__ src = reinterpret_cast<const T*>(D.buf[parity]);
         T* __restrict__ dst = reinterpret_cast<T*>(D.buf[parity ^ 1]);
         const T* __restrict__ srcg = src + 9 * P;
         T* __restrict__ dstg = dst + 9 * P;
-        const R shf = R(D.shift_f), shg = R(D.shift_g);
-        const int x0 = it.x0;
-        const int wdt = min(TX, nx - x0);
-        const bool act = t < wdt;
-        const int x = x0 + (act ? t : 0);
-        const int c = t + 2;
-        // helper lanes: phi at the two halo columns on each side; pbar / n at one
-        int hcell = -1, hx = 0;
-        if (t == 0) { hcell = 0; hx = x0 - 2; }
-        else if (t == 1) { hcell = 1; hx = x0 - 1; }
-        else if (t == TX - 2) { hcell = wdt + 2; hx = x0 + wdt; }
-        else if (t == TX - 1) { hcell = wdt + 3; hx = x0 + wdt + 1; }
-        hx = ((hx % nx) + nx) % nx;
-        const bool hphi = hcell >= 0;
-        const bool hn = hcell == 1 || hcell == wdt + 2;  // pbar and n halo cells
+        const int w = min(TX - 4, nx - it.x0);  // interior columns of this strip
+        const bool inA = t < w + 4;              // phi cells
+        const bool inB = t >= 1 && t < w + 3;    // pbar and normal cells
+        const bool inF = t >= 2 && t < w + 2;    // collided cells
+        int xc = it.x0 - 2 + t;                  // this lane's column (halo lanes wrap)
+        xc = xc < 0 ? xc + nx : (xc >= nx ? xc - nx : xc);
+        const int xm = xc == 0 ? nx - 1 : xc - 1;
+        const int xp = xc == nx - 1 ? 0 : xc + 1;
 
         R f0[9], f1[9], f2[9], g0[9], g1[9];
-        R cdx = 0, cdy = 0, cm2 = 0, cnx = 0, cny = 0;  // centre grad/normal at row L-1
-        R pdx = 0, pdy = 0, pm2 = 0, pnx = 0, pny = 0;  // same, one row below (row L-2)
+        R cdx = 0, cdy = 0, cm2 = 0, cnx = 0, cny = 0;  // grad / normal at row L-1
+        R pdx = 0, pdy = 0, pm2 = 0, pnx = 0, pny = 0;  // the same one row below
 #pragma unroll
         for (int a = 0; a < 9; ++a) { f0[a] = f1[a] = f2[a] = g0[a] = g1[a] = R(0); }
 
@@ -383,113 +427,76 @@ __global__ void __launch_bounds__(TX) lb_fused(const LatDesc* __restrict__ descs
         for (int k = 0; k < H + 4; ++k) {
             const int L = it.y0 - 2 + k;
             // ---- A: phi at the leading row
-            {
-                const int Lr = map_row(L, ny, wall);
-                R* sp = s_phi[L & 3];
-                if (act) {
-                    pull9<ST>(src, P, nx, ny, wall, x, Lr, shf, f0);
-                    sp[c] = sum9(f0);
-                }
-                if (hphi) {
-                    R tmp[9];
-                    pull9<ST>(src, P, nx, ny, wall, hx, Lr, shf, tmp);
-                    sp[hcell] = sum9(tmp);
-                }
+            if (inA) {
+                pull9<ST>(src, P, nx, ny, wall, xc, xm, xp, map_row(L, ny, wall), K.shf, f0);
+                s_phi[L & 3][t] = sum9(f0);
             }
             // ---- B: pbar one row behind
-            if (k >= 2) {
+            if (k >= 2 && inB) {
                 const int Lg = L - 1;
-                const int Lgr = map_row(Lg, ny, wall);
-                R* sp = s_pb[Lg & 3];
-                if (act) {
-                    pull9<ST>(srcg, P, nx, ny, wall, x, Lgr, shg, g0);
-                    sp[c] = sum9(g0);
-                }
-                if (hn) {
-                    R tmp[9];
-                    pull9<ST>(srcg, P, nx, ny, wall, hx, Lgr, shg, tmp);
-                    sp[hcell] = sum9(tmp);
-                }
+                pull9<ST>(srcg, P, nx, ny, wall, xc, xm, xp, map_row(Lg, ny, wall), K.shg, g0);
+                s_pb[Lg & 3][t] = sum9(g0);
             }
             __syncthreads();
             // ---- D: gradient, normal or chemical potential at row L-1
-            if (k >= 2) {
+            if (k >= 2 && inB) {
                 const int Ln = L - 1;
                 const R* rs = s_phi[(Ln - 1) & 3];
                 const R* rm = s_phi[Ln & 3];
                 const R* rn = s_phi[(Ln + 1) & 3];
-                R* na = s_na[Ln & 3];
-                R* nb = s_nb[Ln & 3];
-                R yrow = R(0);
-                if (chem) yrow = R(map_row(Ln, ny, wall));
-#pragma unroll
-                for (int pass = 0; pass < 2; ++pass) {
-                    const bool on = pass == 0 ? act : hn;
-                    const int cc = pass == 0 ? c : hcell;
-                    if (on) {
-                        R gx, gy;
-                        grad3x3(rs, rm, rn, cc, gx, gy);
-                        const R m2 = gx * gx + gy * gy;
-                        // unit normal; zero where |grad phi| < 1e-12
-                        const R m = sqrt(m2);
-                        R ix = R(0), iy = R(0);
-                        if (!(m < R(1e-12))) {
-                            const R im = R(1) / m;
-                            ix = gx * im;
-                            iy = gy * im;
-                        }
-                        if (chem) {
-                            const R ph = rm[cc];
-                            const R beta = R(D.be_a) + R(D.be_b) * yrow;
-                            const R kap = R(D.ka_a) + R(D.ka_b) * yrow;
-                            na[cc] = R(4) * beta * (ph - R(1)) * ph * (ph - R(0.5)) -
-                                     kap * lap3x3(rs, rm, rn, cc);
-                        } else {
-                            na[cc] = ix;
-                            nb[cc] = iy;
-                        }
-                        if (pass == 0) { cdx = gx; cdy = gy; cm2 = m2; cnx = ix; cny = iy; }
-                    }
+                R gx, gy;
+                grad3x3(rs, rm, rn, t, gx, gy);
+                const R m2 = gx * gx + gy * gy;
+                R ix, iy;
+                unit_normal(gx, gy, m2, ix, iy);
+                if (chem) {
+                    const R yrow = R(map_row(Ln, ny, wall));
+                    const R ph = rm[t];
+                    const R beta = K.be_a + K.be_b * yrow;
+                    const R kap = K.ka_a + K.ka_b * yrow;
+                    s_na[Ln & 3][t] = R(4) * beta * (ph - R(1)) * ph * (ph - R(0.5)) -
+                                      kap * lap3x3(rs, rm, rn, t);
+                } else {
+                    s_na[Ln & 3][t] = ix;
+                    s_nb[Ln & 3][t] = iy;
                 }
+                cdx = gx; cdy = gy; cm2 = m2; cnx = ix; cny = iy;
             }
             __syncthreads();
             // ---- F: collide row C = L - 2
-            if (k >= 4 && act) {
+            if (k >= 4 && inF) {
                 const int C = L - 2;
                 NodeIn<R> in;
-                in.phi = s_phi[C & 3][c];
-                in.pbar = s_pb[C & 3][c];
+                in.phi = s_phi[C & 3][t];
+                in.pbar = s_pb[C & 3][t];
                 in.dphx = pdx; in.dphy = pdy; in.m2 = pm2; in.nx = pnx; in.ny = pny;
                 in.y = R(C);
                 in.divn = R(0); in.dmux = R(0); in.dmuy = R(0);
-                {
-                    R gx, gy;
-                    grad3x3(s_pb[(C - 1) & 3], s_pb[C & 3], s_pb[(C + 1) & 3], c, gx, gy);
-                    in.dpx = gx; in.dpy = gy;
-                }
+                grad3x3(s_pb[(C - 1) & 3], s_pb[C & 3], s_pb[(C + 1) & 3], t, in.dpx, in.dpy);
                 if (chem) {
-                    R gx, gy;
-                    grad3x3(s_na[(C - 1) & 3], s_na[C & 3], s_na[(C + 1) & 3], c, gx, gy);
-                    in.dmux = gx; in.dmuy = gy;
+                    grad3x3(s_na[(C - 1) & 3], s_na[C & 3], s_na[(C + 1) & 3], t, in.dmux, in.dmuy);
                 } else {
                     R a1, a2, b1, b2;
-                    grad3x3(s_na[(C - 1) & 3], s_na[C & 3], s_na[(C + 1) & 3], c, a1, a2);
-                    grad3x3(s_nb[(C - 1) & 3], s_nb[C & 3], s_nb[(C + 1) & 3], c, b1, b2);
+                    grad3x3(s_na[(C - 1) & 3], s_na[C & 3], s_na[(C + 1) & 3], t, a1, a2);
+                    grad3x3(s_nb[(C - 1) & 3], s_nb[C & 3], s_nb[(C + 1) & 3], t, b1, b2);
                     in.divn = a1 + b2;
                 }
-                const NodeOut<R> o = node_macro<R>(D, in, g1);
-                const int64_t idx = (int64_t)C * nx + x;
+                const NodeOut<R> o = node_macro<R>(K, chem, in, g1);
+                const uint32_t idx = (uint32_t)C * (uint32_t)nx + (uint32_t)xc;
                 if constexpr (MODE == MODE_STEP) {
-                    hydro_collide<R>(g1, o);
-                    const R th = R(D.four_W) * in.phi * (R(1) - in.phi);
-                    const R Mth = R(D.M) * th;
-                    ace_collide<R>(f2, in.phi, o.ux, o.uy, Mth * in.nx, Mth * in.ny, R(D.omphi));
+                    const R Mth = K.M * (K.four_W * in.phi * (R(1) - in.phi));
+                    ace_collide<R>(f2, in.phi, o.ux, o.uy, Mth * in.nx, Mth * in.ny, K.omphi);
                     const R w0 = R(4.0 / 9.0), w1 = R(1.0 / 9.0), w5 = R(1.0 / 36.0);
 #pragma unroll
                     for (int a = 0; a < 9; ++a) {
                         const R wa = a == 0 ? w0 : (a < 5 ? w1 : w5);
-                        dst[a * P + idx] = ST::st(f2[a] - wa * shf);
-                        dstg[a * P + idx] = ST::st(g1[a] - wa * shg);
+                        sto<ST>(dst + a * P, idx, f2[a] - wa * K.shf);
+                    }
+                    hydro_collide<R>(g1, o);
+#pragma unroll
+                    for (int a = 0; a < 9; ++a) {
+                        const R wa = a == 0 ? w0 : (a < 5 ? w1 : w5);
+                        sto<ST>(dstg + a * P, idx, g1[a] - wa * K.shg);
                     }
                 } else if constexpr (MODE == MODE_FIELDS) {
                     double* F = D.fields;

@@ -18,5 +18,7 @@ hipError_t launch_state_op(int prec, int op, const LatDesc* d, double* plane, in
 hipError_t launch_diag(const LatDesc* d, const double* fields, double* part, double* out, int ny,
                        double step, double u_max, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, uint64_t n, hipStream_t s);
+// Resident workgroups per CU of the fused step kernel (from the HIP occupancy API).
+int fused_occupancy(int prec, int tx);
 
 }  // namespace cmlb

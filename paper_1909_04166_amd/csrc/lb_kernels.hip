@@ -30,6 +30,28 @@ hipError_t launch_step(int prec, int tx, const LatDesc* d, const WorkItem* items
     return hipErrorInvalidValue;
 }
 
+template <class ST>
+static int occ_tx(int tx) {
+    int nb = 0;
+    hipError_t e = hipErrorInvalidValue;
+    switch (tx) {
+    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lb_fused<ST, 64, MODE_STEP>, 64, 0); break;
+    case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lb_fused<ST, 128, MODE_STEP>, 128, 0); break;
+    case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lb_fused<ST, 256, MODE_STEP>, 256, 0); break;
+    }
+    return e == hipSuccess ? nb : 1;
+}
+
+int fused_occupancy(int prec, int tx) {
+    switch (prec) {
+    case LB_FP64: return occ_tx<StF64>(tx);
+    case LB_FP32: return occ_tx<StF32>(tx);
+    case LB_FP32_F16: return occ_tx<StF16>(tx);
+    case LB_FP32_BF16: return occ_tx<StBF16>(tx);
+    }
+    return 1;
+}
+
 // Fields / coupling extraction always runs with 64-wide strips.
 hipError_t launch_extract(int prec, int mode, const LatDesc* d, const WorkItem* items64,
                           int n_items, int parity, hipStream_t s) {

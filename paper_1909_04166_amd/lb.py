@@ -97,7 +97,7 @@ _SIGS = {
     "lb_timing_read": ([_vp, _dp, _i64p], ctypes.c_int32),
     "lb_batch_timing_enable": ([_vp, ctypes.c_int32], ctypes.c_int32),
     "lb_batch_timing_read": ([_vp, _dp, _i64p], ctypes.c_int32),
-    "lb_get_tile": ([_vp, _i32p, _i32p], ctypes.c_int32),
+    "lb_get_schedule": ([_vp, _i32p, _i32p, _i32p], ctypes.c_int32),
     "lb_struct_sizes": ([_u64p, _u64p], ctypes.c_int32),
     "lb_copy_kernel": ([_vp, _vp, ctypes.c_uint64, _vp], ctypes.c_int32),
 }
@@ -252,10 +252,11 @@ def lb_timing_read(h: int) -> tuple[float, int]:
     return float(ms.value), int(n.value)
 
 
-def lb_get_tile(h: int) -> tuple[int, int]:
-    a, b = ctypes.c_int32(), ctypes.c_int32()
-    _check("lb_get_tile", lib().lb_get_tile(_vp(h), ctypes.byref(a), ctypes.byref(b)))
-    return int(a.value), int(b.value)
+def lb_get_schedule(h: int) -> tuple[int, int, int]:
+    """(workgroup width, rows per item or segment, persistent grid or 0)."""
+    a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check("lb_get_schedule", lib().lb_get_schedule(_vp(h), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return int(a.value), int(b.value), int(c.value)
 
 
 def lb_copy_kernel(dst: int, src: int, n: int, stream: int) -> None:
@@ -408,4 +409,4 @@ class Lattice:
 
     @property
     def tile(self):
-        return lb_get_tile(self.h)
+        return lb_get_schedule(self.h)
