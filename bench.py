@@ -74,6 +74,57 @@ def time_lattice(case, phi0, precision, steps, warmup, tile=(0, 0)):
     return dict(wall_s=t1 - t0, ms_kernel=ms_kernel, rc=rc, diag=d, tile=tile_used)
 
 
+def bench_batched(precision: str, steps: int, n: int = 256, seed: int = 20190909):
+    """Uneven batch: n independent droplet / Rayleigh-Taylor lattices, sides in
+    [64, 512], density ratio log-uniform in [3, 1000]; one persistent launch per
+    step, graph replay."""
+    import torch
+    inst = W.batch_instances(n, seed)
+    nodes = sum(c["nx"] * c["ny"] for _, c, _ in inst)
+    B = lb.Batch(n, nodes + 64 * n, precision)
+    for _, c, p in inst:
+        B.add(c, p)
+    B.step(10)  # autotune + warm-up
+    torch.cuda.synchronize()
+    lb.lb_batch_timing_enable(B.b, True)
+    t0 = time.perf_counter()
+    B.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms, _ = lb.lb_batch_timing_read(B.b)
+    unstable = sum(1 for s in range(n) if B.diagnostics(s)["nan_flag"] != 0.0)
+    B.close()
+    return {"MLUPS": round(nodes * steps / wall / 1e6, 1), "nodes": nodes, "instances": n,
+            "steps": steps, "kernel_ms": round(ms, 4),
+            "kernel_GBs": round(36 * STORE[precision] * nodes / (ms * 1e-3) / 1e9, 1),
+            "unstable_instances": unstable}
+
+
+def bench_served(precision: str, n_req: int, rate: float, budget_gb: float = 24.0, seed: int = 5):
+    """Poisson arrivals of elliptic-drop solves (sides log-uniform in [64, 1024],
+    500-20000 steps, aspect 1.1-1.5, ratio 1000, W 5), continuous batching."""
+    from paper_1909_04166_amd import serve
+    trace = W.serve_arrivals(n_req, seed, rate)
+    reqs = []
+    for i, a in enumerate(trace):
+        case, _ = W.ellipse(8, a["aspect"])  # parameters only; the field is built at admission
+        case.update(nx=a["side"], ny=a["side"], W=5.0)
+        reqs.append(serve.Request(rid=i, case=case, phi0=None, steps=a["steps"], arrival=a["t"],
+                                  make=(lambda s=a["side"], r=a["aspect"]: W.ellipse(s, r, W=5.0)[1])))
+    per_node = 2 * 18 * STORE[precision] + 32
+    cap = int(budget_gb * 1e9 / per_node)
+    S = serve.Server(slots=512, node_capacity=cap, precision=precision, tick=128)
+    stats = S.run(reqs)
+    offered = sum(r.nodes * r.steps for r in reqs) / max(a["t"] for a in trace) / 1e9
+    S.close()
+    stats.update({"requests_offered": n_req, "rate_per_s": rate, "offered_GLUPS": round(offered, 1),
+                  "hbm_budget_GB": budget_gb, "unstable": stats["failed"]})
+    for k in ("MLUPS", "p50_s", "p99_s", "wall_s"):
+        if stats.get(k) is not None:
+            stats[k] = round(stats[k], 3)
+    return stats
+
+
 def cpu_baseline(target_s: float = 15.0):
     import oracle
     case, phi0 = W.droplet(128, 25.0, W=5.0)
@@ -102,6 +153,8 @@ def main():
     ap.add_argument("--tile", default="0,0")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--extra", action="store_true", help="also time the other precisions and workloads")
+    ap.add_argument("--batched", action="store_true", help="also time the uneven batch (256 lattices)")
+    ap.add_argument("--served", action="store_true", help="also run the served Poisson stream")
     ap.add_argument("--copy-ref", type=int, default=0, metavar="MIB",
                     help="only run the library's device copy kernel over MIB MiB (bandwidth and "
                          "counter reference) and print its GB/s")
@@ -186,6 +239,18 @@ def main():
                 extra[f"{wl}_{prec}"] = {"MLUPS": round(c2["nx"] * c2["ny"] * 2000 / rr["wall_s"] / 1e6, 1),
                                          "tile": list(rr["tile"])}
         out["extra"] = extra
+    if args.batched:
+        out["batched"] = {p: bench_batched(p, 5000) for p in ("fp16", "bf16", "fp32")}
+        for p, r in out["batched"].items():
+            r["vs_plain_fp64"] = round(r["MLUPS"] / out["value"], 3)
+    if args.served:
+        sat = bench_served("fp16", 500, 50.0)
+        cap_glups = max(sat["MLUPS"] / 1e3, 1e-3)
+        # a second stream at 70 % of the measured capacity, so latency is not pure queue growth
+        mean_work = 1.93e9
+        low = bench_served("fp16", 200, 0.7 * cap_glups * 1e9 / mean_work)
+        out["served"] = {"saturated": sat, "load_0.7": low,
+                         "vs_plain_fp64": round(sat["MLUPS"] / out["value"], 3)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -179,8 +179,9 @@ lb_status lb_batch_create(int32_t slots, int64_t node_capacity, int32_t precisio
                           void* stream, lb_batch** out);
 
 /* Places a lattice in a free slot and initializes it like lb_init_fields.
- * Returns the slot index in *slot.  Errors: LB_E_INVALID_ARG (bad config or
- * precision mismatch), LB_E_WORKSPACE (no free slot or not enough free nodes).
+ * Returns the slot index in *slot.  A slot holds at most min(node_capacity,
+ * 2^24) nodes.  Errors: LB_E_INVALID_ARG (bad config or precision mismatch),
+ * LB_E_WORKSPACE (no free slot, not enough free nodes, or lattice too large).
  * Synchronizes. */
 lb_status lb_batch_add(lb_batch* b, const lb_config* cfg, const double* phi0, int32_t* slot);
 
@@ -214,9 +215,11 @@ lb_status lb_batch_timing_read(lb_batch* b, double* ms_per_step, int64_t* steps)
 
 /* Schedule chosen for the handle (after autotuning when tile_x/tile_h were 0):
  * workgroup width tile_x (lanes; the strip is tile_x - 4 columns), rows per work
- * item (or per persistent segment), and the persistent grid size (0 when every
- * work item gets its own workgroup). */
-lb_status lb_get_schedule(lb_handle* h, int32_t* tile_x, int32_t* rows, int32_t* grid);
+ * item (or per persistent segment), the persistent grid size (0 when every work
+ * item gets its own workgroup) and whether the kernel variant that prefetches
+ * the next rows during the collision is used (1) or not (0). */
+lb_status lb_get_schedule(lb_handle* h, int32_t* tile_x, int32_t* rows, int32_t* grid,
+                          int32_t* prefetch);
 
 /* sizeof(lb_config) and sizeof(lb_diag) as compiled, for binding checks. */
 lb_status lb_struct_sizes(uint64_t* config_bytes, uint64_t* diag_bytes);

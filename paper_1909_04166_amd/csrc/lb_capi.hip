@@ -210,7 +210,7 @@ int cu_count() {
 //   mode 1: persistent grid of mult * (resident workgroups per CU) * CUs, each
 //           workgroup one balanced segment of the concatenated strip rows.
 struct Sched {
-    int tx = 64, th = 64, mode = 0, mult = 1;
+    int tx = 64, th = 64, mode = 0, mult = 1, pf = 0;
     int grid = 0, n_items = 0, rows = 0;
 };
 
@@ -224,7 +224,7 @@ bool build_schedule(const std::vector<LatShape>& lats, int prec, Sched& sc, int 
         sc.rows = sc.th;
         xcd_permute(items, sc.grid);
     } else {
-        int G = sc.mult * std::max(1, fused_occupancy(prec, sc.tx)) * cu_count();
+        int G = sc.mult * std::max(1, fused_occupancy(prec, sc.tx, sc.pf)) * cu_count();
         G = std::min(G, kMaxGrid);
         int nb = 0;
         if (!build_segments(lats, sc.tx, G, max_items, items, &nb)) return false;
@@ -344,7 +344,7 @@ lb_status set_sched(lb_handle* h, Sched sc) {
 
 lb_status launch_steps_eager(lb_handle* h, int64_t n) {
     for (int64_t i = 0; i < n; ++i) {
-        HIPC(launch_step(h->cfg.precision, h->sc.tx, h->d_desc, h->d_items, h->n_items, h->sc.grid,
+        HIPC(launch_step(h->cfg.precision, h->sc.tx, h->sc.pf, h->d_desc, h->d_items, h->n_items, h->sc.grid,
                          h->parity, h->s));
         h->parity ^= 1;
         h->step += 1;
@@ -361,7 +361,7 @@ lb_status graph_for(lb_handle* h, int parity, hipGraphExec_t* out) {
         hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         int p = parity;
         for (int i = 0; i < h->glen && e == hipSuccess; ++i) {
-            e = launch_step(h->cfg.precision, h->sc.tx, h->d_desc, h->d_items, h->n_items, h->sc.grid,
+            e = launch_step(h->cfg.precision, h->sc.tx, h->sc.pf, h->d_desc, h->d_items, h->n_items, h->sc.grid,
                             p, cs);
             p ^= 1;
         }
@@ -392,15 +392,15 @@ lb_status enqueue_diag(lb_handle* h) {
 
 // Times `reps` launches of one candidate without advancing the state (every
 // launch reads the current buffer and overwrites the other one).
-double time_candidate(int prec, int tx, const LatDesc* d, const WorkItem* items, int n, int grid,
+double time_candidate(int prec, int tx, int pf, const LatDesc* d, const WorkItem* items, int n, int grid,
                       int parity, hipStream_t s, int reps) {
     hipEvent_t a, b;
     if (hipEventCreate(&a) != hipSuccess) return 1e30;
     if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return 1e30; }
     double ms_out = 1e30;
-    bool ok = launch_step(prec, tx, d, items, n, grid, parity, s) == hipSuccess;
+    bool ok = launch_step(prec, tx, pf, d, items, n, grid, parity, s) == hipSuccess;
     ok = ok && hipEventRecord(a, s) == hipSuccess;
-    for (int i = 0; i < reps && ok; ++i) ok = launch_step(prec, tx, d, items, n, grid, parity, s) == hipSuccess;
+    for (int i = 0; i < reps && ok; ++i) ok = launch_step(prec, tx, pf, d, items, n, grid, parity, s) == hipSuccess;
     ok = ok && hipEventRecord(b, s) == hipSuccess && hipEventSynchronize(b) == hipSuccess;
     float ms = 0;
     if (ok && hipEventElapsedTime(&ms, a, b) == hipSuccess) ms_out = ms / reps;
@@ -412,20 +412,21 @@ double time_candidate(int prec, int tx, const LatDesc* d, const WorkItem* items,
 // Candidate schedules for one lattice shape.
 std::vector<Sched> candidates(int nx, int ny) {
     std::vector<Sched> out;
-    for (int tx : {64, 128, 256}) {
-        if (tx > 64 && nx <= strip_w(tx / 2)) continue;
-        for (int th : {16, 32, 64, 128, 256}) {
-            if (th > ny && th != 16) continue;
-            Sched sc;
-            sc.tx = tx; sc.th = th; sc.mode = 0;
-            out.push_back(sc);
+    for (int pf : {0, 1})
+        for (int tx : {64, 128, 256}) {
+            if (tx > 64 && nx <= strip_w(tx / 2)) continue;
+            for (int th : {16, 32, 64, 128, 256}) {
+                if (th > ny && th != 16) continue;
+                Sched sc;
+                sc.tx = tx; sc.th = th; sc.mode = 0; sc.pf = pf;
+                out.push_back(sc);
+            }
+            for (int m : {1, 2}) {
+                Sched sc;
+                sc.tx = tx; sc.mode = 1; sc.mult = m; sc.pf = pf;
+                out.push_back(sc);
+            }
         }
-        for (int m : {1, 2}) {
-            Sched sc;
-            sc.tx = tx; sc.mode = 1; sc.mult = m;
-            out.push_back(sc);
-        }
-    }
     return out;
 }
 
@@ -446,7 +447,7 @@ lb_status autotune_single(lb_handle* h) {
             continue;
         HIPC(hipMemcpyAsync(h->d_items, items.data(), items.size() * sizeof(WorkItem),
                             hipMemcpyHostToDevice, h->s));
-        const double ms = time_candidate(h->cfg.precision, sc.tx, h->d_desc, h->d_items, sc.n_items,
+        const double ms = time_candidate(h->cfg.precision, sc.tx, sc.pf, h->d_desc, h->d_items, sc.n_items,
                                          sc.grid, h->parity, h->s, reps);
         if (ms < best) { best = ms; best_sc = sc; }
     }
@@ -737,11 +738,13 @@ lb_status lb_timing_read(lb_handle* h, double* ms_per_step, int64_t* steps) {
     return LB_OK;
 }
 
-lb_status lb_get_schedule(lb_handle* h, int32_t* tile_x, int32_t* rows, int32_t* grid) {
-    if (!h || !tile_x || !rows || !grid) return LB_E_INVALID_ARG;
+lb_status lb_get_schedule(lb_handle* h, int32_t* tile_x, int32_t* rows, int32_t* grid,
+                          int32_t* prefetch) {
+    if (!h || !tile_x || !rows || !grid || !prefetch) return LB_E_INVALID_ARG;
     *tile_x = h->sc.tx;
     *rows = h->sc.rows;
     *grid = h->sc.mode == 1 ? h->sc.grid : 0;
+    *prefetch = h->sc.pf;
     return LB_OK;
 }
 
@@ -785,6 +788,7 @@ struct lb_batch {
     double* d_fields = nullptr;
     double* d_part = nullptr;
     int max_ny = 0;
+    int64_t max_slot_nodes = 0;
     double* d_dout = nullptr;
     char* pool = nullptr;
     uint64_t pool_bytes = 0;
@@ -795,6 +799,7 @@ struct lb_batch {
     Sched sc;
     bool fixed_tile = false;
     bool dirty = true;
+    int64_t tuned_nodes = 0;  // nodes in use when the schedule was last autotuned
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     int glen = 16;
     bool timing = false;
@@ -804,24 +809,29 @@ struct lb_batch {
 
 namespace {
 
+// Largest lattice one batch slot may hold (the FP64 read-out scratch is sized for it).
+constexpr int64_t kMaxSlotNodes = (int64_t)1 << 24;
+
 struct BatchLayout {
     uint64_t descs, items, items64, part, dout, fields, pool, total;
     int max_items, max_items64, max_ny;
+    int64_t max_slot_nodes;
 };
 
 BatchLayout batch_layout(int32_t slots, int64_t cap, int prec) {
     BatchLayout L;
     const int sb = store_bytes(prec);
     L.max_items = (int)std::min<int64_t>((int64_t)1 << 30, cap / 32 + 4 * (int64_t)slots + 3 * kMaxGrid);
-    L.max_items64 = (int)std::min<int64_t>((int64_t)1 << 30, cap / 128 + 4 * (int64_t)slots);
+    L.max_items64 = (int)std::min<int64_t>((int64_t)1 << 30, std::min<int64_t>(cap, kMaxSlotNodes) / 128 + 64);
     L.max_ny = (int)std::min<int64_t>(cap / 8, 1 << 20);
+    L.max_slot_nodes = std::min<int64_t>(cap, kMaxSlotNodes);
     uint64_t o = 0;
     L.descs = o; o += align_up((uint64_t)slots * sizeof(LatDesc));
     L.items = o; o += align_up((uint64_t)L.max_items * sizeof(WorkItem));
     L.items64 = o; o += align_up((uint64_t)L.max_items64 * sizeof(WorkItem));
     L.part = o; o += align_up((uint64_t)4 * L.max_ny * sizeof(double));
     L.dout = o; o += align_up(16 * sizeof(double));
-    L.fields = o; o += align_up((uint64_t)4 * cap * sizeof(double));
+    L.fields = o; o += align_up((uint64_t)4 * L.max_slot_nodes * sizeof(double));
     L.pool = o; o += align_up((uint64_t)2 * 18 * sb * (uint64_t)(cap + 64 * (int64_t)slots) + kAlign * 2 * slots);
     L.total = o;
     return L;
@@ -898,7 +908,7 @@ lb_status batch_autotune(lb_batch* b) {
         if (!build_schedule(lats, b->prec, sc, b->max_items, items)) continue;
         HIPC(hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(WorkItem),
                             hipMemcpyHostToDevice, b->s));
-        const double ms = time_candidate(b->prec, sc.tx, b->d_descs, b->d_items, sc.n_items, sc.grid,
+        const double ms = time_candidate(b->prec, sc.tx, sc.pf, b->d_descs, b->d_items, sc.n_items, sc.grid,
                                          b->parity, b->s, 3);
         if (ms < best) { best = ms; best_sc = sc; }
     }
@@ -913,7 +923,7 @@ lb_status batch_graph(lb_batch* b, int parity, hipGraphExec_t* out) {
         hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         int p = parity;
         for (int i = 0; i < b->glen && e == hipSuccess; ++i) {
-            e = launch_step(b->prec, b->sc.tx, b->d_descs, b->d_items, b->n_items, b->sc.grid, p, cs);
+            e = launch_step(b->prec, b->sc.tx, b->sc.pf, b->d_descs, b->d_items, b->n_items, b->sc.grid, p, cs);
             p ^= 1;
         }
         hipError_t e2 = hipStreamEndCapture(cs, &g);
@@ -981,6 +991,7 @@ lb_status lb_batch_create(int32_t slots, int64_t node_capacity, int32_t precisio
     b->max_items64 = L.max_items64;
     b->d_part = (double*)(b->ws + L.part);
     b->max_ny = L.max_ny;
+    b->max_slot_nodes = L.max_slot_nodes;
     b->d_dout = (double*)(b->ws + L.dout);
     b->d_fields = (double*)(b->ws + L.fields);
     b->pool = b->ws + L.pool;
@@ -1004,7 +1015,7 @@ lb_status lb_batch_add(lb_batch* b, const lb_config* cfg, const double* phi0, in
     lb_status st = validate(cfg);
     if (st != LB_OK) return st;
     if (cfg->precision != b->prec) return LB_E_INVALID_ARG;
-    if (cfg->ny > b->max_ny || (int64_t)cfg->nx * cfg->ny > b->capacity) return LB_E_WORKSPACE;
+    if (cfg->ny > b->max_ny || (int64_t)cfg->nx * cfg->ny > b->max_slot_nodes) return LB_E_WORKSPACE;
     int free_slot = -1;
     for (int i = 0; i < b->nslots; ++i)
         if (!b->slot[i].used) { free_slot = i; break; }
@@ -1053,7 +1064,15 @@ lb_status lb_batch_remove(lb_batch* b, int32_t slot) {
 lb_status lb_batch_step(lb_batch* b, int64_t n, int32_t use_graph) {
     if (!b || n < 0) return LB_E_INVALID_ARG;
     if (b->dirty) {
-        lb_status st = b->fixed_tile ? batch_set_sched(b, b->sc) : batch_autotune(b);
+        int32_t used;
+        int64_t nodes;
+        lb_batch_usage(b, &used, &nodes);
+        // autotune when the load changed by more than 2x since the last tuning,
+        // otherwise rebuild the work list with the current schedule
+        const bool retune = !b->fixed_tile && nodes > 0 &&
+                            (b->tuned_nodes == 0 || nodes > 2 * b->tuned_nodes || 2 * nodes < b->tuned_nodes);
+        lb_status st = retune ? batch_autotune(b) : batch_set_sched(b, b->sc);
+        if (retune && st == LB_OK) b->tuned_nodes = nodes;
         if (st != LB_OK) return st;
         b->dirty = false;
     }
@@ -1071,7 +1090,7 @@ lb_status lb_batch_step(lb_batch* b, int64_t n, int32_t use_graph) {
             left -= reps * b->glen;  // glen is even: parity unchanged
         }
         for (int64_t i = 0; i < left; ++i) {
-            HIPC(launch_step(b->prec, b->sc.tx, b->d_descs, b->d_items, b->n_items, b->sc.grid, b->parity, b->s));
+            HIPC(launch_step(b->prec, b->sc.tx, b->sc.pf, b->d_descs, b->d_items, b->n_items, b->sc.grid, b->parity, b->s));
             b->parity ^= 1;
         }
     } else if (n & 1) {

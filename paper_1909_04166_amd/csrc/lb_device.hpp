@@ -385,7 +385,10 @@ __device__ __forceinline__ void ace_collide(R f[9], R phi, R ux, R uy, R Mth_x, 
 
 // ------------------------------------------------------------- fused kernel
 
-template <class ST, int TX, int MODE>
+// PF: once a lane has stored its post-collision f (and later gbar), the freed
+// registers receive the next row's pulled values, so those loads are in flight
+// while the rest of the collision computes (no extra registers).
+template <class ST, int TX, int MODE, bool PF>
 __global__ void __launch_bounds__(TX) lb_fused(const LatDesc* __restrict__ descs,
                                                const WorkItem* __restrict__ items, int n_items,
                                                int parity) {
@@ -426,15 +429,16 @@ __global__ void __launch_bounds__(TX) lb_fused(const LatDesc* __restrict__ descs
         const int H = it.y1 - it.y0;
         for (int k = 0; k < H + 4; ++k) {
             const int L = it.y0 - 2 + k;
+            const bool have = PF && k >= 5;  // rows already pulled during the last collision
             // ---- A: phi at the leading row
             if (inA) {
-                pull9<ST>(src, P, nx, ny, wall, xc, xm, xp, map_row(L, ny, wall), K.shf, f0);
+                if (!have) pull9<ST>(src, P, nx, ny, wall, xc, xm, xp, map_row(L, ny, wall), K.shf, f0);
                 s_phi[L & 3][t] = sum9(f0);
             }
             // ---- B: pbar one row behind
             if (k >= 2 && inB) {
                 const int Lg = L - 1;
-                pull9<ST>(srcg, P, nx, ny, wall, xc, xm, xp, map_row(Lg, ny, wall), K.shg, g0);
+                if (!have) pull9<ST>(srcg, P, nx, ny, wall, xc, xm, xp, map_row(Lg, ny, wall), K.shg, g0);
                 s_pb[Lg & 3][t] = sum9(g0);
             }
             __syncthreads();
@@ -464,64 +468,94 @@ __global__ void __launch_bounds__(TX) lb_fused(const LatDesc* __restrict__ descs
             }
             __syncthreads();
             // ---- F: collide row C = L - 2
-            if (k >= 4 && inF) {
+            if (k >= 4) {
                 const int C = L - 2;
+                const bool pre = PF && MODE == MODE_STEP && k + 1 < H + 4;
                 NodeIn<R> in;
-                in.phi = s_phi[C & 3][t];
-                in.pbar = s_pb[C & 3][t];
-                in.dphx = pdx; in.dphy = pdy; in.m2 = pm2; in.nx = pnx; in.ny = pny;
-                in.y = R(C);
-                in.divn = R(0); in.dmux = R(0); in.dmuy = R(0);
-                grad3x3(s_pb[(C - 1) & 3], s_pb[C & 3], s_pb[(C + 1) & 3], t, in.dpx, in.dpy);
-                if (chem) {
-                    grad3x3(s_na[(C - 1) & 3], s_na[C & 3], s_na[(C + 1) & 3], t, in.dmux, in.dmuy);
-                } else {
-                    R a1, a2, b1, b2;
-                    grad3x3(s_na[(C - 1) & 3], s_na[C & 3], s_na[(C + 1) & 3], t, a1, a2);
-                    grad3x3(s_nb[(C - 1) & 3], s_nb[C & 3], s_nb[(C + 1) & 3], t, b1, b2);
-                    in.divn = a1 + b2;
+                NodeOut<R> o;
+                uint32_t idx = 0;
+                if (inF) {
+                    in.phi = s_phi[C & 3][t];
+                    in.pbar = s_pb[C & 3][t];
+                    in.dphx = pdx; in.dphy = pdy; in.m2 = pm2; in.nx = pnx; in.ny = pny;
+                    in.y = R(C);
+                    in.divn = R(0); in.dmux = R(0); in.dmuy = R(0);
+                    grad3x3(s_pb[(C - 1) & 3], s_pb[C & 3], s_pb[(C + 1) & 3], t, in.dpx, in.dpy);
+                    if (chem) {
+                        grad3x3(s_na[(C - 1) & 3], s_na[C & 3], s_na[(C + 1) & 3], t, in.dmux, in.dmuy);
+                    } else {
+                        R a1, a2, b1, b2;
+                        grad3x3(s_na[(C - 1) & 3], s_na[C & 3], s_na[(C + 1) & 3], t, a1, a2);
+                        grad3x3(s_nb[(C - 1) & 3], s_nb[C & 3], s_nb[(C + 1) & 3], t, b1, b2);
+                        in.divn = a1 + b2;
+                    }
+                    o = node_macro<R>(K, chem, in, g1);
+                    idx = (uint32_t)C * (uint32_t)nx + (uint32_t)xc;
                 }
-                const NodeOut<R> o = node_macro<R>(K, chem, in, g1);
-                const uint32_t idx = (uint32_t)C * (uint32_t)nx + (uint32_t)xc;
                 if constexpr (MODE == MODE_STEP) {
-                    const R Mth = K.M * (K.four_W * in.phi * (R(1) - in.phi));
-                    ace_collide<R>(f2, in.phi, o.ux, o.uy, Mth * in.nx, Mth * in.ny, K.omphi);
                     const R w0 = R(4.0 / 9.0), w1 = R(1.0 / 9.0), w5 = R(1.0 / 36.0);
+                    if (inF) {
+                        const R Mth = K.M * (K.four_W * in.phi * (R(1) - in.phi));
+                        ace_collide<R>(f2, in.phi, o.ux, o.uy, Mth * in.nx, Mth * in.ny, K.omphi);
 #pragma unroll
-                    for (int a = 0; a < 9; ++a) {
-                        const R wa = a == 0 ? w0 : (a < 5 ? w1 : w5);
-                        sto<ST>(dst + a * P, idx, f2[a] - wa * K.shf);
+                        for (int a = 0; a < 9; ++a) {
+                            const R wa = a == 0 ? w0 : (a < 5 ? w1 : w5);
+                            sto<ST>(dst + a * P, idx, f2[a] - wa * K.shf);
+                        }
                     }
-                    hydro_collide<R>(g1, o);
+                    if (pre && inA)  // next leading row into the freed f registers
+                        pull9<ST>(src, P, nx, ny, wall, xc, xm, xp, map_row(L + 1, ny, wall), K.shf, f2);
+                    if (inF) {
+                        hydro_collide<R>(g1, o);
 #pragma unroll
-                    for (int a = 0; a < 9; ++a) {
-                        const R wa = a == 0 ? w0 : (a < 5 ? w1 : w5);
-                        sto<ST>(dstg + a * P, idx, g1[a] - wa * K.shg);
+                        for (int a = 0; a < 9; ++a) {
+                            const R wa = a == 0 ? w0 : (a < 5 ? w1 : w5);
+                            sto<ST>(dstg + a * P, idx, g1[a] - wa * K.shg);
+                        }
                     }
+                    if (pre && inB)  // next pbar row into the freed gbar registers
+                        pull9<ST>(srcg, P, nx, ny, wall, xc, xm, xp, map_row(L, ny, wall), K.shg, g1);
                 } else if constexpr (MODE == MODE_FIELDS) {
-                    double* F = D.fields;
-                    const int64_t N = (int64_t)nx * ny;
-                    F[idx] = (double)in.phi;
-                    F[N + idx] = (double)o.p;
-                    F[2 * N + idx] = (double)o.ux;
-                    F[3 * N + idx] = (double)o.uy;
+                    if (inF) {
+                        double* F = D.fields;
+                        const int64_t N = (int64_t)nx * ny;
+                        F[idx] = (double)in.phi;
+                        F[N + idx] = (double)o.p;
+                        F[2 * N + idx] = (double)o.ux;
+                        F[3 * N + idx] = (double)o.uy;
+                    }
                 } else {
-                    double* F = D.fields;
-                    const int64_t N = (int64_t)nx * ny;
-                    F[idx] = (double)in.dphx;
-                    F[N + idx] = (double)in.dphy;
-                    F[2 * N + idx] = (double)in.nx;
-                    F[3 * N + idx] = (double)in.ny;
-                    F[4 * N + idx] = (double)in.divn;
-                    F[5 * N + idx] = (double)o.Ftx;
-                    F[6 * N + idx] = (double)o.Fty;
-                    F[7 * N + idx] = (double)o.Fpx;
-                    F[8 * N + idx] = (double)o.Fpy;
+                    if (inF) {
+                        double* F = D.fields;
+                        const int64_t N = (int64_t)nx * ny;
+                        F[idx] = (double)in.dphx;
+                        F[N + idx] = (double)in.dphy;
+                        F[2 * N + idx] = (double)in.nx;
+                        F[3 * N + idx] = (double)in.ny;
+                        F[4 * N + idx] = (double)in.divn;
+                        F[5 * N + idx] = (double)o.Ftx;
+                        F[6 * N + idx] = (double)o.Fty;
+                        F[7 * N + idx] = (double)o.Fpx;
+                        F[8 * N + idx] = (double)o.Fpy;
+                    }
                 }
             }
             // ---- rotate the register pipeline
+            if (PF && MODE == MODE_STEP && k >= 4) {
 #pragma unroll
-            for (int a = 0; a < 9; ++a) { f2[a] = f1[a]; f1[a] = f0[a]; g1[a] = g0[a]; }
+                for (int a = 0; a < 9; ++a) {
+                    const R nf = f2[a];  // prefetched leading row
+                    f2[a] = f1[a];
+                    f1[a] = f0[a];
+                    f0[a] = nf;
+                    const R ng = g1[a];  // prefetched pbar row
+                    g1[a] = g0[a];
+                    g0[a] = ng;
+                }
+            } else {
+#pragma unroll
+                for (int a = 0; a < 9; ++a) { f2[a] = f1[a]; f1[a] = f0[a]; g1[a] = g0[a]; }
+            }
             pdx = cdx; pdy = cdy; pm2 = cm2; pnx = cnx; pny = cny;
         }
         __syncthreads();  // the rings are reused by the next work item

@@ -8,7 +8,8 @@
 
 namespace cmlb {
 
-hipError_t launch_step(int prec, int tx, const LatDesc* d, const WorkItem* items, int n_items,
+// pf != 0 selects the variant that prefetches the next rows during the collision.
+hipError_t launch_step(int prec, int tx, int pf, const LatDesc* d, const WorkItem* items, int n_items,
                        int grid, int parity, hipStream_t s);
 hipError_t launch_extract(int prec, int mode, const LatDesc* d, const WorkItem* items64,
                           int n_items, int parity, hipStream_t s);
@@ -19,6 +20,6 @@ hipError_t launch_diag(const LatDesc* d, const double* fields, double* part, dou
                        double step, double u_max, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, uint64_t n, hipStream_t s);
 // Resident workgroups per CU of the fused step kernel (from the HIP occupancy API).
-int fused_occupancy(int prec, int tx);
+int fused_occupancy(int prec, int tx, int pf);
 
 }  // namespace cmlb

@@ -5,49 +5,56 @@ namespace cmlb {
 
 // ------------------------------------------------------------ fused step
 
-template <class ST, int MODE>
+template <class ST, int MODE, bool PF>
 static hipError_t launch_fused_tx(int tx, const LatDesc* d, const WorkItem* items, int n_items,
                                   int grid, int parity, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
     if (grid <= 0 || grid > n_items) grid = n_items;
     switch (tx) {
-    case 64: hipLaunchKernelGGL((lb_fused<ST, 64, MODE>), dim3(grid), dim3(64), 0, s, d, items, n_items, parity); break;
-    case 128: hipLaunchKernelGGL((lb_fused<ST, 128, MODE>), dim3(grid), dim3(128), 0, s, d, items, n_items, parity); break;
-    case 256: hipLaunchKernelGGL((lb_fused<ST, 256, MODE>), dim3(grid), dim3(256), 0, s, d, items, n_items, parity); break;
+    case 64: hipLaunchKernelGGL((lb_fused<ST, 64, MODE, PF>), dim3(grid), dim3(64), 0, s, d, items, n_items, parity); break;
+    case 128: hipLaunchKernelGGL((lb_fused<ST, 128, MODE, PF>), dim3(grid), dim3(128), 0, s, d, items, n_items, parity); break;
+    case 256: hipLaunchKernelGGL((lb_fused<ST, 256, MODE, PF>), dim3(grid), dim3(256), 0, s, d, items, n_items, parity); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_step(int prec, int tx, const LatDesc* d, const WorkItem* items, int n_items,
+template <class ST>
+static hipError_t launch_step_st(int tx, int pf, const LatDesc* d, const WorkItem* items, int n_items,
+                                 int grid, int parity, hipStream_t s) {
+    return pf ? launch_fused_tx<ST, MODE_STEP, true>(tx, d, items, n_items, grid, parity, s)
+              : launch_fused_tx<ST, MODE_STEP, false>(tx, d, items, n_items, grid, parity, s);
+}
+
+hipError_t launch_step(int prec, int tx, int pf, const LatDesc* d, const WorkItem* items, int n_items,
                        int grid, int parity, hipStream_t s) {
     switch (prec) {
-    case LB_FP64: return launch_fused_tx<StF64, MODE_STEP>(tx, d, items, n_items, grid, parity, s);
-    case LB_FP32: return launch_fused_tx<StF32, MODE_STEP>(tx, d, items, n_items, grid, parity, s);
-    case LB_FP32_F16: return launch_fused_tx<StF16, MODE_STEP>(tx, d, items, n_items, grid, parity, s);
-    case LB_FP32_BF16: return launch_fused_tx<StBF16, MODE_STEP>(tx, d, items, n_items, grid, parity, s);
+    case LB_FP64: return launch_step_st<StF64>(tx, pf, d, items, n_items, grid, parity, s);
+    case LB_FP32: return launch_step_st<StF32>(tx, pf, d, items, n_items, grid, parity, s);
+    case LB_FP32_F16: return launch_step_st<StF16>(tx, pf, d, items, n_items, grid, parity, s);
+    case LB_FP32_BF16: return launch_step_st<StBF16>(tx, pf, d, items, n_items, grid, parity, s);
     }
     return hipErrorInvalidValue;
 }
 
-template <class ST>
+template <class ST, bool PF>
 static int occ_tx(int tx) {
     int nb = 0;
     hipError_t e = hipErrorInvalidValue;
     switch (tx) {
-    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lb_fused<ST, 64, MODE_STEP>, 64, 0); break;
-    case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lb_fused<ST, 128, MODE_STEP>, 128, 0); break;
-    case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lb_fused<ST, 256, MODE_STEP>, 256, 0); break;
+    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lb_fused<ST, 64, MODE_STEP, PF>, 64, 0); break;
+    case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lb_fused<ST, 128, MODE_STEP, PF>, 128, 0); break;
+    case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lb_fused<ST, 256, MODE_STEP, PF>, 256, 0); break;
     }
     return e == hipSuccess ? nb : 1;
 }
 
-int fused_occupancy(int prec, int tx) {
+int fused_occupancy(int prec, int tx, int pf) {
     switch (prec) {
-    case LB_FP64: return occ_tx<StF64>(tx);
-    case LB_FP32: return occ_tx<StF32>(tx);
-    case LB_FP32_F16: return occ_tx<StF16>(tx);
-    case LB_FP32_BF16: return occ_tx<StBF16>(tx);
+    case LB_FP64: return pf ? occ_tx<StF64, true>(tx) : occ_tx<StF64, false>(tx);
+    case LB_FP32: return pf ? occ_tx<StF32, true>(tx) : occ_tx<StF32, false>(tx);
+    case LB_FP32_F16: return pf ? occ_tx<StF16, true>(tx) : occ_tx<StF16, false>(tx);
+    case LB_FP32_BF16: return pf ? occ_tx<StBF16, true>(tx) : occ_tx<StBF16, false>(tx);
     }
     return 1;
 }
@@ -58,10 +65,10 @@ hipError_t launch_extract(int prec, int mode, const LatDesc* d, const WorkItem* 
     if (n_items <= 0) return hipSuccess;
 #define CMLB_EXTRACT(ST)                                                                          \
     if (mode == MODE_FIELDS)                                                                      \
-        hipLaunchKernelGGL((lb_fused<ST, 64, MODE_FIELDS>), dim3(n_items), dim3(64), 0, s, d,   \
+        hipLaunchKernelGGL((lb_fused<ST, 64, MODE_FIELDS, false>), dim3(n_items), dim3(64), 0, s, d,   \
                            items64, n_items, parity);                                             \
     else                                                                                          \
-        hipLaunchKernelGGL((lb_fused<ST, 64, MODE_COUPLING>), dim3(n_items), dim3(64), 0, s, d, \
+        hipLaunchKernelGGL((lb_fused<ST, 64, MODE_COUPLING, false>), dim3(n_items), dim3(64), 0, s, d, \
                            items64, n_items, parity);
     switch (prec) {
     case LB_FP64: CMLB_EXTRACT(StF64); break;
@@ -299,16 +306,29 @@ hipError_t launch_diag(const LatDesc* d, const double* fields, double* part, dou
 
 // ------------------------------------------------------------ copy kernel
 
+// Four independent 16-byte loads per lane before the stores, grid of 64
+// workgroups per CU: the attainable device-to-device copy bandwidth.
 __global__ void __launch_bounds__(256) k_copy(uint4* __restrict__ dst, const uint4* __restrict__ src,
                                               int64_t n16) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n16;
-         i += (int64_t)gridDim.x * blockDim.x)
-        dst[i] = src[i];
+    const int64_t stride = (int64_t)gridDim.x * 1024;
+    for (int64_t b = blockIdx.x * (int64_t)1024 + threadIdx.x; b < n16; b += stride) {
+        uint4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t i = b + u * 256;
+            v[u] = i < n16 ? src[i] : make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t i = b + u * 256;
+            if (i < n16) dst[i] = v[u];
+        }
+    }
 }
 
 hipError_t launch_copy(void* dst, const void* src, uint64_t n, hipStream_t s) {
     const int64_t n16 = (int64_t)(n / 16);
-    int64_t g = (n16 + 255) / 256;
+    int64_t g = (n16 + 1023) / 1024;
     if (g > 256 * 64) g = 256 * 64;
     if (g < 1) g = 1;
     hipLaunchKernelGGL(k_copy, dim3((int)g), dim3(256), 0, s, (uint4*)dst, (const uint4*)src, n16);

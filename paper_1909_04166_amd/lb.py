@@ -97,7 +97,7 @@ _SIGS = {
     "lb_timing_read": ([_vp, _dp, _i64p], ctypes.c_int32),
     "lb_batch_timing_enable": ([_vp, ctypes.c_int32], ctypes.c_int32),
     "lb_batch_timing_read": ([_vp, _dp, _i64p], ctypes.c_int32),
-    "lb_get_schedule": ([_vp, _i32p, _i32p, _i32p], ctypes.c_int32),
+    "lb_get_schedule": ([_vp, _i32p, _i32p, _i32p, _i32p], ctypes.c_int32),
     "lb_struct_sizes": ([_u64p, _u64p], ctypes.c_int32),
     "lb_copy_kernel": ([_vp, _vp, ctypes.c_uint64, _vp], ctypes.c_int32),
 }
@@ -252,11 +252,12 @@ def lb_timing_read(h: int) -> tuple[float, int]:
     return float(ms.value), int(n.value)
 
 
-def lb_get_schedule(h: int) -> tuple[int, int, int]:
-    """(workgroup width, rows per item or segment, persistent grid or 0)."""
-    a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-    _check("lb_get_schedule", lib().lb_get_schedule(_vp(h), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
-    return int(a.value), int(b.value), int(c.value)
+def lb_get_schedule(h: int) -> tuple[int, int, int, int]:
+    """(workgroup width, rows per item or segment, persistent grid or 0, prefetch)."""
+    a, b, c, d = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check("lb_get_schedule", lib().lb_get_schedule(_vp(h), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                                    ctypes.byref(d)))
+    return int(a.value), int(b.value), int(c.value), int(d.value)
 
 
 def lb_copy_kernel(dst: int, src: int, n: int, stream: int) -> None:
@@ -410,3 +411,58 @@ class Lattice:
     @property
     def tile(self):
         return lb_get_schedule(self.h)
+
+
+class Batch:
+    """Many lattices of uneven sizes in one workspace, advanced together by one
+    persistent kernel launch per step (slots can be filled and freed between
+    steps)."""
+
+    def __init__(self, slots: int, node_capacity: int, precision: str = "fp32",
+                 tile: tuple[int, int] = (0, 0), device: str = "cuda:0"):
+        torch = _torch()
+        self.precision = precision
+        nbytes = lb_batch_workspace_bytes(slots, node_capacity, precision)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.stream = torch.cuda.current_stream(self.ws.device).cuda_stream
+        self.b = lb_batch_create(slots, node_capacity, precision, tile, self.ws.data_ptr(), nbytes,
+                                 self.stream)
+        self.shapes = {}
+
+    def close(self):
+        if getattr(self, "b", None):
+            lb_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add(self, case: dict, phi0: np.ndarray, diag_every: int = 0, shift_f: float = 0.5,
+            shift_g: float = 0.0) -> int:
+        cfg = config_from_case(case, self.precision, diag_every, (0, 0), shift_f, shift_g)
+        shape = (int(case["ny"]), int(case["nx"]))
+        slot = lb_batch_add(self.b, cfg, np.asarray(phi0, dtype=np.float64).reshape(shape))
+        self.shapes[slot] = shape
+        return slot
+
+    def remove(self, slot: int) -> None:
+        lb_batch_remove(self.b, slot)
+        self.shapes.pop(slot, None)
+
+    def step(self, n: int = 1, use_graph: bool = True) -> None:
+        lb_batch_step(self.b, n, use_graph)
+
+    def fields(self, slot: int):
+        return lb_batch_get_fields(self.b, slot, self.shapes[slot])
+
+    def diagnostics(self, slot: int) -> dict:
+        return lb_batch_diagnostics(self.b, slot)
+
+    def t(self, slot: int) -> int:
+        return lb_batch_get_step(self.b, slot)
+
+    def usage(self) -> tuple[int, int]:
+        return lb_batch_usage(self.b)

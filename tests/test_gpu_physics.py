@@ -1,0 +1,51 @@
+"""Physics-level checks of the GPU path at full size: Rayleigh-Taylor tip
+positions against the FP64 oracle trajectory (tests/golden/rt256_tips.json,
+written by tests/golden/make_rt_tips.py from the oracle alone), FP64 and FP32;
+stability detection through the diagnostics."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_1909_04166_amd import lb, workloads as W
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_rt_tips_follow_oracle(prec):
+    """Spike and bubble tip positions within 1% of L = 256 (2.56 lattice units)
+    of the oracle's, every 500 steps up to 20000."""
+    gold = json.load(open(os.path.join(HERE, "golden", "rt256_tips.json")))
+    case, phi0 = W.config("rt256")
+    print(f"[case] rt256 {prec} 20000 steps", flush=True)
+    g = lb.Lattice(case, phi0, prec)
+    worst = 0.0
+    for row in gold["rows"]:
+        g.step(row["step"] - g.t)
+        d = g.diagnostics()
+        for k in ("spike_y", "bubble_y"):
+            err = abs(d[k] - row[k])
+            worst = max(worst, err)
+            assert err <= 0.01 * case["nx"], (row["step"], k, d[k], row[k])
+    print(f"   worst tip deviation {worst:.3f} lattice units", flush=True)
+
+
+def test_unstable_run_is_reported():
+    """The stationary droplet at W 4, M 0.02, ratio 1000 diverges near step 450
+    (in the oracle too); lb_step reports LB_E_UNSTABLE after the next check."""
+    case, phi0 = W.config("droplet128")
+    g = lb.Lattice(case, phi0, "fp64", diag_every=100)
+    import torch
+    rcs = [g.step(100) for _ in range(12)]
+    torch.cuda.synchronize()
+    rcs.append(g.step(0))  # the last check has completed by now
+    print("   step codes", rcs, flush=True)
+    assert rcs[0] == lb.LB_OK
+    assert lb.LB_E_UNSTABLE in rcs
+    # the stable variant is not flagged
+    case5, phi5 = W.droplet(128, 25.0, W=5.0)
+    h = lb.Lattice(case5, phi5, "fp64", diag_every=100)
+    assert all(h.step(100) == lb.LB_OK for _ in range(12))
