@@ -38,17 +38,22 @@ class OrcParams(ctypes.Structure):
     _fields_ = [
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
         ("bc_y", ctypes.c_int32), ("force_ref", ctypes.c_int32),
-        ("st_form", ctypes.c_int32), ("pad_", ctypes.c_int32),
+        ("st_form", ctypes.c_int32), ("collision", ctypes.c_int32),
+        ("flow", ctypes.c_int32), ("surf", ctypes.c_int32),
         ("rho_A", ctypes.c_double), ("rho_B", ctypes.c_double),
         ("nu_A", ctypes.c_double), ("nu_B", ctypes.c_double),
         ("sigma0", ctypes.c_double), ("sigma_T", ctypes.c_double),
         ("T0", ctypes.c_double), ("dTdy", ctypes.c_double), ("y_ref", ctypes.c_double),
         ("W", ctypes.c_double), ("M", ctypes.c_double),
         ("gx", ctypes.c_double), ("gy", ctypes.c_double),
+        ("beta", ctypes.c_double), ("psi_a", ctypes.c_double), ("psi_G", ctypes.c_double),
     ]
 
 
-_BC = {"periodic": 0, "wall": 1}
+_BC = {"periodic": 0, "wall": 1, "slip": 2}
+_COLL = {"cascaded": 0, "srt": 1}
+_FLOW = {"coupled": 0, "imposed": 1}
+_SURF = {"linear": 0, "langmuir": 1}
 _FREF = {"mean": 0, "light": 1, "heavy": 2, "none": 3}
 _ST = {"geometric": 0, "chempot": 1}
 
@@ -76,6 +81,9 @@ def _load():
         lib.orc_step_count.restype = ctypes.c_int64
         lib.orc_hydro_collide.argtypes = [dp] + [ctypes.c_double] * 9 + [dp, dp]
         lib.orc_ace_collide.argtypes = [dp] + [ctypes.c_double] * 7 + [dp, dp]
+        lib.orc_hydro_srt.argtypes = [dp] + [ctypes.c_double] * 9 + [dp]
+        lib.orc_ace_srt.argtypes = [dp] + [ctypes.c_double] * 8 + [dp]
+        lib.orc_set_velocity.argtypes = [vp, dp, dp]
         lib.orc_grad9.argtypes = [dp, dp, dp]
         lib.orc_lap9.argtypes = [dp]
         lib.orc_lap9.restype = ctypes.c_double
@@ -107,6 +115,12 @@ def params_from_case(case: dict) -> OrcParams:
     P.y_ref = float(case.get("y_ref", 0.0))
     P.W, P.M = float(case["W"]), float(case["M"])
     P.gx, P.gy = float(case.get("gx", 0.0)), float(case.get("gy", 0.0))
+    P.collision = _COLL[case.get("collision", "cascaded")]
+    P.flow = _FLOW[case.get("flow", "coupled")]
+    P.surf = _SURF[case.get("surf", "linear")]
+    P.beta = float(case.get("beta", 0.0))
+    P.psi_a = float(case.get("psi_a", 0.0))
+    P.psi_G = float(case.get("psi_G", 0.0))
     return P
 
 
@@ -166,6 +180,12 @@ class Oracle:
                  "spike_y", "bubble_y", "centroid_y", "nan_flag"]
         return {k: float(o[i]) for i, k in enumerate(names)}
 
+    def set_velocity(self, ux: np.ndarray, uy: np.ndarray) -> None:
+        """Imposed velocity of an ACE-only case (flow = "imposed")."""
+        ux = np.ascontiguousarray(ux, dtype=np.float64).reshape(self.shape)
+        uy = np.ascontiguousarray(uy, dtype=np.float64).reshape(self.shape)
+        _lib.orc_set_velocity(self._h, _dp(ux), _dp(uy))
+
     def get_dist(self):
         f = np.empty((Q,) + self.shape)
         g = np.empty((Q,) + self.shape)
@@ -196,6 +216,24 @@ def ace_collide(f, phi, ux, uy, M, theta, nx, ny, omega):
     om = np.ascontiguousarray(omega, dtype=np.float64)
     out = np.empty(Q)
     lib.orc_ace_collide(_dp(fi), phi, ux, uy, M, theta, nx, ny, _dp(om), _dp(out))
+    return out
+
+
+def hydro_srt(gbar, p, rho, ux, uy, Ftx, Fty, Fpx, Fpy, omega):
+    """Per-node hydrodynamic SRT collision (post-collision gbar)."""
+    lib = _load()
+    g = np.ascontiguousarray(gbar, dtype=np.float64)
+    out = np.empty(Q)
+    lib.orc_hydro_srt(_dp(g), p, rho, ux, uy, Ftx, Fty, Fpx, Fpy, omega, _dp(out))
+    return out
+
+
+def ace_srt(f, phi, ux, uy, M, theta, nx, ny, omega):
+    """Per-node phase-field SRT collision (post-collision f)."""
+    lib = _load()
+    fi = np.ascontiguousarray(f, dtype=np.float64)
+    out = np.empty(Q)
+    lib.orc_ace_srt(_dp(fi), phi, ux, uy, M, theta, nx, ny, omega, _dp(out))
     return out
 
 

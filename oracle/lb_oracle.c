@@ -27,6 +27,14 @@
  *   O13 raw moments of f, g_0..g_8 and post-collision f      (Sec. 5)
  *   O14 pull streaming, halfway bounce-back at walls         (Eqs. ACEstreamingLB and Sec. 4 streaming)
  *
+ * Options beyond the coupled cascaded step (same order of operations):
+ *   - free-slip walls: halfway specular reflection (Secs. 6.4, 6.5 use free-slip
+ *     boundaries; the paper does not spell out the discrete rule);
+ *   - Langmuir surface tension kappa~(psi) = kappa~_0 (1 + beta ln(1 - psi)) with an
+ *     imposed linear surfactant concentration psi(y) (Eq. Langmuirisotherm, Sec. 6.7);
+ *   - SRT (BGK) collisions for both schemes, the comparison model of Sec. 7;
+ *   - ACE only with an imposed velocity field (Sec. 6.1).
+ *
  * Readings taken where the paper is silent or has typos (each is listed in the
  * design notes of the repository):
  *   - rho(phi), mu(phi) interpolate from phase B (phi=0) to phase A (phi=1):
@@ -68,23 +76,31 @@ static const double CS2 = 1.0 / 3.0; /* c_s^2 = c_sphi^2 (D2Q9, dx = dt = 1) */
 static const double MS8_C00 = 4.0;
 /* Threshold below which the interface normal is set to zero. */
 static const double N_EPS = 1e-12;
+/* Direction with the y component of e_a reversed (specular reflection at a wall y = const). */
+static const int MIRY[Q] = {0, 1, 4, 3, 2, 8, 7, 6, 5};
 
-enum { ORC_PERIODIC = 0, ORC_WALL = 1 };
+enum { ORC_PERIODIC = 0, ORC_WALL = 1, ORC_SLIP = 2 };
+enum { ORC_CASCADED = 0, ORC_SRT = 1 };
+enum { ORC_COUPLED = 0, ORC_IMPOSED = 1 };
+enum { ORC_SIGMA_LINEAR = 0, ORC_SIGMA_LANGMUIR = 1 };
 enum { ORC_FREF_MEAN = 0, ORC_FREF_LIGHT = 1, ORC_FREF_HEAVY = 2, ORC_FREF_NONE = 3 };
 enum { ORC_ST_GEOMETRIC = 0, ORC_ST_CHEMPOT = 1 };
 
 typedef struct {
     int32_t nx, ny;
-    int32_t bc_y;             /* ORC_PERIODIC or ORC_WALL (x is always periodic) */
+    int32_t bc_y;             /* ORC_PERIODIC, ORC_WALL (bounce-back) or ORC_SLIP (x is periodic) */
     int32_t force_ref;        /* reference density of the body force */
     int32_t st_form;          /* surface-tension form */
-    int32_t pad_;
+    int32_t collision;        /* ORC_CASCADED or ORC_SRT */
+    int32_t flow;             /* ORC_COUPLED, or ORC_IMPOSED: ACE only under a given velocity */
+    int32_t surf;             /* ORC_SIGMA_LINEAR (sigma(T(y))) or ORC_SIGMA_LANGMUIR */
     double rho_A, rho_B;      /* phase A (phi = 1), phase B (phi = 0) */
     double nu_A, nu_B;        /* kinematic viscosities */
     double sigma0, sigma_T;   /* sigma(y) = sigma0 + sigma_T * T(y) */
     double T0, dTdy, y_ref;   /* T(y) = T0 + dTdy * (y - y_ref) */
     double W, M;              /* interface width, mobility */
     double gx, gy;            /* body-force acceleration vector */
+    double beta, psi_a, psi_G; /* Langmuir: sigma = sigma0 (1 + beta ln(1 - psi)), psi = psi_a + psi_G y */
 } orc_params;
 
 typedef struct {
@@ -305,10 +321,81 @@ void orc_ace_collide(const double f[Q], double phi, double ux, double uy,
     out[8] = f[8] + (g[0] + g[1] - g[2] + 2.0 * g[3] - g[5] + g[6] - g[7] + g[8]);
 }
 
+/* ------------------------------------------------- SRT collisions (Sec. 7) */
+
+/*
+ * The single-relaxation-time comparison models of Sec. 7 are not printed in the
+ * paper.  Reading: BGK relaxation of the whole distribution at one rate toward
+ * the second-order Hermite expansion of the same continuous equilibrium, with the
+ * second-order Hermite expansion of the same source moments (sigma'_00..sigma'_11
+ * of O9) scaled by (1 - omega / 2).  Zeroth and first moments of the equilibria
+ * agree with the cascaded scheme, and so do the second moments except for the
+ * O(u M theta) cross term of the ACE, which the SRT equilibrium omits; the
+ * higher-order moments and all relaxation rates differ.
+ *
+ * Second-order Hermite expansion on D2Q9 of a distribution with zeroth moment
+ * a0, first moment a1 and second raw moment A2:
+ *   w_a [ a0 + e_a . a1 / c^2 + (A2 - c^2 a0 I) : (e_a e_a - c^2 I) / (2 c^4) ].
+ */
+static double hermite2(int a, double a0, double a1x, double a1y, double A20, double A02,
+                       double A11) {
+    const double c2 = CS2, ex = EX[a], ey = EY[a];
+    const double Bxx = A20 - c2 * a0, Byy = A02 - c2 * a0, Bxy = A11;
+    const double H = Bxx * (ex * ex - c2) + Byy * (ey * ey - c2) + 2.0 * Bxy * ex * ey;
+    return WT[a] * (a0 + (ex * a1x + ey * a1y) / c2 + H / (2.0 * c2 * c2));
+}
+
+/* Pressure-based hydrodynamic SRT: equilibrium moments p, rho c^2 u, p c^2 I +
+ * rho c^2 u u (the discrete moments of c^2 f^M(rho, u) + psi f^M(rho, 0) / rho up to
+ * second order); source moments of O9; one rate om for every moment. */
+void orc_hydro_srt(const double gbar[Q], double p, double rho, double ux, double uy,
+                   double Ftx, double Fty, double Fpx, double Fpy, double om, double out[Q]) {
+    const double c2 = CS2;
+    const double Gp = Fpx * ux + Fpy * uy;
+    const double s00 = Gp, s10 = c2 * Ftx, s01 = c2 * Fty;
+    const double s20 = 2.0 * c2 * (Ftx * ux + Fpx * ux) + c2 * Gp;
+    const double s02 = 2.0 * c2 * (Fty * uy + Fpy * uy) + c2 * Gp;
+    const double s11 = c2 * (Ftx * uy + Fty * ux) + c2 * (Fpx * uy + Fpy * ux);
+    for (int a = 0; a < Q; ++a) {
+        const double geq = hermite2(a, p, rho * c2 * ux, rho * c2 * uy, p * c2 + rho * c2 * ux * ux,
+                                    p * c2 + rho * c2 * uy * uy, rho * c2 * ux * uy);
+        const double src = hermite2(a, s00, s10, s01, s20, s02, s11);
+        out[a] = gbar[a] + om * (geq - gbar[a]) + (1.0 - 0.5 * om) * src;
+    }
+}
+
+/* Conservative Allen-Cahn SRT: equilibrium moments phi, phi u + M theta n,
+ * c^2 phi I + phi u u; one rate om (= omega^phi) for every moment. */
+void orc_ace_srt(const double f[Q], double phi, double ux, double uy, double M, double theta,
+                 double nx, double ny, double om, double out[Q]) {
+    const double c2 = CS2;
+    for (int a = 0; a < Q; ++a) {
+        const double feq = hermite2(a, phi, phi * ux + M * theta * nx, phi * uy + M * theta * ny,
+                                    c2 * phi + phi * ux * ux, c2 * phi + phi * uy * uy, phi * ux * uy);
+        out[a] = f[a] + om * (feq - f[a]);
+    }
+}
+
 /* ------------------------------------------------------------ grid state */
 
 static double sigma_of_y(const orc_params *P, double y) {
     return P->sigma0 + P->sigma_T * (P->T0 + P->dTdy * (y - P->y_ref));
+}
+
+/* kappa~(y) = 1.5 W sigma(y) and its analytic y derivative.  Linear law:
+ * sigma(T(y)) with T linear in y.  Langmuir law (Eq. Langmuirisotherm):
+ * kappa~_0 (1 + beta ln(1 - psi(y))) with psi = psi_a + psi_G y imposed, so
+ * d kappa~/dy = -kappa~_0 beta psi_G / (1 - psi). */
+static void kappa_tilde(const orc_params *P, double y, double *kt, double *dkt_dy) {
+    const double k0 = 1.5 * P->W;
+    if (P->surf == ORC_SIGMA_LANGMUIR) {
+        const double psi = P->psi_a + P->psi_G * y;
+        *kt = k0 * P->sigma0 * (1.0 + P->beta * log(1.0 - psi));
+        *dkt_dy = -k0 * P->sigma0 * P->beta * P->psi_G / (1.0 - psi);
+    } else {
+        *kt = k0 * sigma_of_y(P, y);
+        *dkt_dy = k0 * P->sigma_T * P->dTdy;
+    }
 }
 
 static double rho_ref_of(const orc_params *P) {
@@ -335,6 +422,11 @@ int orc_create(const orc_params *P, orc_state **out) {
     if (P->nx < 4 || P->ny < 4 || !(P->W > 0) || !(P->M > 0) || !(P->rho_A > 0) ||
         !(P->rho_B > 0) || !(P->nu_A > 0) || !(P->nu_B > 0))
         return -1;
+    if (P->bc_y < ORC_PERIODIC || P->bc_y > ORC_SLIP || P->collision < ORC_CASCADED ||
+        P->collision > ORC_SRT || P->flow < ORC_COUPLED || P->flow > ORC_IMPOSED ||
+        P->surf < ORC_SIGMA_LINEAR || P->surf > ORC_SIGMA_LANGMUIR)
+        return -1;
+    if (P->surf == ORC_SIGMA_LANGMUIR && P->st_form != ORC_ST_GEOMETRIC) return -1;
     orc_state *S = (orc_state *)calloc(1, sizeof(orc_state));
     if (!S) return -2;
     S->P = *P;
@@ -363,6 +455,12 @@ void orc_init(orc_state *S, const double *phi0) {
             S->g[a * N + k] = 0.0;
         }
     S->step = 0;
+}
+
+/* Imposed velocity for ORC_IMPOSED (ny*nx each, row-major); kept until replaced. */
+void orc_set_velocity(orc_state *S, const double *ux, const double *uy) {
+    memcpy(S->ux, ux, sizeof(double) * S->N);
+    memcpy(S->uy, uy, sizeof(double) * S->N);
 }
 
 void orc_set_dist(orc_state *S, const double *f, const double *g, int64_t step) {
@@ -438,6 +536,14 @@ static void orc_fields_internal(orc_state *S) {
             const double rho = P->rho_B + ph * (P->rho_A - P->rho_B);
             const double drhox = dRho * dphx, drhoy = dRho * dphy;
 
+            if (P->flow == ORC_IMPOSED) {
+                /* ACE only: u is the imposed field (kept in ux, uy); no hydrodynamics. */
+                S->rho[k] = rho;
+                S->p[k] = 0.0; S->psi[k] = 0.0; S->divn[k] = 0.0;
+                S->Ftx[k] = 0.0; S->Fty[k] = 0.0; S->Fpx[k] = 0.0; S->Fpy[k] = 0.0;
+                continue;
+            }
+
             /* O4 + O6: surface tension. */
             double Fsx, Fsy;
             const double y = (double)j;
@@ -459,9 +565,10 @@ static void orc_fields_internal(orc_state *S) {
                 orc_grad9(qy, &b1, &b2);
                 const double divn = a1 + b2;
                 S->divn[k] = divn;
-                /* kappa~(y) = 1.5 W sigma(y); its gradient is analytic. */
-                const double kt = 1.5 * P->W * sigma_of_y(P, y);
-                const double dktx = 0.0, dkty = 1.5 * P->W * P->sigma_T * P->dTdy;
+                /* kappa~(y) and its analytic gradient (linear or Langmuir law). */
+                double kt, dkty;
+                kappa_tilde(P, y, &kt, &dkty);
+                const double dktx = 0.0;
                 Fsx = -kt * m2 * divn * nx0 + m2 * ((1.0 - nx0 * nx0) * dktx - nx0 * ny0 * dkty);
                 Fsy = -kt * m2 * divn * ny0 + m2 * ((1.0 - ny0 * ny0) * dkty - nx0 * ny0 * dktx);
             }
@@ -518,17 +625,30 @@ void orc_step(orc_state *S, int64_t nsteps) {
                 const double om_h[Q] = {1, 1, 1, 1, omv, omv, 1, 1, 1};
                 double gin[Q], gout[Q], fin[Q], fout[Q];
                 for (int a = 0; a < Q; ++a) { gin[a] = S->g[a * N + k]; fin[a] = S->f[a * N + k]; }
-                orc_hydro_collide(gin, S->p[k], S->rho[k], S->psi[k], S->ux[k], S->uy[k],
-                                  S->Ftx[k], S->Fty[k], S->Fpx[k], S->Fpy[k], om_h, gout);
+                if (P->flow == ORC_IMPOSED) {
+                    for (int a = 0; a < Q; ++a) gout[a] = gin[a]; /* gbar unused */
+                } else if (P->collision == ORC_SRT) {
+                    orc_hydro_srt(gin, S->p[k], S->rho[k], S->ux[k], S->uy[k], S->Ftx[k],
+                                  S->Fty[k], S->Fpx[k], S->Fpy[k], omv, gout);
+                } else {
+                    orc_hydro_collide(gin, S->p[k], S->rho[k], S->psi[k], S->ux[k], S->uy[k],
+                                      S->Ftx[k], S->Fty[k], S->Fpx[k], S->Fpy[k], om_h, gout);
+                }
                 const double om_f[Q] = {1, omphi, omphi, 1, 1, 1, 1, 1, 1};
                 const double theta = 4.0 * ph * (1.0 - ph) / P->W;
                 const int64_t g0 = gidx(S, i, j);
-                orc_ace_collide(fin, ph, S->ux[k], S->uy[k], P->M, theta,
-                                S->nnx[g0], S->nny[g0], om_f, fout);
+                if (P->collision == ORC_SRT)
+                    orc_ace_srt(fin, ph, S->ux[k], S->uy[k], P->M, theta, S->nnx[g0], S->nny[g0],
+                                omphi, fout);
+                else
+                    orc_ace_collide(fin, ph, S->ux[k], S->uy[k], P->M, theta,
+                                    S->nnx[g0], S->nny[g0], om_f, fout);
                 for (int a = 0; a < Q; ++a) { S->gt[a * N + k] = gout[a]; S->ft[a * N + k] = fout[a]; }
             }
 
-        /* O14: pull streaming; halfway bounce-back where the source lies beyond a wall. */
+        /* O14: pull streaming.  Where the source lies beyond a wall: halfway
+         * bounce-back takes the opposite direction at the same node; halfway specular
+         * reflection takes the y-mirrored direction at the node the particle left. */
 #pragma omp parallel for schedule(static)
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
@@ -539,6 +659,10 @@ void orc_step(orc_state *S, int64_t nsteps) {
                     if (P->bc_y == ORC_WALL && (js < 0 || js >= ny)) {
                         S->f[a * N + k] = S->ft[OPP[a] * N + k];
                         S->g[a * N + k] = S->gt[OPP[a] * N + k];
+                    } else if (P->bc_y == ORC_SLIP && (js < 0 || js >= ny)) {
+                        const int64_t kr = (int64_t)j * nx + is;
+                        S->f[a * N + k] = S->ft[MIRY[a] * N + kr];
+                        S->g[a * N + k] = S->gt[MIRY[a] * N + kr];
                     } else {
                         const int64_t ks = (int64_t)wrap(js, ny) * nx + is;
                         S->f[a * N + k] = S->ft[a * N + ks];

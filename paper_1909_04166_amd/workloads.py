@@ -7,7 +7,8 @@ phase-field profile) and no step of the lattice Boltzmann method itself.
 A case is a plain dictionary::
 
     nx, ny            lattice size (x contiguous in every array, index y*nx + x)
-    bc_y              "periodic" or "wall" (halfway bounce-back); x is periodic
+    bc_y              "periodic", "wall" (halfway bounce-back) or "slip" (halfway
+                      specular reflection); x is periodic
     rho_A, rho_B      densities of phase A (phi = 1) and phase B (phi = 0)
     nu_A, nu_B        kinematic viscosities
     sigma0, sigma_T   sigma(y) = sigma0 + sigma_T * T(y)
@@ -16,6 +17,10 @@ A case is a plain dictionary::
     gx, gy            body-force acceleration; F_ext = (rho - rho_ref) g
     force_ref         "mean" | "light" | "heavy" | "none" (rho_ref)
     st_form           "geometric" | "chempot" (surface-tension form)
+    collision         "cascaded" (default) | "srt" (single-relaxation-time comparison model)
+    flow              "coupled" (default) | "imposed" (phase field only, velocity given)
+    surf              "linear" (sigma(T(y)), default) | "langmuir":
+                      sigma = sigma0 (1 + beta ln(1 - psi)), psi = psi_a + psi_G y
 
 Initial phase fields use the equilibrium tanh profile of the conservative
 Allen-Cahn equation (Sec. 2, Eq. hyperbolictangentprofile) with phi_A = 1,
@@ -33,7 +38,8 @@ def base_case(nx: int, ny: int, **kw) -> dict:
     c = dict(nx=int(nx), ny=int(ny), bc_y="periodic", rho_A=1.0, rho_B=1.0,
              nu_A=0.1, nu_B=0.1, sigma0=0.0, sigma_T=0.0, T0=0.0, dTdy=0.0,
              y_ref=0.0, W=4.0, M=0.02, gx=0.0, gy=0.0, force_ref="mean",
-             st_form="geometric")
+             st_form="geometric", collision="cascaded", flow="coupled", surf="linear",
+             beta=0.0, psi_a=0.0, psi_G=0.0)
     c.update(kw)
     return c
 
@@ -110,6 +116,89 @@ def thermocapillary(nx: int = 512, ny: int = 256, R: float = 32.0, ratio: float 
     x, y = _grid(nx, ny)
     r = np.hypot(x - nx / 2, y - yc)
     return case, tanh_profile(R - r, W)
+
+
+def surfactant_young(sigma0_beta: float = 0.0244, G: float = 9.95e-5, D: float = 30.0,
+                     nx: int = 51, ny: int = 201, sigma0: float = 0.01, psi_a: float = 0.0,
+                     nu: float = 0.05, W: float = 4.0, M: float = 0.02, yc: float | None = None):
+    """Young's migration problem recast with an imposed surfactant concentration
+    (Sec. 6.7): neutrally buoyant drop (density ratio 1, nu_A = nu_B) of diameter D
+    near the bottom of a periodic-x channel with no-slip walls, Langmuir law
+    sigma = sigma0 (1 + beta ln(1 - psi)) with psi(y) = psi_a + G y.  The paper
+    gives sigma0 beta only; sigma0 = 0.01 and psi_a = 0 are readings.  Drop centre
+    (nx/2, yc) with yc = D by default.  Creeping-flow terminal velocity
+    V = sigma0 beta G D / (6 mu_B + 9 mu_A) (upward)."""
+    R = D / 2.0
+    yc = float(D if yc is None else yc)
+    case = base_case(nx, ny, bc_y="wall", rho_A=1.0, rho_B=1.0, nu_A=nu, nu_B=nu,
+                     sigma0=sigma0, W=W, M=M, surf="langmuir", beta=sigma0_beta / sigma0,
+                     psi_a=psi_a, psi_G=G)
+    x, y = _grid(nx, ny)
+    r = np.hypot(x - nx // 2, y - yc)
+    return case, tanh_profile(R - r, W)
+
+
+def young_velocity(case: dict, D: float) -> float:
+    """Creeping-flow migration speed -sigma_psi G D / (6 mu_B + 9 mu_A) with the
+    linearized Langmuir sensitivity sigma_psi = -sigma0 beta."""
+    muA, muB = case["rho_A"] * case["nu_A"], case["rho_B"] * case["nu_B"]
+    return case["sigma0"] * case["beta"] * case["psi_G"] * D / (6 * muB + 9 * muA)
+
+
+def falling_drop(Oh: float = 0.3, Eo: float = 43.0, D: float = 30.0, nx: int = 151,
+                 ny: int = 451, ratio: float = 5.0, W: float = 4.0, M: float = 0.02):
+    """Drop falling under gravity (Sec. 6.4): diameter D of phase A at (75, 300) in
+    a 151 x 451 box, periodic in x, free-slip walls at the bottom and top,
+    F_ext = -(rho - rho_B) g j.  nu_A = nu_B = nu from Oh = mu_A / sqrt(rho_A D sigma)
+    (nu = 0.1, 0.2333, 0.3333 for Oh = 0.3, 0.7, 1.0), sigma from that relation and
+    g from Eo = g (rho_A - rho_B) D^2 / sigma.  rho_B = 1, W and M are readings.
+    Time unit sqrt(D / g)."""
+    nu = {0.3: 0.1, 0.7: 0.2333, 1.0: 0.3333}.get(round(Oh, 3), None)
+    rho_A, rho_B = float(ratio), 1.0
+    if nu is None:
+        raise KeyError(Oh)
+    sigma = (rho_A * nu / Oh) ** 2 / (rho_A * D)
+    g = Eo * sigma / ((rho_A - rho_B) * D * D)
+    case = base_case(nx, ny, bc_y="slip", rho_A=rho_A, rho_B=rho_B, nu_A=nu, nu_B=nu,
+                     sigma0=sigma, W=W, M=M, gy=-g, force_ref="light")
+    x, y = _grid(nx, ny)
+    r = np.hypot(x - 75.0, y - 300.0)
+    return case, tanh_profile(D / 2.0 - r, W)
+
+
+def reversing_shear(L0: int = 200, U0: float = 0.04, W: float = 3.0, Pe: float = 60.0):
+    """Circular interface in the imposed reversing vortex of Sec. 6.1: periodic
+    L0 x L0, R = L0 / 5 centred at (L0/2, 3 L0/10), W = 3, M = U0 W / Pe.  The
+    velocity field is evaluated at node centres x = i + 1/2, y = j + 1/2 (reading)
+    and is reversed at T_f = L0 / U0 steps; U0 is a reading (the paper gives only
+    Pe).  Returns (case, phi0, (ux, uy), T_f)."""
+    n = int(L0)
+    case = base_case(n, n, flow="imposed", W=W, M=U0 * W / Pe)
+    x, y = _grid(n, n)
+    xc, yc = x + 0.5, y + 0.5
+    r = np.hypot(xc - n / 2.0, yc - 0.3 * n)
+    phi0 = tanh_profile(n / 5.0 - r, W)
+    a, b = np.pi * (xc / n - 0.5), np.pi * (yc / n - 0.5)
+    ux = -U0 * np.pi * np.cos(a) * np.sin(b)
+    uy = U0 * np.pi * np.sin(a) * np.cos(b)
+    return case, phi0, (ux, uy), int(round(n / U0))
+
+
+def elliptic_cylinder(ratio: float, nu: float, collision: str = "cascaded", n: int = 200,
+                      a: float = 25.0, b: float = 15.0, kappa: float = 0.01, W: float = 4.0,
+                      M: float = 0.02):
+    """Oscillating liquid cylinder of Sec. 7: heavy phase A (rho_A / rho_B = ratio,
+    rho_B = 1) in an ellipse with semi-axes a (x) and b (y) at the centre of a
+    periodic n x n box, nu_A = nu_B = nu, surface-tension parameter
+    kappa~ = 1.5 sigma W.  W and M are readings."""
+    case = base_case(n, n, rho_A=float(ratio), rho_B=1.0, nu_A=nu, nu_B=nu,
+                     sigma0=kappa / (1.5 * W), W=W, M=M, collision=collision)
+    x, y = _grid(n, n)
+    X, Y = x - n / 2, y - n / 2
+    s = np.sqrt((X / a) ** 2 + (Y / b) ** 2)
+    rr = np.hypot(X, Y)
+    d = np.where(s > 0, rr * (1.0 / np.maximum(s, 1e-300) - 1.0), max(a, b))
+    return case, tanh_profile(d, W)
 
 
 def flat_interface(nx: int = 4, ny: int = 128, W: float = 4.0, ratio: float = 1000.0,
