@@ -2,6 +2,7 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
                     [--precision fp64|fp32|fp16|bf16] [--no-cpu-baseline] [--extra]
+                    [--batched] [--served] [--variants] [--stability]
 
 One step = one fused stream-collide pass of both schemes (f and gbar) over
 every node of the synthetic workload, inputs resident in HBM.  Prints ONE JSON
@@ -53,9 +54,11 @@ def make_workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def time_lattice(case, phi0, precision, steps, warmup, tile=(0, 0)):
+def time_lattice(case, phi0, precision, steps, warmup, tile=(0, 0), vel=None):
     import torch
     L = lb.Lattice(case, phi0, precision, tile=tile)
+    if vel is not None:
+        L.set_velocity(*vel)
     L.step(warmup)
     torch.cuda.synchronize()
     lb.lb_timing_enable(L.h, True)
@@ -125,6 +128,73 @@ def bench_served(precision: str, n_req: int, rate: float, budget_gb: float = 24.
     return stats
 
 
+def bench_variants(side: int, steps: int, warmup: int):
+    """Throughput of the option kernels on the roofline grid (the tiled droplets):
+    the SRT pair (same bytes as the cascaded step, 36 s per node) and the phase
+    field alone under an imposed vortex-array velocity (9 + 9 values of f and two
+    compute-type velocity values per node)."""
+    case, phi0 = W.droplet(128, 25.0, W=5.0)
+    case, phi0 = W.tiled(case, phi0, side // 128, side // 128)
+    N = case["nx"] * case["ny"]
+    out = {}
+    for prec in ("fp64", "fp32", "fp16"):
+        rr = time_lattice(dict(case, collision="srt"), phi0, prec, steps, warmup)
+        gbs = 36 * STORE[prec] * N / (rr["ms_kernel"] * 1e-3) / 1e9
+        out[f"srt_{prec}"] = {"MLUPS": round(N * steps / rr["wall_s"] / 1e6, 1), "kernel_GBs": round(gbs, 1),
+                              "frac": round(gbs / HBM_PEAK_GBS, 4), "tile": list(rr["tile"])}
+    y, x = np.mgrid[0:side, 0:side].astype(np.float64)
+    vel = (0.05 * np.sin(2 * np.pi * (y + 0.5) / 128) * np.cos(2 * np.pi * (x + 0.5) / 128),
+           -0.05 * np.cos(2 * np.pi * (y + 0.5) / 128) * np.sin(2 * np.pi * (x + 0.5) / 128))
+    del x, y
+    for coll in ("cascaded", "srt"):
+        for prec in ("fp64", "fp32", "fp16"):
+            rr = time_lattice(dict(case, flow="imposed", collision=coll), phi0, prec, steps, warmup, vel=vel)
+            per_node = 18 * STORE[prec] + 2 * (8 if prec == "fp64" else 4)
+            gbs = per_node * N / (rr["ms_kernel"] * 1e-3) / 1e9
+            out[f"ace_only_{coll}_{prec}"] = {"MLUPS": round(N * steps / rr["wall_s"] / 1e6, 1),
+                                              "kernel_GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                              "alg_bytes_per_node": per_node, "tile": list(rr["tile"])}
+    out["workload"] = (f"{side}x{side} tiled 128^2 droplets (R=25, ratio 1000, W 5); ACE-only rows "
+                       "under an imposed 128-periodic vortex array, |u| <= 0.05")
+    return out
+
+
+def bench_stability(steps: int = 20000):
+    """Sec. 7: smallest viscosity (nu_A = nu_B) with a stable run of the
+    oscillating elliptic cylinder (200^2, a = 25, b = 15, kappa~ = 0.01) for the
+    cascaded and the SRT pair at density ratios 500-900.  Stable: no NaN/Inf and
+    max |u| < 0.1 after `steps` steps.  nu ladder 0.1 * 0.6^k, k = 0..19.  Each
+    model runs as one batch of 80 lattices."""
+    ratios = (500, 600, 800, 900)
+    nus = [0.1 * 0.6 ** k for k in range(20)]
+    stable = {}
+    t0 = time.perf_counter()
+    for coll in ("cascaded", "srt"):
+        B = lb.Batch(len(ratios) * len(nus), 40000 * len(ratios) * len(nus) + 1000, "fp64")
+        slots = {}
+        for r in ratios:
+            for nu in nus:
+                c, p = W.elliptic_cylinder(r, nu, collision=coll)
+                slots[B.add(c, p)] = (r, nu)
+        B.step(steps)
+        for sl, (r, nu) in slots.items():
+            d = B.diagnostics(sl)
+            stable[(coll, r, nu)] = bool(d["nan_flag"] == 0 and d["max_u"] < 0.1)
+        B.close()
+    out = {"steps": steps, "nu_ladder": [float(f"{v:.3e}") for v in nus], "wall_s": None}
+    for r in ratios:
+        row = {}
+        for coll in ("cascaded", "srt"):
+            ok = [nu for nu in nus if stable[(coll, r, nu)]]
+            row[f"{coll}_nu_min"] = float(f"{min(ok):.3e}") if ok else None
+            row[f"{coll}_unstable"] = [float(f"{nu:.3e}") for nu in nus if not stable[(coll, r, nu)]]
+        if row["cascaded_nu_min"] and row["srt_nu_min"]:
+            row["srt_over_cascaded"] = round(row["srt_nu_min"] / row["cascaded_nu_min"], 1)
+        out[f"ratio_{r}"] = row
+    out["wall_s"] = round(time.perf_counter() - t0, 1)
+    return out
+
+
 def cpu_baseline(target_s: float = 15.0):
     import oracle
     case, phi0 = W.droplet(128, 25.0, W=5.0)
@@ -155,6 +225,10 @@ def main():
     ap.add_argument("--extra", action="store_true", help="also time the other precisions and workloads")
     ap.add_argument("--batched", action="store_true", help="also time the uneven batch (256 lattices)")
     ap.add_argument("--served", action="store_true", help="also run the served Poisson stream")
+    ap.add_argument("--variants", action="store_true",
+                    help="also time the SRT pair and the phase-field-only kernels on the roofline grid")
+    ap.add_argument("--stability", action="store_true",
+                    help="also run the nu_min stability sweep of the cascaded and SRT pairs")
     ap.add_argument("--copy-ref", type=int, default=0, metavar="MIB",
                     help="only run the library's device copy kernel over MIB MiB (bandwidth and "
                          "counter reference) and print its GB/s")
@@ -251,6 +325,11 @@ def main():
         low = bench_served("fp16", 200, 0.7 * cap_glups * 1e9 / mean_work)
         out["served"] = {"saturated": sat, "load_0.7": low,
                          "vs_plain_fp64": round(sat["MLUPS"] / out["value"], 3)}
+    if args.variants:
+        side = case["nx"] if args.workload.startswith("tiled") else 8192
+        out["variants"] = bench_variants(side, args.steps, args.warmup)
+    if args.stability:
+        out["stability"] = bench_stability()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

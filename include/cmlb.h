@@ -8,6 +8,11 @@
  *     Marangoni terms, Eqs. surfacetensiongeometricsurfactantsxcomp/ycomp, or the
  *     chemical-potential form of Eq. surfacetensionthermodynamic) and a body force;
  *   - the conservative Allen-Cahn (phase-field) scheme for f (Sec. 5);
+ *   - options used by the paper's test problems: the single-relaxation-time (SRT)
+ *     pair of the stability comparison (Sec. 7), free-slip walls (Secs. 6.4, 6.5),
+ *     the Langmuir surface-tension law of an imposed surfactant concentration
+ *     (Eq. Langmuirisotherm, Sec. 6.7) and the phase field alone under an imposed
+ *     velocity (Sec. 6.1);
  *   - the isotropic finite-difference fields that couple them (grad phi, n,
  *     div n, lap phi, chemical potential, grad rho, grad p; text after
  *     Eq. fluidviscosity).
@@ -25,8 +30,9 @@
  *     storage precision.  Distribution arrays are FP64 [9][ny][nx] in the
  *     velocity order 0 rest, 1 +x, 2 +y, 3 -x, 4 -y, 5 (+,+), 6 (-,+), 7 (-,-),
  *     8 (+,-) (Eq. particlevelocities).
- *   - Node (x, y) = (i, j).  x is periodic.  y is periodic or bounded by
- *     halfway bounce-back walls at y = -1/2 and y = ny - 1/2.
+ *   - Node (x, y) = (i, j).  x is periodic.  y is periodic or bounded by walls
+ *     at y = -1/2 and y = ny - 1/2: halfway bounce-back (no slip) or halfway
+ *     specular reflection (free slip).
  *   - A handle is not thread-safe; distinct handles are independent.
  */
 #ifndef CMLB_H
@@ -49,7 +55,18 @@ enum {
     LB_E_STATE = -6        /* buffer of the wrong size for save/load */
 };
 
-enum { LB_PERIODIC = 0, LB_HALFWAY_BB = 1 };
+enum { LB_PERIODIC = 0, LB_HALFWAY_BB = 1, LB_FREE_SLIP = 2 };
+/* collision model of both schemes: cascaded central moments (Secs. 4, 5) or the
+ * single-relaxation-time comparison pair (Sec. 7; BGK toward second-order Hermite
+ * equilibria and sources with the same zeroth to second moments, one rate:
+ * omega(nu(phi)) for gbar, omega^phi for f) */
+enum { LB_CASCADED = 0, LB_SRT = 1 };
+/* LB_FLOW_IMPOSED: only the phase field f is advanced, under the velocity set by
+ * lb_set_velocity (Sec. 6.1); gbar, the pressure and all forces are absent. */
+enum { LB_FLOW_COUPLED = 0, LB_FLOW_IMPOSED = 1 };
+/* surface-tension law: linear sigma(T(y)), or Langmuir
+ * sigma = sigma0 (1 + beta ln(1 - psi)) of psi(y) = psi_a + psi_G y (geometric form only) */
+enum { LB_SIGMA_LINEAR = 0, LB_SIGMA_LANGMUIR = 1 };
 /* reference density of the body force F_ext = (rho - rho_ref) g */
 enum { LB_FREF_MEAN = 0, LB_FREF_LIGHT = 1, LB_FREF_HEAVY = 2, LB_FREF_NONE = 3 };
 /* surface-tension form: geometric with Marangoni term (default), or chemical potential */
@@ -62,12 +79,14 @@ enum { LB_FP64 = 0, LB_FP32 = 1, LB_FP32_F16 = 2, LB_FP32_BF16 = 3 };
  *   rho(phi) = rho_B + phi (rho_A - rho_B), mu(phi) = mu_B + phi (mu_A - mu_B),
  *   mu_X = rho_X nu_X; omega_4 = omega_5 = 1 / (1/2 + 3 nu(phi)); other hydro rates 1.
  *   M = (1/omega^phi - 1/2) / 3 for the first-order ACE moments; other ACE rates 1.
- *   sigma(y) = sigma0 + sigma_T * (T0 + dTdy * (y - y_ref)); kappa~ = 1.5 W sigma(y).
- * Derived rates must lie in (0, 2).
+ *   sigma(y) = sigma0 + sigma_T * (T0 + dTdy * (y - y_ref)), or the Langmuir law;
+ *   kappa~ = 1.5 W sigma(y), its y derivative analytic.
+ * Derived rates must lie in (0, 2); under the Langmuir law 1 - psi(y) > 0 on every row.
  */
 typedef struct lb_config {
     int32_t nx, ny;          /* lattice size, each >= 8 */
-    int32_t bc_x, bc_y;      /* bc_x must be LB_PERIODIC; bc_y LB_PERIODIC or LB_HALFWAY_BB */
+    int32_t bc_x, bc_y;      /* bc_x must be LB_PERIODIC; bc_y LB_PERIODIC, LB_HALFWAY_BB or
+                                LB_FREE_SLIP */
     int32_t force_ref;       /* LB_FREF_* */
     int32_t st_form;         /* LB_ST_* */
     int32_t precision;       /* LB_FP64, LB_FP32, LB_FP32_F16, LB_FP32_BF16 */
@@ -83,6 +102,11 @@ typedef struct lb_config {
     int32_t tile_x;          /* workgroup width in lanes (64, 128 or 256; strips of tile_x - 4
                                 columns); 0: autotuned */
     int32_t tile_h;          /* rows per work item (>= 8); 0: autotuned */
+    int32_t collision;       /* LB_CASCADED or LB_SRT */
+    int32_t flow;            /* LB_FLOW_COUPLED or LB_FLOW_IMPOSED */
+    int32_t surf;            /* LB_SIGMA_LINEAR or LB_SIGMA_LANGMUIR */
+    int32_t reserved;        /* must be 0 */
+    double beta, psi_a, psi_G; /* Langmuir law parameters */
 } lb_config;
 
 typedef struct lb_diag {
@@ -105,7 +129,8 @@ typedef struct lb_batch lb_batch;
 const char* lb_status_string(lb_status s);
 
 /* Device workspace bytes for one lattice (two copies of the 18 planes in the
- * storage precision, four FP64 field planes, diagnostics and the work list).
+ * storage precision, four FP64 field planes, diagnostics and the work list; with
+ * LB_FLOW_IMPOSED also two velocity planes in the compute type).
  * Errors: LB_E_INVALID_ARG. */
 lb_status lb_workspace_bytes(const lb_config* cfg, uint64_t* bytes);
 
@@ -119,6 +144,12 @@ lb_status lb_create(const lb_config* cfg, void* dev_ws, uint64_t ws_bytes, void*
 /* Initial state at t = 0 (Sec. 5 / readings): f_a = w_a phi0, gbar_a = 0 (p = 0, u = 0).
  * phi0: host, ny*nx FP64, caller-owned, read before return.  Synchronizes. */
 lb_status lb_init_fields(lb_handle* h, const double* phi0);
+
+/* Imposed velocity for LB_FLOW_IMPOSED (Sec. 6.1): host FP64 ux, uy of ny*nx each,
+ * caller-owned, read before return; kept in the compute precision until replaced
+ * (e.g. negated to reverse the flow).  Not part of a checkpoint.  Synchronizes.
+ * Errors: LB_E_INVALID_ARG (NULL, or a coupled lattice). */
+lb_status lb_set_velocity(lb_handle* h, const double* ux, const double* uy);
 
 /* Advances n time steps (stream-collide of both schemes per step).  Enqueued
  * asynchronously on the handle's stream.  With diag_every > 0, a stability check
@@ -139,11 +170,13 @@ lb_status lb_get_coupling(lb_handle* h, double* dev_out);
 lb_status lb_diagnostics(lb_handle* h, lb_diag* out);
 
 /* Post-streaming distributions f, gbar at the current time (FP64 host arrays of
- * 9*ny*nx each; NULL skips one).  Synchronizes. */
+ * 9*ny*nx each; NULL skips one; gbar is all zero under LB_FLOW_IMPOSED).
+ * Synchronizes. */
 lb_status lb_get_dist(lb_handle* h, double* f, double* g);
 
 /* Sets the state at time `step` from post-streaming FP64 distributions (host,
- * 9*ny*nx each), rounded to the storage precision.  Synchronizes. */
+ * 9*ny*nx each), rounded to the storage precision.  g is ignored (and may be
+ * NULL) under LB_FLOW_IMPOSED.  Synchronizes. */
 lb_status lb_set_dist(lb_handle* h, const double* f, const double* g, int64_t step);
 
 /* Bytes of a checkpoint: the 18 stored planes in the storage precision plus the
@@ -162,8 +195,8 @@ void lb_destroy(lb_handle* h);
 /* ------------------------------------------------------------------ batch ----
  * Many independent lattices of uneven sizes advanced by ONE persistent kernel
  * launch per step over a shared work list of (instance, strip, rows) items.
- * All instances share the storage precision cfgs[0].precision and one tile
- * shape.  A slot holds one lattice; slots can be filled and emptied between
+ * All instances share the storage precision, the collision model and one tile
+ * shape; LB_FLOW_IMPOSED lattices are not batched.  A slot holds one lattice; slots can be filled and emptied between
  * steps (continuous batching).  Results of a slot do not depend on the other
  * slots (bit-identical to the same lattice alone). */
 
@@ -180,7 +213,8 @@ lb_status lb_batch_create(int32_t slots, int64_t node_capacity, int32_t precisio
 
 /* Places a lattice in a free slot and initializes it like lb_init_fields.
  * Returns the slot index in *slot.  A slot holds at most min(node_capacity,
- * 2^24) nodes.  Errors: LB_E_INVALID_ARG (bad config or precision mismatch),
+ * 2^24) nodes.  Errors: LB_E_INVALID_ARG (bad config, or a precision or collision
+ * model other than the batch's), LB_E_UNSUPPORTED (LB_FLOW_IMPOSED),
  * LB_E_WORKSPACE (no free slot, not enough free nodes, or lattice too large).
  * Synchronizes. */
 lb_status lb_batch_add(lb_batch* b, const lb_config* cfg, const double* phi0, int32_t* slot);

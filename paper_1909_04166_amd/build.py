@@ -1,7 +1,10 @@
 """Build ``libcmlb.so`` (HIP, gfx950) in-tree with hipcc.
 
 Every HIP source is compiled with packed FP32 instructions disabled
-(``-target-feature -packed-fp32-ops``).
+(``-target-feature -packed-fp32-ops``) and with multiply-add contraction limited
+to single source expressions (``-ffp-contract=on``): every kernel instantiation
+(workgroup width, prefetch variant) then rounds identically, so a lattice gives
+the same bits alone, in a batch or under any tile shape.
 """
 from __future__ import annotations
 
@@ -15,7 +18,7 @@ LIB = os.path.join(HERE, "libcmlb.so")
 SOURCES = ["lb_kernels.hip", "lb_capi.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-Wno-unused-command-line-argument"]
+         "-ffp-contract=on", "-Wno-unused-command-line-argument"]
 
 
 def build(verbose: bool = False, extra: list[str] | None = None, out: str | None = None) -> str:

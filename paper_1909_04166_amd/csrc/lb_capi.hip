@@ -43,7 +43,12 @@ lb_status validate(const lb_config* c) {
     // every plane (storage type) and every FP64 field plane must be < 4 GiB
     if ((uint64_t)c->nx * c->ny * 8 >= ((uint64_t)1 << 32)) return LB_E_INVALID_ARG;
     if (c->bc_x != LB_PERIODIC) return c->bc_x == LB_HALFWAY_BB ? LB_E_UNSUPPORTED : LB_E_INVALID_ARG;
-    if (c->bc_y != LB_PERIODIC && c->bc_y != LB_HALFWAY_BB) return LB_E_INVALID_ARG;
+    if (c->bc_y != LB_PERIODIC && c->bc_y != LB_HALFWAY_BB && c->bc_y != LB_FREE_SLIP)
+        return LB_E_INVALID_ARG;
+    if (c->collision != LB_CASCADED && c->collision != LB_SRT) return LB_E_INVALID_ARG;
+    if (c->flow != LB_FLOW_COUPLED && c->flow != LB_FLOW_IMPOSED) return LB_E_INVALID_ARG;
+    if (c->surf != LB_SIGMA_LINEAR && c->surf != LB_SIGMA_LANGMUIR) return LB_E_INVALID_ARG;
+    if (c->reserved != 0) return LB_E_INVALID_ARG;
     if (c->force_ref < LB_FREF_MEAN || c->force_ref > LB_FREF_NONE) return LB_E_INVALID_ARG;
     if (c->st_form != LB_ST_GEOMETRIC && c->st_form != LB_ST_CHEMPOT) return LB_E_INVALID_ARG;
     if (store_bytes(c->precision) == 0) return LB_E_INVALID_ARG;
@@ -51,9 +56,15 @@ lb_status validate(const lb_config* c) {
         !finite_pos(c->nu_B) || !finite_pos(c->W) || !finite_pos(c->M))
         return LB_E_INVALID_ARG;
     const double vals[] = {c->sigma0, c->sigma_T, c->T0, c->dTdy, c->y_ref, c->gx, c->gy,
-                           c->shift_f, c->shift_g, c->u_max};
+                           c->shift_f, c->shift_g, c->u_max, c->beta, c->psi_a, c->psi_G};
     for (double v : vals)
         if (!std::isfinite(v)) return LB_E_INVALID_ARG;
+    if (c->surf == LB_SIGMA_LANGMUIR) {
+        if (c->st_form != LB_ST_GEOMETRIC) return LB_E_UNSUPPORTED;
+        // 1 - psi(y) > 0 on every row (psi is linear: check the end rows)
+        if (!(1.0 - c->psi_a > 0.0) || !(1.0 - (c->psi_a + c->psi_G * (c->ny - 1)) > 0.0))
+            return LB_E_INVALID_ARG;
+    }
     // derived rates in (0, 2): omega_nu = 1/(1/2 + 3 nu) at both phases, omega_phi
     const double om[] = {1.0 / (0.5 + 3.0 * c->nu_A), 1.0 / (0.5 + 3.0 * c->nu_B),
                          1.0 / (0.5 + 3.0 * c->M)};
@@ -75,12 +86,20 @@ double rho_ref_of(const lb_config* c) {
     }
 }
 
+int kind_of(const lb_config* c) {
+    const bool srt = c->collision == LB_SRT;
+    if (c->flow == LB_FLOW_IMPOSED) return srt ? KIND_ACE_SRT : KIND_ACE_CASCADED;
+    return srt ? KIND_COUPLED_SRT : KIND_COUPLED_CASCADED;
+}
+
 void fill_desc(const lb_config* c, LatDesc& D, void* b0, void* b1, int64_t plane, double* fields) {
     std::memset(&D, 0, sizeof(D));
     D.nx = c->nx;
     D.ny = c->ny;
-    D.wall_y = c->bc_y == LB_HALFWAY_BB ? 1 : 0;
+    D.wall_y = c->bc_y == LB_HALFWAY_BB ? WALL_BOUNCE : (c->bc_y == LB_FREE_SLIP ? WALL_SLIP : WALL_NONE);
     D.st_form = c->st_form;
+    D.surf = c->surf == LB_SIGMA_LANGMUIR ? 1 : 0;
+    D.flow = c->flow == LB_FLOW_IMPOSED ? 1 : 0;
     D.plane = plane;
     D.buf[0] = b0;
     D.buf[1] = b1;
@@ -108,6 +127,10 @@ void fill_desc(const lb_config* c, LatDesc& D, void* b0, void* b1, int64_t plane
     const bool half = c->precision == LB_FP32_F16 || c->precision == LB_FP32_BF16;
     D.shift_f = half ? c->shift_f : 0.0;
     D.shift_g = half ? c->shift_g : 0.0;
+    D.kt0 = 1.5 * c->W * c->sigma0;
+    D.lbeta = c->beta;
+    D.ps_a = c->psi_a;
+    D.ps_G = c->psi_G;
 }
 
 // Strip width of a TX-lane workgroup: two halo lanes on each side.
@@ -214,7 +237,7 @@ struct Sched {
     int grid = 0, n_items = 0, rows = 0;
 };
 
-bool build_schedule(const std::vector<LatShape>& lats, int prec, Sched& sc, int max_items,
+bool build_schedule(const std::vector<LatShape>& lats, int prec, int kind, Sched& sc, int max_items,
                     std::vector<WorkItem>& items) {
     items.clear();
     if (sc.mode == 0) {
@@ -224,7 +247,7 @@ bool build_schedule(const std::vector<LatShape>& lats, int prec, Sched& sc, int 
         sc.rows = sc.th;
         xcd_permute(items, sc.grid);
     } else {
-        int G = sc.mult * std::max(1, fused_occupancy(prec, sc.tx, sc.pf)) * cu_count();
+        int G = sc.mult * std::max(1, step_occupancy(prec, kind, sc.tx, sc.pf)) * cu_count();
         G = std::min(G, kMaxGrid);
         int nb = 0;
         if (!build_segments(lats, sc.tx, G, max_items, items, &nb)) return false;
@@ -249,9 +272,10 @@ Sched default_sched(int nx, int ny) {
 }
 
 struct TuneKey {
-    int prec, nx, ny, wall, st, batch;
+    int prec, nx, ny, wall, st, kind, surf;
     bool operator<(const TuneKey& o) const {
-        return std::tie(prec, nx, ny, wall, st, batch) < std::tie(o.prec, o.nx, o.ny, o.wall, o.st, o.batch);
+        return std::tie(prec, nx, ny, wall, st, kind, surf) <
+               std::tie(o.prec, o.nx, o.ny, o.wall, o.st, o.kind, o.surf);
     }
 };
 std::mutex g_tune_mu;
@@ -269,6 +293,7 @@ std::map<TuneKey, Sched> g_tune;
 
 struct lb_handle {
     lb_config cfg;
+    int kind = KIND_COUPLED_CASCADED;
     hipStream_t s = nullptr;
     char* ws = nullptr;
     uint64_t ws_bytes = 0;
@@ -306,7 +331,7 @@ struct lb_handle {
 namespace {
 
 struct Layout {
-    uint64_t desc, desc_cp, items, items64, part, dout, fields, bufA, bufB, total;
+    uint64_t desc, desc_cp, items, items64, part, dout, fields, bufA, bufB, vel, ktab, total;
 };
 
 Layout layout_of(const lb_config* c) {
@@ -324,13 +349,16 @@ Layout layout_of(const lb_config* c) {
     L.fields = o; o += align_up((uint64_t)4 * N * sizeof(double));
     L.bufA = o; o += align_up((uint64_t)18 * P * sb);
     L.bufB = o; o += align_up((uint64_t)18 * P * sb);
+    L.vel = o;
+    if (c->flow == LB_FLOW_IMPOSED) o += align_up((uint64_t)2 * P * (c->precision == LB_FP64 ? 8 : 4));
+    L.ktab = o; o += align_up((uint64_t)2 * c->ny * sizeof(double));
     L.total = o;
     return L;
 }
 
 lb_status set_sched(lb_handle* h, Sched sc) {
     std::vector<WorkItem> items;
-    if (!build_schedule({{0, h->cfg.nx, h->cfg.ny}}, h->cfg.precision, sc, h->max_items, items))
+    if (!build_schedule({{0, h->cfg.nx, h->cfg.ny}}, h->cfg.precision, h->kind, sc, h->max_items, items))
         return LB_E_INVALID_ARG;
     HIPC(hipMemcpyAsync(h->d_items, items.data(), items.size() * sizeof(WorkItem),
                         hipMemcpyHostToDevice, h->s));
@@ -344,8 +372,8 @@ lb_status set_sched(lb_handle* h, Sched sc) {
 
 lb_status launch_steps_eager(lb_handle* h, int64_t n) {
     for (int64_t i = 0; i < n; ++i) {
-        HIPC(launch_step(h->cfg.precision, h->sc.tx, h->sc.pf, h->d_desc, h->d_items, h->n_items, h->sc.grid,
-                         h->parity, h->s));
+        HIPC(launch_step(h->cfg.precision, h->kind, h->sc.tx, h->sc.pf, h->d_desc, h->d_items, h->n_items,
+                         h->sc.grid, h->parity, h->s));
         h->parity ^= 1;
         h->step += 1;
     }
@@ -361,8 +389,8 @@ lb_status graph_for(lb_handle* h, int parity, hipGraphExec_t* out) {
         hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         int p = parity;
         for (int i = 0; i < h->glen && e == hipSuccess; ++i) {
-            e = launch_step(h->cfg.precision, h->sc.tx, h->sc.pf, h->d_desc, h->d_items, h->n_items, h->sc.grid,
-                            p, cs);
+            e = launch_step(h->cfg.precision, h->kind, h->sc.tx, h->sc.pf, h->d_desc, h->d_items, h->n_items,
+                            h->sc.grid, p, cs);
             p ^= 1;
         }
         hipError_t e2 = hipStreamEndCapture(cs, &g);
@@ -382,7 +410,7 @@ lb_status graph_for(lb_handle* h, int parity, hipGraphExec_t* out) {
 }
 
 lb_status enqueue_diag(lb_handle* h) {
-    HIPC(launch_extract(h->cfg.precision, MODE_FIELDS, h->d_desc, h->d_items64, h->n_items64,
+    HIPC(launch_extract(h->cfg.precision, h->kind, MODE_FIELDS, h->d_desc, h->d_items64, h->n_items64,
                         h->parity, h->s));
     const double umax = h->cfg.u_max > 0 ? h->cfg.u_max : 0.3;
     HIPC(launch_diag(h->d_desc, h->d_fields, h->d_part, h->d_dout, h->cfg.ny, (double)h->step,
@@ -392,15 +420,16 @@ lb_status enqueue_diag(lb_handle* h) {
 
 // Times `reps` launches of one candidate without advancing the state (every
 // launch reads the current buffer and overwrites the other one).
-double time_candidate(int prec, int tx, int pf, const LatDesc* d, const WorkItem* items, int n, int grid,
-                      int parity, hipStream_t s, int reps) {
+double time_candidate(int prec, int kind, int tx, int pf, const LatDesc* d, const WorkItem* items, int n,
+                      int grid, int parity, hipStream_t s, int reps) {
     hipEvent_t a, b;
     if (hipEventCreate(&a) != hipSuccess) return 1e30;
     if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return 1e30; }
     double ms_out = 1e30;
-    bool ok = launch_step(prec, tx, pf, d, items, n, grid, parity, s) == hipSuccess;
+    bool ok = launch_step(prec, kind, tx, pf, d, items, n, grid, parity, s) == hipSuccess;
     ok = ok && hipEventRecord(a, s) == hipSuccess;
-    for (int i = 0; i < reps && ok; ++i) ok = launch_step(prec, tx, pf, d, items, n, grid, parity, s) == hipSuccess;
+    for (int i = 0; i < reps && ok; ++i)
+        ok = launch_step(prec, kind, tx, pf, d, items, n, grid, parity, s) == hipSuccess;
     ok = ok && hipEventRecord(b, s) == hipSuccess && hipEventSynchronize(b) == hipSuccess;
     float ms = 0;
     if (ok && hipEventElapsedTime(&ms, a, b) == hipSuccess) ms_out = ms / reps;
@@ -409,11 +438,13 @@ double time_candidate(int prec, int tx, int pf, const LatDesc* d, const WorkItem
     return ms_out;
 }
 
-// Candidate schedules for one lattice shape.
-std::vector<Sched> candidates(int nx, int ny) {
+// Candidate schedules for one lattice shape (the prefetching variant exists for
+// the coupled cascaded kernel only).
+std::vector<Sched> candidates(int nx, int ny, int kind) {
     std::vector<Sched> out;
     for (int pf : {0, 1})
         for (int tx : {64, 128, 256}) {
+            if (pf && kind != KIND_COUPLED_CASCADED) continue;
             if (tx > 64 && nx <= strip_w(tx / 2)) continue;
             for (int th : {16, 32, 64, 128, 256}) {
                 if (th > ny && th != 16) continue;
@@ -431,7 +462,8 @@ std::vector<Sched> candidates(int nx, int ny) {
 }
 
 lb_status autotune_single(lb_handle* h) {
-    const TuneKey key{h->cfg.precision, h->cfg.nx, h->cfg.ny, h->hdesc.wall_y, h->cfg.st_form, 0};
+    const TuneKey key{h->cfg.precision, h->cfg.nx, h->cfg.ny, h->hdesc.wall_y, h->cfg.st_form, h->kind,
+                      h->cfg.surf};
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune.find(key);
@@ -441,14 +473,14 @@ lb_status autotune_single(lb_handle* h) {
     double best = 1e30;
     const int64_t N = (int64_t)h->cfg.nx * h->cfg.ny;
     const int reps = N >= (1 << 22) ? 3 : 10;
-    for (Sched sc : candidates(h->cfg.nx, h->cfg.ny)) {
+    for (Sched sc : candidates(h->cfg.nx, h->cfg.ny, h->kind)) {
         std::vector<WorkItem> items;
-        if (!build_schedule({{0, h->cfg.nx, h->cfg.ny}}, h->cfg.precision, sc, h->max_items, items))
+        if (!build_schedule({{0, h->cfg.nx, h->cfg.ny}}, h->cfg.precision, h->kind, sc, h->max_items, items))
             continue;
         HIPC(hipMemcpyAsync(h->d_items, items.data(), items.size() * sizeof(WorkItem),
                             hipMemcpyHostToDevice, h->s));
-        const double ms = time_candidate(h->cfg.precision, sc.tx, sc.pf, h->d_desc, h->d_items, sc.n_items,
-                                         sc.grid, h->parity, h->s, reps);
+        const double ms = time_candidate(h->cfg.precision, h->kind, sc.tx, sc.pf, h->d_desc, h->d_items,
+                                         sc.n_items, sc.grid, h->parity, h->s, reps);
         if (ms < best) { best = ms; best_sc = sc; }
     }
     {
@@ -509,7 +541,10 @@ lb_status lb_create(const lb_config* cfg, void* dev_ws, uint64_t ws_bytes, void*
     h->plane = plane_elems(cfg->nx, cfg->ny);
     h->sbytes = store_bytes(cfg->precision);
     h->glen = 32;
+    h->kind = kind_of(cfg);
     fill_desc(cfg, h->hdesc, h->buf[0], h->buf[1], h->plane, h->d_fields);
+    h->hdesc.vel = cfg->flow == LB_FLOW_IMPOSED ? (void*)(h->ws + L.vel) : nullptr;
+    h->hdesc.ktab = (double*)(h->ws + L.ktab);
     auto fail = [&](lb_status s) { lb_destroy(h); return s; };
     if (hipHostMalloc((void**)&h->h_diag, 16 * sizeof(double), hipHostMallocDefault) != hipSuccess)
         return fail(LB_E_HIP);
@@ -518,6 +553,12 @@ lb_status lb_create(const lb_config* cfg, void* dev_ws, uint64_t ws_bytes, void*
     if (hipEventCreate(&h->t0) != hipSuccess || hipEventCreate(&h->t1) != hipSuccess)
         return fail(LB_E_HIP);
     if (hipMemcpyAsync(h->d_desc, &h->hdesc, sizeof(LatDesc), hipMemcpyHostToDevice, h->s) != hipSuccess)
+        return fail(LB_E_HIP);
+    if (cfg->surf == LB_SIGMA_LANGMUIR && launch_kappa_table(h->d_desc, cfg->ny, h->s) != hipSuccess)
+        return fail(LB_E_HIP);
+    // the imposed velocity is zero until lb_set_velocity
+    if (h->hdesc.vel &&
+        hipMemsetAsync(h->hdesc.vel, 0, L.ktab - L.vel, h->s) != hipSuccess)
         return fail(LB_E_HIP);
     std::vector<WorkItem> it64;
     build_items(0, cfg->nx, cfg->ny, 64, 64, it64);
@@ -540,10 +581,23 @@ lb_status lb_init_fields(lb_handle* h, const double* phi0) {
     const int64_t N = (int64_t)h->cfg.nx * h->cfg.ny;
     HIPC(hipMemcpyAsync(h->d_fields, phi0, N * sizeof(double), hipMemcpyHostToDevice, h->s));
     HIPC(launch_state_op(h->cfg.precision, 0, h->d_desc, h->d_fields, 0, 0, h->parity, N, h->s));
+    // the phase-field-only kernel never writes gbar: keep it zero in both buffers
+    if (h->cfg.flow == LB_FLOW_IMPOSED)
+        HIPC(launch_state_op(h->cfg.precision, 0, h->d_desc, h->d_fields, 0, 0, h->parity ^ 1, N, h->s));
     HIPC(hipStreamSynchronize(h->s));
     h->step = 0;
     h->unstable = false;
     h->diag_pending = false;
+    return LB_OK;
+}
+
+lb_status lb_set_velocity(lb_handle* h, const double* ux, const double* uy) {
+    if (!h || !ux || !uy || h->cfg.flow != LB_FLOW_IMPOSED) return LB_E_INVALID_ARG;
+    const int64_t N = (int64_t)h->cfg.nx * h->cfg.ny;
+    HIPC(hipMemcpyAsync(h->d_fields, ux, N * sizeof(double), hipMemcpyHostToDevice, h->s));
+    HIPC(hipMemcpyAsync(h->d_fields + N, uy, N * sizeof(double), hipMemcpyHostToDevice, h->s));
+    HIPC(launch_set_velocity(h->cfg.precision, h->d_desc, h->d_fields, N, h->s));
+    HIPC(hipStreamSynchronize(h->s));
     return LB_OK;
 }
 
@@ -600,7 +654,7 @@ lb_status lb_step(lb_handle* h, int64_t n) {
 lb_status lb_get_fields(lb_handle* h, double* phi, double* p, double* ux, double* uy) {
     if (!h) return LB_E_INVALID_ARG;
     const int64_t N = (int64_t)h->cfg.nx * h->cfg.ny;
-    HIPC(launch_extract(h->cfg.precision, MODE_FIELDS, h->d_desc, h->d_items64, h->n_items64,
+    HIPC(launch_extract(h->cfg.precision, h->kind, MODE_FIELDS, h->d_desc, h->d_items64, h->n_items64,
                         h->parity, h->s));
     double* outs[4] = {phi, p, ux, uy};
     for (int i = 0; i < 4; ++i)
@@ -616,8 +670,8 @@ lb_status lb_get_coupling(lb_handle* h, double* dev_out) {
     LatDesc d = h->hdesc;
     d.fields = dev_out;
     HIPC(hipMemcpyAsync(h->d_desc_cp, &d, sizeof(LatDesc), hipMemcpyHostToDevice, h->s));
-    HIPC(launch_extract(h->cfg.precision, MODE_COUPLING, h->d_desc_cp, h->d_items64, h->n_items64,
-                        h->parity, h->s));
+    HIPC(launch_extract(h->cfg.precision, h->kind, MODE_COUPLING, h->d_desc_cp, h->d_items64,
+                        h->n_items64, h->parity, h->s));
     HIPC(hipStreamSynchronize(h->s));
     return LB_OK;
 }
@@ -638,6 +692,10 @@ lb_status lb_get_dist(lb_handle* h, double* f, double* g) {
     if (!h) return LB_E_INVALID_ARG;
     const int64_t N = (int64_t)h->cfg.nx * h->cfg.ny;
     double* outs[2] = {f, g};
+    if (g && h->cfg.flow == LB_FLOW_IMPOSED) {
+        std::memset(g, 0, sizeof(double) * 9 * N);
+        outs[1] = nullptr;
+    }
     for (int which = 0; which < 2; ++which) {
         if (!outs[which]) continue;
         for (int a = 0; a < 9; ++a) {
@@ -651,10 +709,11 @@ lb_status lb_get_dist(lb_handle* h, double* f, double* g) {
 }
 
 lb_status lb_set_dist(lb_handle* h, const double* f, const double* g, int64_t step) {
-    if (!h || !f || !g || step < 0) return LB_E_INVALID_ARG;
+    const bool imposed = h && h->cfg.flow == LB_FLOW_IMPOSED;
+    if (!h || !f || (!g && !imposed) || step < 0) return LB_E_INVALID_ARG;
     const int64_t N = (int64_t)h->cfg.nx * h->cfg.ny;
     const double* ins[2] = {f, g};
-    for (int which = 0; which < 2; ++which)
+    for (int which = 0; which < (imposed ? 1 : 2); ++which)
         for (int b = 0; b < 9; ++b) {
             HIPC(hipMemcpyAsync(h->d_fields, ins[which] + b * N, N * sizeof(double),
                                 hipMemcpyHostToDevice, h->s));
@@ -775,6 +834,7 @@ struct BatchSlot {
 
 struct lb_batch {
     int prec = 0, nslots = 0, sbytes = 0;
+    int kind = -1;  // kernel kind of the occupied slots (-1 while empty)
     int64_t capacity = 0;
     hipStream_t s = nullptr;
     char* ws = nullptr;
@@ -832,7 +892,9 @@ BatchLayout batch_layout(int32_t slots, int64_t cap, int prec) {
     L.part = o; o += align_up((uint64_t)4 * L.max_ny * sizeof(double));
     L.dout = o; o += align_up(16 * sizeof(double));
     L.fields = o; o += align_up((uint64_t)4 * L.max_slot_nodes * sizeof(double));
-    L.pool = o; o += align_up((uint64_t)2 * 18 * sb * (uint64_t)(cap + 64 * (int64_t)slots) + kAlign * 2 * slots);
+    // per slot: two buffers of 18 planes and the per-row table (2 ny doubles <= 2 N bytes)
+    L.pool = o; o += align_up((uint64_t)2 * 18 * sb * (uint64_t)(cap + 64 * (int64_t)slots) + 2 * (uint64_t)cap +
+                              kAlign * 3 * slots);
     L.total = o;
     return L;
 }
@@ -883,7 +945,8 @@ std::vector<LatShape> batch_shapes(lb_batch* b) {
 
 lb_status batch_set_sched(lb_batch* b, Sched sc) {
     std::vector<WorkItem> items;
-    if (!build_schedule(batch_shapes(b), b->prec, sc, b->max_items, items)) return LB_E_WORKSPACE;
+    if (!build_schedule(batch_shapes(b), b->prec, std::max(b->kind, 0), sc, b->max_items, items))
+        return LB_E_WORKSPACE;
     if (!items.empty())
         HIPC(hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(WorkItem),
                             hipMemcpyHostToDevice, b->s));
@@ -902,14 +965,14 @@ lb_status batch_autotune(lb_batch* b) {
     for (auto& l : lats) { min_nx = std::min(min_nx, l.nx); max_ny = std::max(max_ny, l.ny); }
     Sched best_sc = b->sc;
     double best = 1e30;
-    for (Sched sc : candidates(min_nx, max_ny)) {
+    for (Sched sc : candidates(min_nx, max_ny, b->kind)) {
         if (sc.tx > 128) continue;
         std::vector<WorkItem> items;
-        if (!build_schedule(lats, b->prec, sc, b->max_items, items)) continue;
+        if (!build_schedule(lats, b->prec, b->kind, sc, b->max_items, items)) continue;
         HIPC(hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(WorkItem),
                             hipMemcpyHostToDevice, b->s));
-        const double ms = time_candidate(b->prec, sc.tx, sc.pf, b->d_descs, b->d_items, sc.n_items, sc.grid,
-                                         b->parity, b->s, 3);
+        const double ms = time_candidate(b->prec, b->kind, sc.tx, sc.pf, b->d_descs, b->d_items, sc.n_items,
+                                         sc.grid, b->parity, b->s, 3);
         if (ms < best) { best = ms; best_sc = sc; }
     }
     return batch_set_sched(b, best_sc);
@@ -923,7 +986,8 @@ lb_status batch_graph(lb_batch* b, int parity, hipGraphExec_t* out) {
         hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         int p = parity;
         for (int i = 0; i < b->glen && e == hipSuccess; ++i) {
-            e = launch_step(b->prec, b->sc.tx, b->sc.pf, b->d_descs, b->d_items, b->n_items, b->sc.grid, p, cs);
+            e = launch_step(b->prec, b->kind, b->sc.tx, b->sc.pf, b->d_descs, b->d_items, b->n_items, b->sc.grid,
+                            p, cs);
             p ^= 1;
         }
         hipError_t e2 = hipStreamEndCapture(cs, &g);
@@ -949,7 +1013,8 @@ lb_status batch_extract(lb_batch* b, int32_t slot) {
     if ((int)it64.size() > b->max_items64) return LB_E_WORKSPACE;
     HIPC(hipMemcpyAsync(b->d_items64, it64.data(), it64.size() * sizeof(WorkItem),
                         hipMemcpyHostToDevice, b->s));
-    HIPC(launch_extract(b->prec, MODE_FIELDS, b->d_descs, b->d_items64, (int)it64.size(), b->parity, b->s));
+    HIPC(launch_extract(b->prec, b->kind, MODE_FIELDS, b->d_descs, b->d_items64, (int)it64.size(), b->parity,
+                        b->s));
     return LB_OK;
 }
 
@@ -1015,6 +1080,11 @@ lb_status lb_batch_add(lb_batch* b, const lb_config* cfg, const double* phi0, in
     lb_status st = validate(cfg);
     if (st != LB_OK) return st;
     if (cfg->precision != b->prec) return LB_E_INVALID_ARG;
+    if (cfg->flow != LB_FLOW_COUPLED) return LB_E_UNSUPPORTED;
+    int32_t used_slots;
+    int64_t used_nodes;
+    lb_batch_usage(b, &used_slots, &used_nodes);
+    if (used_slots > 0 && kind_of(cfg) != b->kind) return LB_E_INVALID_ARG;
     if (cfg->ny > b->max_ny || (int64_t)cfg->nx * cfg->ny > b->max_slot_nodes) return LB_E_WORKSPACE;
     int free_slot = -1;
     for (int i = 0; i < b->nslots; ++i)
@@ -1022,23 +1092,27 @@ lb_status lb_batch_add(lb_batch* b, const lb_config* cfg, const double* phi0, in
     if (free_slot < 0) return LB_E_WORKSPACE;
     const int64_t P = plane_elems(cfg->nx, cfg->ny);
     const uint64_t one = align_up((uint64_t)18 * P * b->sbytes);
+    const uint64_t tab = align_up((uint64_t)2 * cfg->ny * sizeof(double));
     uint64_t off;
-    if (!pool_alloc(b, 2 * one, &off)) return LB_E_WORKSPACE;
+    if (!pool_alloc(b, 2 * one + tab, &off)) return LB_E_WORKSPACE;
     BatchSlot& S = b->slot[free_slot];
     S.used = true;
     S.cfg = *cfg;
     S.add_step = b->gstep;
     S.off = off;
-    S.bytes = 2 * one;
+    S.bytes = 2 * one + tab;
     S.plane = P;
     LatDesc& D = b->hdescs[free_slot];
     fill_desc(cfg, D, b->pool + off, b->pool + off + one, P, b->d_fields);
+    D.ktab = (double*)(b->pool + off + 2 * one);
     auto undo = [&](lb_status s) {
         S.used = false;
-        pool_free(b, off, 2 * one);
+        pool_free(b, off, 2 * one + tab);
         return s;
     };
     if (hipMemcpyAsync(b->d_descs + free_slot, &D, sizeof(LatDesc), hipMemcpyHostToDevice, b->s) != hipSuccess)
+        return undo(LB_E_HIP);
+    if (cfg->surf == LB_SIGMA_LANGMUIR && launch_kappa_table(b->d_descs + free_slot, cfg->ny, b->s) != hipSuccess)
         return undo(LB_E_HIP);
     const int64_t N = (int64_t)cfg->nx * cfg->ny;
     if (hipMemcpyAsync(b->d_fields, phi0, N * sizeof(double), hipMemcpyHostToDevice, b->s) != hipSuccess)
@@ -1047,6 +1121,11 @@ lb_status lb_batch_add(lb_batch* b, const lb_config* cfg, const double* phi0, in
     if (launch_state_op(b->prec, 0, b->d_descs + free_slot, b->d_fields, 0, 0, b->parity, N, b->s) != hipSuccess)
         return undo(LB_E_HIP);
     if (hipStreamSynchronize(b->s) != hipSuccess) return undo(LB_E_HIP);
+    if (b->kind != kind_of(cfg)) {  // first lattice of an empty batch sets the kind
+        b->kind = kind_of(cfg);
+        b->tuned_nodes = 0;
+        batch_drop_graphs(b);
+    }
     b->dirty = true;
     *slot = free_slot;
     return LB_OK;
@@ -1090,7 +1169,8 @@ lb_status lb_batch_step(lb_batch* b, int64_t n, int32_t use_graph) {
             left -= reps * b->glen;  // glen is even: parity unchanged
         }
         for (int64_t i = 0; i < left; ++i) {
-            HIPC(launch_step(b->prec, b->sc.tx, b->sc.pf, b->d_descs, b->d_items, b->n_items, b->sc.grid, b->parity, b->s));
+            HIPC(launch_step(b->prec, b->kind, b->sc.tx, b->sc.pf, b->d_descs, b->d_items, b->n_items, b->sc.grid,
+                             b->parity, b->s));
             b->parity ^= 1;
         }
     } else if (n & 1) {

@@ -63,13 +63,16 @@ struct StBF16 {
 // Per-lattice parameters, precomputed on the host.  Lives in device memory.
 struct alignas(16) LatDesc {
     int32_t nx, ny;
-    int32_t wall_y;     // 0 periodic, 1 halfway bounce-back at y = -1/2, ny - 1/2
+    int32_t wall_y;     // walls at y = -1/2, ny - 1/2: 0 none (periodic), 1 halfway
+                        // bounce-back, 2 halfway specular reflection (free slip)
     int32_t st_form;    // 0 geometric (+ Marangoni), 1 chemical potential
     int64_t plane;      // element stride between planes
-    int64_t pad0;
+    int32_t surf;       // kappa~(y): 0 linear, 1 Langmuir of an imposed linear psi(y)
+    int32_t flow;       // 0 coupled, 1 phase field only under an imposed velocity
     void* buf[2];       // 18 planes each
     double* fields;     // FP64 output planes (phi, p, ux, uy or the 9 coupling planes)
-    double* pad1;
+    void* vel;          // imposed velocity: planes ux, uy in the compute type (flow 1)
+    double* ktab;       // Langmuir law: kappa~(y) for y < ny, then d kappa~/dy (surf 1)
     double rhoB, dRho;  // rho(phi) = rhoB + phi dRho
     double muB, dMu;    // mu(phi)  = muB + phi dMu
     double kt_a, kt_b;  // kappa~(y) = kt_a + kt_b y = 1.5 W sigma(y)
@@ -79,6 +82,7 @@ struct alignas(16) LatDesc {
     double M, omphi;    // mobility, first-order ACE rate 1 / (1/2 + 3 M)
     double gx, gy, rho_ref;
     double shift_f, shift_g;
+    double kt0, lbeta, ps_a, ps_G;  // Langmuir: kappa~ = kt0 (1 + lbeta ln(1 - psi)), psi = ps_a + ps_G y
 };
 
 struct WorkItem {
@@ -89,6 +93,12 @@ struct WorkItem {
 };
 
 enum { MODE_STEP = 0, MODE_FIELDS = 1, MODE_COUPLING = 2 };
+// Collision models of the coupled step: the cascaded pair, or the SRT pair of the
+// stability comparison.
+enum { COLL_CASCADED = 0, COLL_SRT = 1 };
+enum { WALL_NONE = 0, WALL_BOUNCE = 1, WALL_SLIP = 2 };
+// Kernel behind a step: coupled pair or phase field alone, cascaded or SRT.
+enum { KIND_COUPLED_CASCADED = 0, KIND_COUPLED_SRT = 1, KIND_ACE_CASCADED = 2, KIND_ACE_SRT = 3 };
 
 // D2Q9 weights and velocities in the order 0 rest, 1 +x, 2 +y, 3 -x, 4 -y,
 // 5 (+,+), 6 (-,+), 7 (-,-), 8 (+,-).
@@ -115,10 +125,11 @@ __device__ __forceinline__ void sto(typename ST::T* plane, uint32_t e, typename 
     *reinterpret_cast<T*>(reinterpret_cast<char*>(plane) + e * (uint32_t)sizeof(T)) = ST::st(v);
 }
 
-// Pull the nine values arriving at (x, r): f_a(x, r) = f~_a(x - e_a); a source
-// beyond a halfway wall is replaced by the opposite direction at the same node.
-// base points at plane 0 of the nine (f or gbar); xm, xp are the periodic
-// neighbours of x.
+// Pull the nine values arriving at (x, r): f_a(x, r) = f~_a(x - e_a).  A source
+// beyond a halfway wall is replaced by the opposite direction at the same node
+// (bounce-back), or by the y-mirrored direction at the node the particle left,
+// x - e_ax (specular reflection).  base points at plane 0 of the nine (f or
+// gbar); xm, xp are the periodic neighbours of x.
 template <class ST>
 __device__ __forceinline__ void pull9(const typename ST::T* __restrict__ base, int64_t P, int nx,
                                       int ny, int wall, int x, int xm, int xp, int r,
@@ -126,32 +137,28 @@ __device__ __forceinline__ void pull9(const typename ST::T* __restrict__ base, i
     using R = typename ST::R;
     const bool bot = wall && r == 0;       // sources of 2, 5, 6 lie below the wall
     const bool top = wall && r == ny - 1;  // sources of 4, 7, 8 lie above the wall
+    const bool slip = wall == WALL_SLIP;
     const int rb = r == 0 ? ny - 1 : r - 1;
     const int rt = r == ny - 1 ? 0 : r + 1;
-    const uint32_t o = (uint32_t)r * (uint32_t)nx, ob = (uint32_t)rb * (uint32_t)nx,
-                   ot = (uint32_t)rt * (uint32_t)nx;
+    const uint32_t o = (uint32_t)r * (uint32_t)nx;
+    // Every source is selected (uniform plane and row, per-lane column) so that
+    // the nine loads issue together without branches.
+    const uint32_t ob = bot ? o : (uint32_t)rb * (uint32_t)nx;
+    const uint32_t ot = top ? o : (uint32_t)rt * (uint32_t)nx;
+    const int p2 = bot ? 4 : 2, p5 = bot ? (slip ? 8 : 7) : 5, p6 = bot ? (slip ? 7 : 8) : 6;
+    const int p4 = top ? 2 : 4, p7 = top ? (slip ? 6 : 5) : 7, p8 = top ? (slip ? 5 : 6) : 8;
+    const int x5 = (bot && !slip) ? x : xm, x6 = (bot && !slip) ? x : xp;
+    const int x7 = (top && !slip) ? x : xp, x8 = (top && !slip) ? x : xm;
     const R w0 = R(4.0 / 9.0) * sh, w1 = R(1.0 / 9.0) * sh, w5 = R(1.0 / 36.0) * sh;
     out[0] = ldo<ST>(base, o + x) + w0;
     out[1] = ldo<ST>(base + P, o + xm) + w1;
     out[3] = ldo<ST>(base + 3 * P, o + xp) + w1;
-    if (!bot) {
-        out[2] = ldo<ST>(base + 2 * P, ob + x) + w1;
-        out[5] = ldo<ST>(base + 5 * P, ob + xm) + w5;
-        out[6] = ldo<ST>(base + 6 * P, ob + xp) + w5;
-    } else {
-        out[2] = ldo<ST>(base + 4 * P, o + x) + w1;
-        out[5] = ldo<ST>(base + 7 * P, o + x) + w5;
-        out[6] = ldo<ST>(base + 8 * P, o + x) + w5;
-    }
-    if (!top) {
-        out[4] = ldo<ST>(base + 4 * P, ot + x) + w1;
-        out[7] = ldo<ST>(base + 7 * P, ot + xp) + w5;
-        out[8] = ldo<ST>(base + 8 * P, ot + xm) + w5;
-    } else {
-        out[4] = ldo<ST>(base + 2 * P, o + x) + w1;
-        out[7] = ldo<ST>(base + 5 * P, o + x) + w5;
-        out[8] = ldo<ST>(base + 6 * P, o + x) + w5;
-    }
+    out[2] = ldo<ST>(base + p2 * P, ob + x) + w1;
+    out[5] = ldo<ST>(base + p5 * P, ob + x5) + w5;
+    out[6] = ldo<ST>(base + p6 * P, ob + x6) + w5;
+    out[4] = ldo<ST>(base + p4 * P, ot + x) + w1;
+    out[7] = ldo<ST>(base + p7 * P, ot + x7) + w5;
+    out[8] = ldo<ST>(base + p8 * P, ot + x8) + w5;
 }
 
 template <class R>
@@ -221,8 +228,23 @@ struct NodeIn {
     R divn;                    // div n (geometric form)
     R dmux, dmuy;              // grad mu_phi (chemical-potential form)
     R dpx, dpy;                // grad pbar
-    R y;                       // row coordinate
+    R kt, dkt;                 // kappa~ at the node's row and d kappa~ / dy (geometric form)
 };
+
+// kappa~ and d kappa~/dy of row y: the linear law kt_a + kt_b y, or the Langmuir
+// law read from the per-row table (computed once per lattice by k_kappa_table;
+// evaluating the logarithm here would cost the FP64 kernel half its occupancy).
+template <class R>
+__device__ __forceinline__ void row_kappa(const KConst<R>& K, const double* ktab, int ny, int y, R& kt,
+                                          R& dkt) {
+    if (ktab) {
+        kt = R(ktab[y]);
+        dkt = R(ktab[ny + y]);
+    } else {
+        kt = K.kt_a + K.kt_b * R(y);
+        dkt = K.kt_b;
+    }
+}
 
 template <class R>
 struct NodeOut {
@@ -246,9 +268,8 @@ __device__ __forceinline__ NodeOut<R> node_macro(const KConst<R>& K, int chem, c
     o.omv = rho * rho * rr;
     R Fsx, Fsy;
     if (!chem) {
-        const R kt = K.kt_a + K.kt_b * in.y;
-        const R a = in.m2 * kt * in.divn;
-        const R b = in.m2 * K.kt_b;
+        const R a = in.m2 * in.kt * in.divn;
+        const R b = in.m2 * in.dkt;
         Fsx = -a * in.nx - b * in.nx * in.ny;
         Fsy = -a * in.ny + b * (R(1) - in.ny * in.ny);
     } else {
@@ -383,12 +404,62 @@ __device__ __forceinline__ void ace_collide(R f[9], R phi, R ux, R uy, R Mth_x, 
     add_Kc(f, R(0), G1, G2, G3, G4, G5, G6, G7, G8);
 }
 
+// --------------------------------------------------- SRT collisions (Sec. 7)
+
+// Single-relaxation-time comparison models: BGK relaxation at one rate toward the
+// second-order Hermite equilibrium with the cascaded scheme's zeroth to second
+// moments, plus the Hermite-2 form of the same source moments times (1 - om/2).
+// With c^2 = 1/3 the expansion of a distribution with moments (a0, a1, A2) is
+// w_a [a0 + 3 e.a1 + 4.5 (A2 - a0/3 I):(e e) - 1.5 tr(A2 - a0/3 I)].
+
+// Hydrodynamic: equilibrium w_a [p + rho (e.u) + rho (1.5 (e.u)^2 - 0.5 u^2)];
+// source w_a [F_p.u + e.F_t + 4.5 A:(e e) - 1.5 tr A] with A the second-order
+// source moments less c^2 F_p.u I.  Rate omv = omega(nu(phi)).
+template <class R>
+__device__ __forceinline__ void hydro_srt(R g[9], const NodeOut<R>& o) {
+    const R ux = o.ux, uy = o.uy, om = o.omv, hw = R(1) - R(0.5) * om;
+    const R Sx = o.Ftx + o.Fpx, Sy = o.Fty + o.Fpy;
+    const R Axx = R(2.0 / 3.0) * Sx * ux, Ayy = R(2.0 / 3.0) * Sy * uy;
+    const R Axy = R(1.0 / 3.0) * (Sx * uy + Sy * ux);
+    const R peq = o.p - R(0.5) * o.rho * (ux * ux + uy * uy);
+    const R s0 = (o.Fpx * ux + o.Fpy * uy) - R(1.5) * (Axx + Ayy);
+    auto upd = [&](int a, R w, int ex, int ey) {
+        const R eu = R(ex) * ux + R(ey) * uy;
+        const R eF = R(ex) * o.Ftx + R(ey) * o.Fty;
+        const R AE = R(ex * ex) * Axx + R(ey * ey) * Ayy + R(2 * ex * ey) * Axy;
+        const R geq = w * (peq + o.rho * (eu + R(1.5) * eu * eu));
+        const R src = w * (s0 + eF + R(4.5) * AE);
+        g[a] += om * (geq - g[a]) + hw * src;
+    };
+    const R w0 = R(4.0 / 9.0), w1 = R(1.0 / 9.0), w5 = R(1.0 / 36.0);
+    upd(0, w0, 0, 0);
+    upd(1, w1, 1, 0); upd(2, w1, 0, 1); upd(3, w1, -1, 0); upd(4, w1, 0, -1);
+    upd(5, w5, 1, 1); upd(6, w5, -1, 1); upd(7, w5, -1, -1); upd(8, w5, 1, -1);
+}
+
+// Conservative Allen-Cahn: equilibrium w_a [phi (1 + 3 e.u + 4.5 (e.u)^2 - 1.5 u^2)
+// + 3 e.(M theta n)], every moment at rate omphi.
+template <class R>
+__device__ __forceinline__ void ace_srt(R f[9], R phi, R ux, R uy, R Mth_x, R Mth_y, R om) {
+    const R base = phi * (R(1) - R(1.5) * (ux * ux + uy * uy));
+    auto upd = [&](int a, R w, int ex, int ey) {
+        const R eu = R(ex) * ux + R(ey) * uy;
+        const R en = R(ex) * Mth_x + R(ey) * Mth_y;
+        const R feq = w * (base + phi * (R(3) * eu + R(4.5) * eu * eu) + R(3) * en);
+        f[a] += om * (feq - f[a]);
+    };
+    const R w0 = R(4.0 / 9.0), w1 = R(1.0 / 9.0), w5 = R(1.0 / 36.0);
+    upd(0, w0, 0, 0);
+    upd(1, w1, 1, 0); upd(2, w1, 0, 1); upd(3, w1, -1, 0); upd(4, w1, 0, -1);
+    upd(5, w5, 1, 1); upd(6, w5, -1, 1); upd(7, w5, -1, -1); upd(8, w5, 1, -1);
+}
+
 // ------------------------------------------------------------- fused kernel
 
 // PF: once a lane has stored its post-collision f (and later gbar), the freed
 // registers receive the next row's pulled values, so those loads are in flight
 // while the rest of the collision computes (no extra registers).
-template <class ST, int TX, int MODE, bool PF>
+template <class ST, int TX, int MODE, bool PF, int COLL = COLL_CASCADED>
 __global__ void __launch_bounds__(TX) lb_fused(const LatDesc* __restrict__ descs,
                                                const WorkItem* __restrict__ items, int n_items,
                                                int parity) {
@@ -407,6 +478,7 @@ __global__ void __launch_bounds__(TX) lb_fused(const LatDesc* __restrict__ descs
         const int nx = D.nx, ny = D.ny, wall = D.wall_y, chem = D.st_form;
         const int64_t P = D.plane;
         const KConst<R> K = load_const<R>(D);
+        const double* ktab = D.surf ? D.ktab : nullptr;  // per-row Langmuir table
         const T* __restrict__ src = reinterpret_cast<const T*>(D.buf[parity]);
         T* __restrict__ dst = reinterpret_cast<T*>(D.buf[parity ^ 1]);
         const T* __restrict__ srcg = src + 9 * P;
@@ -478,7 +550,7 @@ __global__ void __launch_bounds__(TX) lb_fused(const LatDesc* __restrict__ descs
                     in.phi = s_phi[C & 3][t];
                     in.pbar = s_pb[C & 3][t];
                     in.dphx = pdx; in.dphy = pdy; in.m2 = pm2; in.nx = pnx; in.ny = pny;
-                    in.y = R(C);
+                    row_kappa(K, ktab, ny, C, in.kt, in.dkt);
                     in.divn = R(0); in.dmux = R(0); in.dmuy = R(0);
                     grad3x3(s_pb[(C - 1) & 3], s_pb[C & 3], s_pb[(C + 1) & 3], t, in.dpx, in.dpy);
                     if (chem) {
@@ -496,7 +568,10 @@ __global__ void __launch_bounds__(TX) lb_fused(const LatDesc* __restrict__ descs
                     const R w0 = R(4.0 / 9.0), w1 = R(1.0 / 9.0), w5 = R(1.0 / 36.0);
                     if (inF) {
                         const R Mth = K.M * (K.four_W * in.phi * (R(1) - in.phi));
-                        ace_collide<R>(f2, in.phi, o.ux, o.uy, Mth * in.nx, Mth * in.ny, K.omphi);
+                        if constexpr (COLL == COLL_SRT)
+                            ace_srt<R>(f2, in.phi, o.ux, o.uy, Mth * in.nx, Mth * in.ny, K.omphi);
+                        else
+                            ace_collide<R>(f2, in.phi, o.ux, o.uy, Mth * in.nx, Mth * in.ny, K.omphi);
 #pragma unroll
                         for (int a = 0; a < 9; ++a) {
                             const R wa = a == 0 ? w0 : (a < 5 ? w1 : w5);
@@ -506,7 +581,10 @@ __global__ void __launch_bounds__(TX) lb_fused(const LatDesc* __restrict__ descs
                     if (pre && inA)  // next leading row into the freed f registers
                         pull9<ST>(src, P, nx, ny, wall, xc, xm, xp, map_row(L + 1, ny, wall), K.shf, f2);
                     if (inF) {
-                        hydro_collide<R>(g1, o);
+                        if constexpr (COLL == COLL_SRT)
+                            hydro_srt<R>(g1, o);
+                        else
+                            hydro_collide<R>(g1, o);
 #pragma unroll
                         for (int a = 0; a < 9; ++a) {
                             const R wa = a == 0 ? w0 : (a < 5 ? w1 : w5);
@@ -559,6 +637,97 @@ __global__ void __launch_bounds__(TX) lb_fused(const LatDesc* __restrict__ descs
             pdx = cdx; pdy = cdy; pm2 = cm2; pnx = cnx; pny = cny;
         }
         __syncthreads();  // the rings are reused by the next work item
+    }
+}
+
+// ------------------------------------------------- phase field only (Sec. 6.1)
+
+// The conservative Allen-Cahn step alone under an imposed velocity (planes ux, uy
+// of the compute type at D.vel, stride D.plane).  Same work items and lane layout
+// as lb_fused (lane t at column x0 - 2 + t, strips of TX - 4 columns); the
+// pipeline lags one row: pull f at row L into the phi ring, then take grad phi,
+// n and theta at row L - 1 and collide it.  One barrier per row suffices with a
+// ring of four rows.  COLL selects the cascaded or the SRT collision.
+template <class ST, int TX, int MODE, int COLL>
+__global__ void __launch_bounds__(TX) lb_ace(const LatDesc* __restrict__ descs,
+                                             const WorkItem* __restrict__ items, int n_items,
+                                             int parity) {
+    using R = typename ST::R;
+    using T = typename ST::T;
+    __shared__ R s_phi[4][TX];
+    const int t = threadIdx.x;
+
+    for (int wi = blockIdx.x; wi < n_items; wi += gridDim.x) {
+        const WorkItem it = items[wi];
+        if (it.y1 <= it.y0) continue;
+        const LatDesc& D = descs[it.inst];
+        const int nx = D.nx, ny = D.ny, wall = D.wall_y;
+        const int64_t P = D.plane;
+        const R shf = R(D.shift_f), four_W = R(D.four_W), Mm = R(D.M), omphi = R(D.omphi);
+        const T* __restrict__ src = reinterpret_cast<const T*>(D.buf[parity]);
+        T* __restrict__ dst = reinterpret_cast<T*>(D.buf[parity ^ 1]);
+        const R* __restrict__ vel = reinterpret_cast<const R*>(D.vel);
+        const int w = min(TX - 4, nx - it.x0);
+        const bool inA = t < w + 4;
+        const bool inF = t >= 2 && t < w + 2;
+        int xc = it.x0 - 2 + t;
+        xc = xc < 0 ? xc + nx : (xc >= nx ? xc - nx : xc);
+        const int xm = xc == 0 ? nx - 1 : xc - 1;
+        const int xp = xc == nx - 1 ? 0 : xc + 1;
+
+        R f0[9], f1[9];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) { f0[a] = f1[a] = R(0); }
+        const int H = it.y1 - it.y0;
+        for (int k = 0; k < H + 2; ++k) {
+            const int L = it.y0 - 1 + k;
+            if (inA) {
+                pull9<ST>(src, P, nx, ny, wall, xc, xm, xp, map_row(L, ny, wall), shf, f0);
+                s_phi[L & 3][t] = sum9(f0);
+            }
+            __syncthreads();
+            if (k >= 2 && inF) {
+                const int C = L - 1;
+                const R phi = s_phi[C & 3][t];
+                R gx, gy, ix, iy;
+                grad3x3(s_phi[(C - 1) & 3], s_phi[C & 3], s_phi[(C + 1) & 3], t, gx, gy);
+                const R m2 = gx * gx + gy * gy;
+                unit_normal(gx, gy, m2, ix, iy);
+                const uint32_t idx = (uint32_t)C * (uint32_t)nx + (uint32_t)xc;
+                const R ux = vel[idx], uy = vel[P + idx];
+                if constexpr (MODE == MODE_STEP) {
+                    const R Mth = Mm * (four_W * phi * (R(1) - phi));
+                    if constexpr (COLL == COLL_SRT)
+                        ace_srt<R>(f1, phi, ux, uy, Mth * ix, Mth * iy, omphi);
+                    else
+                        ace_collide<R>(f1, phi, ux, uy, Mth * ix, Mth * iy, omphi);
+                    const R w0 = R(4.0 / 9.0), w1 = R(1.0 / 9.0), w5 = R(1.0 / 36.0);
+#pragma unroll
+                    for (int a = 0; a < 9; ++a) {
+                        const R wa = a == 0 ? w0 : (a < 5 ? w1 : w5);
+                        sto<ST>(dst + a * P, idx, f1[a] - wa * shf);
+                    }
+                } else {
+                    double* F = D.fields;
+                    const int64_t N = (int64_t)nx * ny;
+                    if constexpr (MODE == MODE_FIELDS) {
+                        F[idx] = (double)phi;
+                        F[N + idx] = 0.0;
+                        F[2 * N + idx] = (double)ux;
+                        F[3 * N + idx] = (double)uy;
+                    } else {
+                        F[idx] = (double)gx;
+                        F[N + idx] = (double)gy;
+                        F[2 * N + idx] = (double)ix;
+                        F[3 * N + idx] = (double)iy;
+                        for (int q = 4; q < 9; ++q) F[q * N + idx] = 0.0;
+                    }
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < 9; ++a) f1[a] = f0[a];
+        }
+        __syncthreads();
     }
 }
 

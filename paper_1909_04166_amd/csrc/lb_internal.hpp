@@ -8,18 +8,23 @@
 
 namespace cmlb {
 
-// pf != 0 selects the variant that prefetches the next rows during the collision.
-hipError_t launch_step(int prec, int tx, int pf, const LatDesc* d, const WorkItem* items, int n_items,
-                       int grid, int parity, hipStream_t s);
-hipError_t launch_extract(int prec, int mode, const LatDesc* d, const WorkItem* items64,
+// kind: KIND_*; pf != 0 selects the variant that prefetches the next rows during
+// the collision (coupled cascaded kind only).
+hipError_t launch_step(int prec, int kind, int tx, int pf, const LatDesc* d, const WorkItem* items,
+                       int n_items, int grid, int parity, hipStream_t s);
+hipError_t launch_extract(int prec, int kind, int mode, const LatDesc* d, const WorkItem* items64,
                           int n_items, int parity, hipStream_t s);
+// stage: FP64 ux plane then uy plane, N values each.
+hipError_t launch_set_velocity(int prec, const LatDesc* d, const double* stage, int64_t N, hipStream_t s);
+// Per-row Langmuir table of a lattice (d->ktab, 2 ny doubles).
+hipError_t launch_kappa_table(const LatDesc* d, int ny, hipStream_t s);
 // op 0: init from phi0 plane; 1: set stored plane from staged plane a; 2: get plane a
 hipError_t launch_state_op(int prec, int op, const LatDesc* d, double* plane, int a, int which,
                            int cur, int64_t N, hipStream_t s);
 hipError_t launch_diag(const LatDesc* d, const double* fields, double* part, double* out, int ny,
                        double step, double u_max, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, uint64_t n, hipStream_t s);
-// Resident workgroups per CU of the fused step kernel (from the HIP occupancy API).
-int fused_occupancy(int prec, int tx, int pf);
+// Resident workgroups per CU of a step kernel (from the HIP occupancy API).
+int step_occupancy(int prec, int kind, int tx, int pf);
 
 }  // namespace cmlb

@@ -5,80 +5,125 @@ namespace cmlb {
 
 // ------------------------------------------------------------ fused step
 
-template <class ST, int MODE, bool PF>
-static hipError_t launch_fused_tx(int tx, const LatDesc* d, const WorkItem* items, int n_items,
-                                  int grid, int parity, hipStream_t s) {
+// The kernel behind a step: the coupled pair (lb_fused) or the phase field alone
+// (lb_ace), with the cascaded or the SRT collisions.  The SRT variants exist
+// without row prefetching only.
+template <class ST, int TX, int MODE, bool PF, int KIND>
+static void launch_one(dim3 grid, const LatDesc* d, const WorkItem* items, int n_items, int parity,
+                       hipStream_t s) {
+    if constexpr (KIND == KIND_COUPLED_CASCADED)
+        hipLaunchKernelGGL((lb_fused<ST, TX, MODE, PF, COLL_CASCADED>), grid, dim3(TX), 0, s, d, items, n_items, parity);
+    else if constexpr (KIND == KIND_COUPLED_SRT)
+        hipLaunchKernelGGL((lb_fused<ST, TX, MODE, false, COLL_SRT>), grid, dim3(TX), 0, s, d, items, n_items, parity);
+    else if constexpr (KIND == KIND_ACE_CASCADED)
+        hipLaunchKernelGGL((lb_ace<ST, TX, MODE, COLL_CASCADED>), grid, dim3(TX), 0, s, d, items, n_items, parity);
+    else
+        hipLaunchKernelGGL((lb_ace<ST, TX, MODE, COLL_SRT>), grid, dim3(TX), 0, s, d, items, n_items, parity);
+}
+
+template <class ST, int MODE, bool PF, int KIND>
+static hipError_t launch_tx(int tx, const LatDesc* d, const WorkItem* items, int n_items, int grid,
+                            int parity, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
     if (grid <= 0 || grid > n_items) grid = n_items;
     switch (tx) {
-    case 64: hipLaunchKernelGGL((lb_fused<ST, 64, MODE, PF>), dim3(grid), dim3(64), 0, s, d, items, n_items, parity); break;
-    case 128: hipLaunchKernelGGL((lb_fused<ST, 128, MODE, PF>), dim3(grid), dim3(128), 0, s, d, items, n_items, parity); break;
-    case 256: hipLaunchKernelGGL((lb_fused<ST, 256, MODE, PF>), dim3(grid), dim3(256), 0, s, d, items, n_items, parity); break;
+    case 64: launch_one<ST, 64, MODE, PF, KIND>(dim3(grid), d, items, n_items, parity, s); break;
+    case 128: launch_one<ST, 128, MODE, PF, KIND>(dim3(grid), d, items, n_items, parity, s); break;
+    case 256: launch_one<ST, 256, MODE, PF, KIND>(dim3(grid), d, items, n_items, parity, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 template <class ST>
-static hipError_t launch_step_st(int tx, int pf, const LatDesc* d, const WorkItem* items, int n_items,
-                                 int grid, int parity, hipStream_t s) {
-    return pf ? launch_fused_tx<ST, MODE_STEP, true>(tx, d, items, n_items, grid, parity, s)
-              : launch_fused_tx<ST, MODE_STEP, false>(tx, d, items, n_items, grid, parity, s);
-}
-
-hipError_t launch_step(int prec, int tx, int pf, const LatDesc* d, const WorkItem* items, int n_items,
-                       int grid, int parity, hipStream_t s) {
-    switch (prec) {
-    case LB_FP64: return launch_step_st<StF64>(tx, pf, d, items, n_items, grid, parity, s);
-    case LB_FP32: return launch_step_st<StF32>(tx, pf, d, items, n_items, grid, parity, s);
-    case LB_FP32_F16: return launch_step_st<StF16>(tx, pf, d, items, n_items, grid, parity, s);
-    case LB_FP32_BF16: return launch_step_st<StBF16>(tx, pf, d, items, n_items, grid, parity, s);
+static hipError_t launch_step_st(int kind, int tx, int pf, const LatDesc* d, const WorkItem* items,
+                                 int n_items, int grid, int parity, hipStream_t s) {
+    switch (kind) {
+    case KIND_COUPLED_CASCADED:
+        return pf ? launch_tx<ST, MODE_STEP, true, KIND_COUPLED_CASCADED>(tx, d, items, n_items, grid, parity, s)
+                  : launch_tx<ST, MODE_STEP, false, KIND_COUPLED_CASCADED>(tx, d, items, n_items, grid, parity, s);
+    case KIND_COUPLED_SRT:
+        return launch_tx<ST, MODE_STEP, false, KIND_COUPLED_SRT>(tx, d, items, n_items, grid, parity, s);
+    case KIND_ACE_CASCADED:
+        return launch_tx<ST, MODE_STEP, false, KIND_ACE_CASCADED>(tx, d, items, n_items, grid, parity, s);
+    case KIND_ACE_SRT:
+        return launch_tx<ST, MODE_STEP, false, KIND_ACE_SRT>(tx, d, items, n_items, grid, parity, s);
     }
     return hipErrorInvalidValue;
 }
 
-template <class ST, bool PF>
-static int occ_tx(int tx) {
-    int nb = 0;
-    hipError_t e = hipErrorInvalidValue;
-    switch (tx) {
-    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lb_fused<ST, 64, MODE_STEP, PF>, 64, 0); break;
-    case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lb_fused<ST, 128, MODE_STEP, PF>, 128, 0); break;
-    case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lb_fused<ST, 256, MODE_STEP, PF>, 256, 0); break;
+hipError_t launch_step(int prec, int kind, int tx, int pf, const LatDesc* d, const WorkItem* items,
+                       int n_items, int grid, int parity, hipStream_t s) {
+    switch (prec) {
+    case LB_FP64: return launch_step_st<StF64>(kind, tx, pf, d, items, n_items, grid, parity, s);
+    case LB_FP32: return launch_step_st<StF32>(kind, tx, pf, d, items, n_items, grid, parity, s);
+    case LB_FP32_F16: return launch_step_st<StF16>(kind, tx, pf, d, items, n_items, grid, parity, s);
+    case LB_FP32_BF16: return launch_step_st<StBF16>(kind, tx, pf, d, items, n_items, grid, parity, s);
     }
-    return e == hipSuccess ? nb : 1;
+    return hipErrorInvalidValue;
 }
 
-int fused_occupancy(int prec, int tx, int pf) {
-    switch (prec) {
-    case LB_FP64: return pf ? occ_tx<StF64, true>(tx) : occ_tx<StF64, false>(tx);
-    case LB_FP32: return pf ? occ_tx<StF32, true>(tx) : occ_tx<StF32, false>(tx);
-    case LB_FP32_F16: return pf ? occ_tx<StF16, true>(tx) : occ_tx<StF16, false>(tx);
-    case LB_FP32_BF16: return pf ? occ_tx<StBF16, true>(tx) : occ_tx<StBF16, false>(tx);
+template <class F>
+static int occ_of(F kern, int tx) {
+    int nb = 0;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, tx, 0) == hipSuccess ? nb : 1;
+}
+
+template <class ST, int TX>
+static int occ_kind(int kind, int pf) {
+    switch (kind) {
+    case KIND_COUPLED_CASCADED:
+        return pf ? occ_of(lb_fused<ST, TX, MODE_STEP, true, COLL_CASCADED>, TX)
+                  : occ_of(lb_fused<ST, TX, MODE_STEP, false, COLL_CASCADED>, TX);
+    case KIND_COUPLED_SRT: return occ_of(lb_fused<ST, TX, MODE_STEP, false, COLL_SRT>, TX);
+    case KIND_ACE_CASCADED: return occ_of(lb_ace<ST, TX, MODE_STEP, COLL_CASCADED>, TX);
+    case KIND_ACE_SRT: return occ_of(lb_ace<ST, TX, MODE_STEP, COLL_SRT>, TX);
     }
     return 1;
 }
 
-// Fields / coupling extraction always runs with 64-wide strips.
-hipError_t launch_extract(int prec, int mode, const LatDesc* d, const WorkItem* items64,
-                          int n_items, int parity, hipStream_t s) {
-    if (n_items <= 0) return hipSuccess;
-#define CMLB_EXTRACT(ST)                                                                          \
-    if (mode == MODE_FIELDS)                                                                      \
-        hipLaunchKernelGGL((lb_fused<ST, 64, MODE_FIELDS, false>), dim3(n_items), dim3(64), 0, s, d,   \
-                           items64, n_items, parity);                                             \
-    else                                                                                          \
-        hipLaunchKernelGGL((lb_fused<ST, 64, MODE_COUPLING, false>), dim3(n_items), dim3(64), 0, s, d, \
-                           items64, n_items, parity);
-    switch (prec) {
-    case LB_FP64: CMLB_EXTRACT(StF64); break;
-    case LB_FP32: CMLB_EXTRACT(StF32); break;
-    case LB_FP32_F16: CMLB_EXTRACT(StF16); break;
-    case LB_FP32_BF16: CMLB_EXTRACT(StBF16); break;
-    default: return hipErrorInvalidValue;
+template <class ST>
+static int occ_st(int kind, int tx, int pf) {
+    switch (tx) {
+    case 64: return occ_kind<ST, 64>(kind, pf);
+    case 128: return occ_kind<ST, 128>(kind, pf);
+    case 256: return occ_kind<ST, 256>(kind, pf);
     }
-#undef CMLB_EXTRACT
-    return hipGetLastError();
+    return 1;
+}
+
+int step_occupancy(int prec, int kind, int tx, int pf) {
+    switch (prec) {
+    case LB_FP64: return occ_st<StF64>(kind, tx, pf);
+    case LB_FP32: return occ_st<StF32>(kind, tx, pf);
+    case LB_FP32_F16: return occ_st<StF16>(kind, tx, pf);
+    case LB_FP32_BF16: return occ_st<StBF16>(kind, tx, pf);
+    }
+    return 1;
+}
+
+// Fields / coupling extraction always runs with 64-wide strips.  The coupled
+// kinds share one extraction kernel (the fields do not depend on the collision).
+template <class ST>
+static hipError_t launch_extract_st(int kind, int mode, const LatDesc* d, const WorkItem* items64,
+                                    int n_items, int parity, hipStream_t s) {
+    const bool ace = kind == KIND_ACE_CASCADED || kind == KIND_ACE_SRT;
+    if (mode == MODE_FIELDS)
+        return ace ? launch_tx<ST, MODE_FIELDS, false, KIND_ACE_CASCADED>(64, d, items64, n_items, 0, parity, s)
+                   : launch_tx<ST, MODE_FIELDS, false, KIND_COUPLED_CASCADED>(64, d, items64, n_items, 0, parity, s);
+    return ace ? launch_tx<ST, MODE_COUPLING, false, KIND_ACE_CASCADED>(64, d, items64, n_items, 0, parity, s)
+               : launch_tx<ST, MODE_COUPLING, false, KIND_COUPLED_CASCADED>(64, d, items64, n_items, 0, parity, s);
+}
+
+hipError_t launch_extract(int prec, int kind, int mode, const LatDesc* d, const WorkItem* items64,
+                          int n_items, int parity, hipStream_t s) {
+    switch (prec) {
+    case LB_FP64: return launch_extract_st<StF64>(kind, mode, d, items64, n_items, parity, s);
+    case LB_FP32: return launch_extract_st<StF32>(kind, mode, d, items64, n_items, parity, s);
+    case LB_FP32_F16: return launch_extract_st<StF16>(kind, mode, d, items64, n_items, parity, s);
+    case LB_FP32_BF16: return launch_extract_st<StBF16>(kind, mode, d, items64, n_items, parity, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 // ------------------------------------------------ state set-up and read-out
@@ -92,10 +137,24 @@ __device__ __forceinline__ int ey_of(int a) {
 __device__ __forceinline__ int opp_of(int a) {
     return a == 0 ? 0 : (a <= 4 ? ((a + 1) & 3) + 1 : ((a - 3) & 3) + 5);
 }
+// Direction with e_y reversed (specular reflection at a wall y = const).
+__device__ __forceinline__ int miry_of(int a) {
+    switch (a) {
+    case 2: return 4;
+    case 4: return 2;
+    case 5: return 8;
+    case 8: return 5;
+    case 6: return 7;
+    case 7: return 6;
+    }
+    return a;
+}
+__device__ __forceinline__ int wrapx(int x, int nx) { return x < 0 ? x + nx : (x >= nx ? x - nx : x); }
 
 // Stored (pre-streaming) value of direction a at node (x, y) such that pulling
-// gives the post-streaming value val(b, x', y'):  f~_a(x) = f_a(x + e_a), or
-// f_{opp a}(x) when x + e_a lies beyond a halfway wall.
+// gives the post-streaming value val(b, x', y'):  f~_a(x) = f_a(x + e_a); when
+// x + e_a lies beyond a halfway wall, f_{opp a}(x) (bounce-back) or
+// f_{mir a}(x + e_ax, y) (specular).
 // The state at t = 0 is f_a = w_a phi0, gbar_a = 0.
 template <class ST>
 __global__ void k_init(const LatDesc* __restrict__ dp, const double* __restrict__ phi0, int cur) {
@@ -112,7 +171,8 @@ __global__ void k_init(const LatDesc* __restrict__ dp, const double* __restrict_
             xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
             double ph;
             if (ys < 0 || ys >= ny) {
-                if (D.wall_y) ph = phi0[k];  // f_{opp a}(x) = w phi0(x), w_opp = w_a
+                if (D.wall_y == WALL_SLIP) ph = phi0[(int64_t)y * nx + xs];  // w_mir = w_a
+                else if (D.wall_y) ph = phi0[k];  // f_{opp a}(x) = w phi0(x), w_opp = w_a
                 else ph = phi0[(int64_t)(ys < 0 ? ys + ny : ys - ny) * nx + xs];
             } else {
                 ph = phi0[(int64_t)ys * nx + xs];
@@ -125,8 +185,9 @@ __global__ void k_init(const LatDesc* __restrict__ dp, const double* __restrict_
 }
 
 // Writes the stored planes from one staged post-streaming FP64 plane b of f
-// (which = 0) or gbar (which = 1): f~_b(x) = f_b(x + e_b) where x + e_b is inside,
-// and f~_{opp b}(x) = f_b(x) where x - e_b lies beyond a wall.
+// (which = 0) or gbar (which = 1): f~_b(x) = f_b(x + e_b) where x + e_b is inside;
+// where x - e_b lies beyond a wall, f~_{opp b}(x) = f_b(x) (bounce-back) or
+// f~_{mir b}(x - e_bx, y) = f_b(x) (specular).  Every stored value is written once.
 template <class ST>
 __global__ void k_set_plane(const LatDesc* __restrict__ dp, const double* __restrict__ stage,
                             int b, int which, int cur) {
@@ -148,8 +209,14 @@ __global__ void k_set_plane(const LatDesc* __restrict__ dp, const double* __rest
         }
         const int yb = y - ey_of(b);
         if (D.wall_y && (yb < 0 || yb >= ny)) {
-            const int o = opp_of(b);
-            buf[o * D.plane + k] = ST::st((typename ST::R)(stage[k] - wgt(o) * sh));
+            if (D.wall_y == WALL_SLIP) {
+                const int m = miry_of(b);
+                const int64_t kr = (int64_t)y * nx + wrapx(x - ex_of(b), nx);
+                buf[m * D.plane + kr] = ST::st((typename ST::R)(stage[k] - wgt(m) * sh));
+            } else {
+                const int o = opp_of(b);
+                buf[o * D.plane + k] = ST::st((typename ST::R)(stage[k] - wgt(o) * sh));
+            }
         }
     }
 }
@@ -171,7 +238,10 @@ __global__ void k_get_plane(const LatDesc* __restrict__ dp, double* __restrict__
         xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
         const bool outside = ys < 0 || ys >= ny;
         double v;
-        if (outside && D.wall_y) {
+        if (outside && D.wall_y == WALL_SLIP) {
+            const int m = miry_of(a);
+            v = (double)ST::ld(buf[m * D.plane + (int64_t)y * nx + xs]) + wgt(m) * sh;
+        } else if (outside && D.wall_y) {
             const int o = opp_of(a);
             v = (double)ST::ld(buf[o * D.plane + k]) + wgt(o) * sh;
         } else {
@@ -180,6 +250,47 @@ __global__ void k_get_plane(const LatDesc* __restrict__ dp, double* __restrict__
         }
         out[k] = v;
     }
+}
+
+// Langmuir law per row (Eq. Langmuirisotherm): kappa~(y) = kt0 (1 + beta ln(1 - psi))
+// with psi = ps_a + ps_G y, and its derivative -kt0 beta ps_G / (1 - psi).
+__global__ void k_kappa_table(const LatDesc* __restrict__ dp) {
+    const LatDesc& D = *dp;
+    for (int y = blockIdx.x * blockDim.x + threadIdx.x; y < D.ny; y += gridDim.x * blockDim.x) {
+        const double q = 1.0 - (D.ps_a + D.ps_G * (double)y);
+        D.ktab[y] = D.kt0 * (1.0 + D.lbeta * log(q));
+        D.ktab[D.ny + y] = -D.kt0 * D.lbeta * D.ps_G / q;
+    }
+}
+
+hipError_t launch_kappa_table(const LatDesc* d, int ny, hipStream_t s) {
+    int g = (ny + 255) / 256;
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(k_kappa_table, dim3(g), dim3(256), 0, s, d);
+    return hipGetLastError();
+}
+
+// Imposed velocity: staged FP64 planes ux, uy (N each) into the compute-type planes.
+template <class R>
+__global__ void k_set_vel(const LatDesc* __restrict__ dp, const double* __restrict__ stage) {
+    const LatDesc& D = *dp;
+    const int64_t N = (int64_t)D.nx * D.ny;
+    R* vel = reinterpret_cast<R*>(D.vel);
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < N;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        vel[k] = (R)stage[k];
+        vel[D.plane + k] = (R)stage[N + k];
+    }
+}
+
+hipError_t launch_set_velocity(int prec, const LatDesc* d, const double* stage, int64_t N, hipStream_t s) {
+    const int bs = 256;
+    int64_t g = (N + bs - 1) / bs;
+    if (g > 65536) g = 65536;
+    if (g < 1) g = 1;
+    if (prec == LB_FP64) hipLaunchKernelGGL((k_set_vel<double>), dim3((int)g), dim3(bs), 0, s, d, stage);
+    else hipLaunchKernelGGL((k_set_vel<float>), dim3((int)g), dim3(bs), 0, s, d, stage);
+    return hipGetLastError();
 }
 
 template <class ST>

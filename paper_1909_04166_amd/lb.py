@@ -18,7 +18,11 @@ LIB_PATH = os.path.join(_HERE, "libcmlb.so")
 
 LB_OK, LB_E_INVALID_ARG, LB_E_WORKSPACE, LB_E_HIP, LB_E_UNSTABLE, LB_E_UNSUPPORTED, LB_E_STATE = (
     0, -1, -2, -3, -4, -5, -6)
-LB_PERIODIC, LB_HALFWAY_BB = 0, 1
+LB_PERIODIC, LB_HALFWAY_BB, LB_FREE_SLIP = 0, 1, 2
+LB_BC = {"periodic": LB_PERIODIC, "wall": LB_HALFWAY_BB, "slip": LB_FREE_SLIP}
+LB_COLLISION = {"cascaded": 0, "srt": 1}
+LB_FLOW = {"coupled": 0, "imposed": 1}
+LB_SIGMA = {"linear": 0, "langmuir": 1}
 LB_FREF = {"mean": 0, "light": 1, "heavy": 2, "none": 3}
 LB_ST = {"geometric": 0, "chempot": 1}
 PRECISION = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
@@ -40,6 +44,9 @@ class lb_config(ctypes.Structure):
         ("shift_f", ctypes.c_double), ("shift_g", ctypes.c_double),
         ("u_max", ctypes.c_double),
         ("tile_x", ctypes.c_int32), ("tile_h", ctypes.c_int32),
+        ("collision", ctypes.c_int32), ("flow", ctypes.c_int32),
+        ("surf", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("beta", ctypes.c_double), ("psi_a", ctypes.c_double), ("psi_G", ctypes.c_double),
     ]
 
 
@@ -71,6 +78,7 @@ _SIGS = {
     "lb_workspace_bytes": ([ctypes.POINTER(lb_config), _u64p], ctypes.c_int32),
     "lb_create": ([ctypes.POINTER(lb_config), _vp, ctypes.c_uint64, _vp, ctypes.POINTER(_vp)], ctypes.c_int32),
     "lb_init_fields": ([_vp, _dp], ctypes.c_int32),
+    "lb_set_velocity": ([_vp, _dp, _dp], ctypes.c_int32),
     "lb_step": ([_vp, ctypes.c_int64], ctypes.c_int32),
     "lb_get_fields": ([_vp, _dp, _dp, _dp, _dp], ctypes.c_int32),
     "lb_get_coupling": ([_vp, _vp], ctypes.c_int32),
@@ -142,7 +150,7 @@ def config_from_case(case: dict, precision: str = "fp64", diag_every: int = 0,
     c = lb_config()
     c.nx, c.ny = int(case["nx"]), int(case["ny"])
     c.bc_x = LB_PERIODIC
-    c.bc_y = LB_HALFWAY_BB if case.get("bc_y", "periodic") == "wall" else LB_PERIODIC
+    c.bc_y = LB_BC[case.get("bc_y", "periodic")]
     c.force_ref = LB_FREF[case.get("force_ref", "mean")]
     c.st_form = LB_ST[case.get("st_form", "geometric")]
     c.precision = PRECISION[precision]
@@ -155,6 +163,11 @@ def config_from_case(case: dict, precision: str = "fp64", diag_every: int = 0,
     c.gx, c.gy = float(case.get("gx", 0.0)), float(case.get("gy", 0.0))
     c.shift_f, c.shift_g, c.u_max = float(shift_f), float(shift_g), float(u_max)
     c.tile_x, c.tile_h = int(tile[0]), int(tile[1])
+    c.collision = LB_COLLISION[case.get("collision", "cascaded")]
+    c.flow = LB_FLOW[case.get("flow", "coupled")]
+    c.surf = LB_SIGMA[case.get("surf", "linear")]
+    c.beta = float(case.get("beta", 0.0))
+    c.psi_a, c.psi_G = float(case.get("psi_a", 0.0)), float(case.get("psi_G", 0.0))
     return c
 
 
@@ -175,6 +188,13 @@ def lb_create(cfg: lb_config, ws_ptr: int, ws_bytes: int, stream: int) -> int:
 def lb_init_fields(h: int, phi0: np.ndarray) -> None:
     a = np.ascontiguousarray(phi0, dtype=np.float64)
     _check("lb_init_fields", lib().lb_init_fields(_vp(h), _dptr(a)))
+
+
+def lb_set_velocity(h: int, ux: np.ndarray, uy: np.ndarray) -> None:
+    a = np.ascontiguousarray(ux, dtype=np.float64)
+    b = np.ascontiguousarray(uy, dtype=np.float64)
+    assert a.shape == b.shape
+    _check("lb_set_velocity", lib().lb_set_velocity(_vp(h), _dptr(a), _dptr(b)))
 
 
 def lb_step(h: int, n: int) -> int:
@@ -208,9 +228,9 @@ def lb_get_dist(h: int, shape) -> tuple:
     return f, g
 
 
-def lb_set_dist(h: int, f: np.ndarray, g: np.ndarray, step: int = 0) -> None:
+def lb_set_dist(h: int, f: np.ndarray, g: np.ndarray | None, step: int = 0) -> None:
     f = np.ascontiguousarray(f, dtype=np.float64)
-    g = np.ascontiguousarray(g, dtype=np.float64)
+    g = None if g is None else np.ascontiguousarray(g, dtype=np.float64)
     _check("lb_set_dist", lib().lb_set_dist(_vp(h), _dptr(f), _dptr(g), int(step)))
 
 
@@ -377,6 +397,11 @@ class Lattice:
 
     def step(self, n: int = 1) -> int:
         return lb_step(self.h, n)
+
+    def set_velocity(self, ux: np.ndarray, uy: np.ndarray) -> None:
+        """Imposed velocity of a phase-field-only lattice (flow = "imposed")."""
+        lb_set_velocity(self.h, np.asarray(ux, dtype=np.float64).reshape(self.shape),
+                        np.asarray(uy, dtype=np.float64).reshape(self.shape))
 
     def fields(self):
         return lb_get_fields(self.h, self.shape)

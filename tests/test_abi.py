@@ -76,3 +76,38 @@ def test_batch_workspace_bytes():
     assert b > a > 2 * 18 * 4 * (1 << 16)
     with pytest.raises(lb.LBError):
         lb.lb_batch_workspace_bytes(0, 1 << 16, "fp32")
+
+
+def test_option_validation():
+    """Collision model, flow mode, wall kind and surface-tension law are checked on
+    the host: unknown values are invalid, the Langmuir law needs 1 - psi > 0 on
+    every row and the geometric form, and the imposed-flow mode adds the two
+    velocity planes to the workspace."""
+    case, _ = W.surfactant_young()
+    cfg = lb.config_from_case(case, "fp64")
+    base = lb.lb_workspace_bytes(cfg)
+
+    def code(**kw):
+        c = lb.config_from_case(case, "fp64")
+        for k, v in kw.items():
+            setattr(c, k, v)
+        try:
+            lb.lb_workspace_bytes(c)
+            return lb.LB_OK
+        except lb.LBError as e:
+            return e.code
+
+    assert code(bc_y=lb.LB_FREE_SLIP) == lb.LB_OK
+    assert code(bc_y=3) == lb.LB_E_INVALID_ARG
+    assert code(collision=2) == lb.LB_E_INVALID_ARG
+    assert code(flow=2) == lb.LB_E_INVALID_ARG
+    assert code(surf=2) == lb.LB_E_INVALID_ARG
+    assert code(reserved=1) == lb.LB_E_INVALID_ARG
+    assert code(st_form=1) == lb.LB_E_UNSUPPORTED  # Langmuir with the chemical-potential form
+    assert code(psi_a=1.0) == lb.LB_E_INVALID_ARG
+    assert code(psi_G=1.0 / 200.0) == lb.LB_E_INVALID_ARG  # psi reaches 1 on the last row
+    assert code(psi_G=0.99 / 200.0) == lb.LB_OK
+    assert code(beta=float("nan")) == lb.LB_E_INVALID_ARG
+    c = lb.config_from_case(case, "fp64")
+    c.flow = lb.LB_FLOW["imposed"]
+    assert lb.lb_workspace_bytes(c) >= base + 2 * 8 * case["nx"] * case["ny"]

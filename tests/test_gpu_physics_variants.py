@@ -1,0 +1,124 @@
+"""Physics of the option paths on the GPU (HIP through the C-ABI), at the
+paper's problem sizes:
+
+- Young's migration under an imposed surfactant gradient (Sec. 6.7, Langmuir
+  law): upward, proportional to sigma0 beta, and within the band this
+  discretization gives in the paper's 51 x 201 channel (about half the
+  creeping-flow value: confinement by the walls and the periodic images, and a
+  small net force of the discrete surface-tension term acting as a 2D Stokeslet);
+- the reversing vortex (Sec. 6.1): after one cycle the interface returns to its
+  start within a small L1 error, with phi conserved;
+- the falling drop between free-slip walls (Sec. 6.4): it falls, conserves phi and
+  stays mirror-symmetric about its axis until round-off is amplified;
+- the stability comparison (Sec. 7): at density ratio 500 and nu = 0.01 the
+  cascaded pair runs stably where the SRT pair diverges.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1909_04166_amd import lb, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def test_young_migration_langmuir():
+    print("[case] Young migration, 51 x 201, sigma0 beta = 0.0048, 0.0146, 0.0244", flush=True)
+    B = lb.Batch(3, 40000, "fp64")
+    runs = []
+    for sb in (0.0048, 0.0146, 0.0244):
+        c, p = W.surfactant_young(sb)
+        runs.append((B.add(c, p), c, sb))
+    yc = {s: [] for s, _, _ in runs}
+    for _ in range(16):
+        B.step(5000)
+        for s, _, _ in runs:
+            d = B.diagnostics(s)
+            assert d["nan_flag"] == 0
+            yc[s].append(d["centroid_y"])
+    speeds = []
+    for s, c, sb in runs:
+        h = np.array(yc[s])
+        v = (h[-1] - h[7]) / (8 * 5000)  # late window: steady migration
+        ratio = v / W.young_velocity(c, 30.0)
+        print(f"   sigma0 beta {sb}: V = {v:.3e}, V / V_Young = {ratio:.3f}", flush=True)
+        assert np.all(np.diff(h) > 0)  # moves up, toward lower surface tension
+        assert 0.35 <= ratio <= 0.75
+        speeds.append(v / sb)
+    assert max(speeds) / min(speeds) <= 1.25  # proportional to sigma0 beta
+    B.close()
+
+
+@pytest.mark.parametrize("coll,bound", [("cascaded", 0.08), ("srt", 0.03)])
+def test_reversing_vortex_cycle(coll, bound):
+    case, phi0, vel, Tf = W.reversing_shear(200)
+    case["collision"] = coll
+    print(f"[case] reversing vortex 200^2, {coll}, T_f = {Tf}", flush=True)
+    L = lb.Lattice(case, phi0, "fp64")
+    L.set_velocity(*vel)
+    L.step(Tf)
+    mid = L.fields()[0]
+    L.set_velocity(-vel[0], -vel[1])
+    L.step(Tf)
+    phi = L.fields()[0]
+    l1 = np.abs(phi - phi0).sum() / phi0.sum()
+    print(f"   L1 {l1:.4f}, mass {phi.sum() / phi0.sum() - 1:.2e}, mid-cycle deformation "
+          f"{np.abs(mid - phi0).sum() / phi0.sum():.3f}", flush=True)
+    assert abs(phi.sum() / phi0.sum() - 1) <= 1e-11
+    assert np.abs(mid - phi0).sum() / phi0.sum() > 0.5  # strongly deformed at T_f
+    assert l1 <= bound
+
+
+def test_reversing_vortex_matches_oracle_over_a_cycle():
+    """Full cycle at L0 = 100 against the oracle (FP64 both)."""
+    case, phi0, vel, Tf = W.reversing_shear(100)
+    print(f"[case] reversing vortex 100^2 cycle vs oracle, T_f = {Tf}", flush=True)
+    g = lb.Lattice(case, phi0, "fp64")
+    o = oracle.Oracle(case, phi0)
+    for sgn in (1.0, -1.0):
+        g.set_velocity(sgn * vel[0], sgn * vel[1])
+        o.set_velocity(sgn * vel[0], sgn * vel[1])
+        g.step(Tf)
+        o.step(Tf)
+    err = np.abs(g.fields()[0] - o.fields()[0]).max()
+    print(f"   max |phi_gpu - phi_oracle| after {2 * Tf} steps: {err:.3e}", flush=True)
+    assert err <= 1e-9
+
+
+@pytest.mark.parametrize("Oh", [0.3, 1.0])
+def test_falling_drop_free_slip(Oh):
+    case, phi0 = W.falling_drop(Oh)
+    print(f"[case] falling drop 151 x 451 free slip, Oh = {Oh}", flush=True)
+    L = lb.Lattice(case, phi0, "fp64")
+    Tu = math.sqrt(30.0 / -case["gy"])
+    s0 = phi0.sum()
+    ys = [L.diagnostics()["centroid_y"]]
+    for T in (2.04, 4.07, 6.11, 8.14):
+        L.step(int(round(T * Tu)) - L.t)
+        d = L.diagnostics()
+        assert d["nan_flag"] == 0
+        assert abs(d["sum_phi"] / s0 - 1) <= 1e-12
+        ys.append(d["centroid_y"])
+        if T == 2.04:
+            phi = L.fields()[0]
+            asym = np.abs(phi - phi[:, 150 - np.arange(151)]).max()
+            print(f"   mirror asymmetry at T = 2.04: {asym:.2e}", flush=True)
+            assert asym <= 1e-6
+    print("   centroid", [round(y, 2) for y in ys], flush=True)
+    assert np.all(np.diff(ys) < 0)
+    assert ys[-1] < 160.0  # fell more than 140 lattice units by T = 8.14
+
+
+def test_cascaded_more_stable_than_srt():
+    print("[case] elliptic cylinder 200^2, ratio 500, nu = 0.01, cascaded vs SRT", flush=True)
+    out = {}
+    for coll in ("cascaded", "srt"):
+        c, p = W.elliptic_cylinder(500, 0.01, collision=coll)
+        L = lb.Lattice(c, p, "fp64")
+        L.step(20000)
+        d = L.diagnostics()
+        out[coll] = d["nan_flag"] == 0 and d["max_u"] < 0.1
+        print(f"   {coll}: stable {out[coll]} (max |u| {d['max_u']:.2e})", flush=True)
+    assert out["cascaded"] and not out["srt"]
