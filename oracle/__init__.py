@@ -40,6 +40,7 @@ class OrcParams(ctypes.Structure):
         ("bc_y", ctypes.c_int32), ("force_ref", ctypes.c_int32),
         ("st_form", ctypes.c_int32), ("collision", ctypes.c_int32),
         ("flow", ctypes.c_int32), ("surf", ctypes.c_int32),
+        ("bc_x", ctypes.c_int32), ("pad_", ctypes.c_int32),
         ("rho_A", ctypes.c_double), ("rho_B", ctypes.c_double),
         ("nu_A", ctypes.c_double), ("nu_B", ctypes.c_double),
         ("sigma0", ctypes.c_double), ("sigma_T", ctypes.c_double),
@@ -104,6 +105,7 @@ def params_from_case(case: dict) -> OrcParams:
     P = OrcParams()
     P.nx, P.ny = int(case["nx"]), int(case["ny"])
     P.bc_y = _BC[case.get("bc_y", "periodic")]
+    P.bc_x = _BC[case.get("bc_x", "periodic")]
     P.force_ref = _FREF[case.get("force_ref", "mean")]
     P.st_form = _ST[case.get("st_form", "geometric")]
     P.rho_A, P.rho_B = float(case["rho_A"]), float(case["rho_B"])

@@ -76,8 +76,10 @@ static const double CS2 = 1.0 / 3.0; /* c_s^2 = c_sphi^2 (D2Q9, dx = dt = 1) */
 static const double MS8_C00 = 4.0;
 /* Threshold below which the interface normal is set to zero. */
 static const double N_EPS = 1e-12;
-/* Direction with the y component of e_a reversed (specular reflection at a wall y = const). */
+/* Direction with the y (x) component of e_a reversed: specular reflection at a
+ * wall y = const (x = const). */
 static const int MIRY[Q] = {0, 1, 4, 3, 2, 8, 7, 6, 5};
+static const int MIRX[Q] = {0, 3, 2, 1, 4, 6, 5, 8, 7};
 
 enum { ORC_PERIODIC = 0, ORC_WALL = 1, ORC_SLIP = 2 };
 enum { ORC_CASCADED = 0, ORC_SRT = 1 };
@@ -88,12 +90,15 @@ enum { ORC_ST_GEOMETRIC = 0, ORC_ST_CHEMPOT = 1 };
 
 typedef struct {
     int32_t nx, ny;
-    int32_t bc_y;             /* ORC_PERIODIC, ORC_WALL (bounce-back) or ORC_SLIP (x is periodic) */
+    int32_t bc_y;             /* walls at y = -1/2 and ny - 1/2: ORC_PERIODIC, ORC_WALL (bounce-back)
+                                 or ORC_SLIP (specular) */
     int32_t force_ref;        /* reference density of the body force */
     int32_t st_form;          /* surface-tension form */
     int32_t collision;        /* ORC_CASCADED or ORC_SRT */
     int32_t flow;             /* ORC_COUPLED, or ORC_IMPOSED: ACE only under a given velocity */
     int32_t surf;             /* ORC_SIGMA_LINEAR (sigma(T(y))) or ORC_SIGMA_LANGMUIR */
+    int32_t bc_x;             /* walls at x = -1/2 and nx - 1/2: ORC_PERIODIC, ORC_WALL or ORC_SLIP */
+    int32_t pad_;
     double rho_A, rho_B;      /* phase A (phi = 1), phase B (phi = 0) */
     double nu_A, nu_B;        /* kinematic viscosities */
     double sigma0, sigma_T;   /* sigma(y) = sigma0 + sigma_T * T(y) */
@@ -120,28 +125,31 @@ typedef struct {
 
 static inline int wrap(int i, int n) { i %= n; return i < 0 ? i + n : i; }
 
-/* Row index of a (possibly ghost) row j: periodic wrap, or mirror across a
- * halfway wall at y = -1/2 and y = ny - 1/2. */
-static inline int row_of(const orc_params *P, int j) {
-    if (P->bc_y == ORC_PERIODIC) return wrap(j, P->ny);
-    if (j < 0) return -1 - j;
-    if (j >= P->ny) return 2 * P->ny - 1 - j;
-    return j;
+/* Index of a (possibly ghost) row j or column i: periodic wrap, or mirror
+ * across halfway walls at -1/2 and n - 1/2. */
+static inline int mirror_or_wrap(int bc, int i, int n) {
+    if (bc == ORC_PERIODIC) return wrap(i, n);
+    if (i < 0) return -1 - i;
+    if (i >= n) return 2 * n - 1 - i;
+    return i;
 }
+static inline int row_of(const orc_params *P, int j) { return mirror_or_wrap(P->bc_y, j, P->ny); }
+static inline int col_of(const orc_params *P, int i) { return mirror_or_wrap(P->bc_x, i, P->nx); }
 
 static inline double phi_at(const orc_state *S, int i, int j) {
-    return S->phi[(int64_t)row_of(&S->P, j) * S->P.nx + wrap(i, S->P.nx)];
+    return S->phi[(int64_t)row_of(&S->P, j) * S->P.nx + col_of(&S->P, i)];
 }
 static inline double pbar_at(const orc_state *S, int i, int j) {
-    return S->pbar[(int64_t)row_of(&S->P, j) * S->P.nx + wrap(i, S->P.nx)];
+    return S->pbar[(int64_t)row_of(&S->P, j) * S->P.nx + col_of(&S->P, i)];
 }
-/* fields stored with one ghost row on each side: row j in [-1, ny] */
+/* fields stored with one ghost row and column on each side: j in [-1, ny], i in [-1, nx] */
 static inline int64_t gidx(const orc_state *S, int i, int j) {
-    return (int64_t)(j + 1) * S->P.nx + wrap(i, S->P.nx);
+    return (int64_t)(j + 1) * (S->P.nx + 2) + (i + 1);
 }
-/* For ghost rows beyond the range stored, use the periodic image. */
+/* Across a periodic boundary the ghost is the periodic image. */
 static inline int64_t gidx_any(const orc_state *S, int i, int j) {
     if (S->P.bc_y == ORC_PERIODIC) j = wrap(j, S->P.ny);
+    if (S->P.bc_x == ORC_PERIODIC) i = wrap(i, S->P.nx);
     return gidx(S, i, j);
 }
 
@@ -422,7 +430,8 @@ int orc_create(const orc_params *P, orc_state **out) {
     if (P->nx < 4 || P->ny < 4 || !(P->W > 0) || !(P->M > 0) || !(P->rho_A > 0) ||
         !(P->rho_B > 0) || !(P->nu_A > 0) || !(P->nu_B > 0))
         return -1;
-    if (P->bc_y < ORC_PERIODIC || P->bc_y > ORC_SLIP || P->collision < ORC_CASCADED ||
+    if (P->bc_y < ORC_PERIODIC || P->bc_y > ORC_SLIP || P->bc_x < ORC_PERIODIC ||
+        P->bc_x > ORC_SLIP || P->collision < ORC_CASCADED ||
         P->collision > ORC_SRT || P->flow < ORC_COUPLED || P->flow > ORC_IMPOSED ||
         P->surf < ORC_SIGMA_LINEAR || P->surf > ORC_SIGMA_LANGMUIR)
         return -1;
@@ -431,7 +440,7 @@ int orc_create(const orc_params *P, orc_state **out) {
     if (!S) return -2;
     S->P = *P;
     S->N = (int64_t)P->nx * P->ny;
-    const int64_t N = S->N, NG = (int64_t)P->nx * (P->ny + 2);
+    const int64_t N = S->N, NG = (int64_t)(P->nx + 2) * (P->ny + 2);
     int ok = 1;
 #define ALLOC(ptr, n) do { (ptr) = (double *)calloc((size_t)(n), sizeof(double)); ok &= (ptr) != NULL; } while (0)
     ALLOC(S->f, Q * N); ALLOC(S->g, Q * N); ALLOC(S->ft, Q * N); ALLOC(S->gt, Q * N);
@@ -496,11 +505,11 @@ static void orc_fields_internal(orc_state *S) {
             S->pbar[k] = sg;
         }
 
-    /* O2 + O3: grad phi, |grad phi|^2 and n on interior rows and one ghost row
-     * per side, sampling phi through its ghost extension. */
+    /* O2 + O3: grad phi, |grad phi|^2 and n on the interior and one ghost row and
+     * column per side, sampling phi through its ghost extension. */
 #pragma omp parallel for schedule(static)
     for (int j = -1; j <= ny; ++j)
-        for (int i = 0; i < nx; ++i) {
+        for (int i = -1; i <= nx; ++i) {
             double q9[Q], dx, dy;
             for (int a = 0; a < Q; ++a) q9[a] = phi_at(S, i + EX[a], j + EY[a]);
             orc_grad9(q9, &dx, &dy);
@@ -648,25 +657,39 @@ void orc_step(orc_state *S, int64_t nsteps) {
 
         /* O14: pull streaming.  Where the source lies beyond a wall: halfway
          * bounce-back takes the opposite direction at the same node; halfway specular
-         * reflection takes the y-mirrored direction at the node the particle left. */
+         * reflection takes the mirrored direction at the node the particle left
+         * along the wall.  Beyond two walls at once (a corner), bounce-back (the
+         * two reflections in sequence). */
 #pragma omp parallel for schedule(static)
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
                 const int64_t k = (int64_t)j * nx + i;
                 for (int a = 0; a < Q; ++a) {
-                    const int js = j - EY[a];
-                    const int is = wrap(i - EX[a], nx);
-                    if (P->bc_y == ORC_WALL && (js < 0 || js >= ny)) {
-                        S->f[a * N + k] = S->ft[OPP[a] * N + k];
-                        S->g[a * N + k] = S->gt[OPP[a] * N + k];
-                    } else if (P->bc_y == ORC_SLIP && (js < 0 || js >= ny)) {
-                        const int64_t kr = (int64_t)j * nx + is;
-                        S->f[a * N + k] = S->ft[MIRY[a] * N + kr];
-                        S->g[a * N + k] = S->gt[MIRY[a] * N + kr];
+                    const int js = j - EY[a], is0 = i - EX[a];
+                    const int outy = P->bc_y != ORC_PERIODIC && (js < 0 || js >= ny);
+                    const int outx = P->bc_x != ORC_PERIODIC && (is0 < 0 || is0 >= nx);
+                    const int is = wrap(is0, nx);
+                    int b = a;
+                    int64_t ks;
+                    if ((outy && outx) || (outy && P->bc_y == ORC_WALL) || (outx && P->bc_x == ORC_WALL)) {
+                        b = OPP[a];
+                        ks = k;
+                    } else if (outy) { /* specular at a y wall: same row, mirrored direction */
+                        b = MIRY[a];
+                        ks = (int64_t)j * nx + is;
+                    } else if (outx) { /* specular at an x wall: same column */
+                        b = MIRX[a];
+                        ks = (int64_t)wrap(js, ny) * nx + i;
                     } else {
-                        const int64_t ks = (int64_t)wrap(js, ny) * nx + is;
-                        S->f[a * N + k] = S->ft[a * N + ks];
-                        S->g[a * N + k] = S->gt[a * N + ks];
+                        ks = -1;
+                    }
+                    if (ks >= 0) {
+                        S->f[a * N + k] = S->ft[b * N + ks];
+                        S->g[a * N + k] = S->gt[b * N + ks];
+                    } else {
+                        const int64_t kp = (int64_t)wrap(js, ny) * nx + is;
+                        S->f[a * N + k] = S->ft[a * N + kp];
+                        S->g[a * N + k] = S->gt[a * N + kp];
                     }
                 }
             }

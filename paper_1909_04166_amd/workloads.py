@@ -7,8 +7,8 @@ phase-field profile) and no step of the lattice Boltzmann method itself.
 A case is a plain dictionary::
 
     nx, ny            lattice size (x contiguous in every array, index y*nx + x)
-    bc_y              "periodic", "wall" (halfway bounce-back) or "slip" (halfway
-                      specular reflection); x is periodic
+    bc_x, bc_y        "periodic", "wall" (halfway bounce-back) or "slip" (halfway
+                      specular reflection) at x = -1/2, nx - 1/2 and y = -1/2, ny - 1/2
     rho_A, rho_B      densities of phase A (phi = 1) and phase B (phi = 0)
     nu_A, nu_B        kinematic viscosities
     sigma0, sigma_T   sigma(y) = sigma0 + sigma_T * T(y)
@@ -35,7 +35,7 @@ import numpy as np
 
 
 def base_case(nx: int, ny: int, **kw) -> dict:
-    c = dict(nx=int(nx), ny=int(ny), bc_y="periodic", rho_A=1.0, rho_B=1.0,
+    c = dict(nx=int(nx), ny=int(ny), bc_x="periodic", bc_y="periodic", rho_A=1.0, rho_B=1.0,
              nu_A=0.1, nu_B=0.1, sigma0=0.0, sigma_T=0.0, T0=0.0, dTdy=0.0,
              y_ref=0.0, W=4.0, M=0.02, gx=0.0, gy=0.0, force_ref="mean",
              st_form="geometric", collision="cascaded", flow="coupled", surf="linear",
@@ -164,6 +164,30 @@ def falling_drop(Oh: float = 0.3, Eo: float = 43.0, D: float = 30.0, nx: int = 1
     x, y = _grid(nx, ny)
     r = np.hypot(x - 75.0, y - 300.0)
     return case, tanh_profile(D / 2.0 - r, W)
+
+
+def rising_bubble(Eo: float = 125.0, Re: float = 35.0, D: float = 64.0, nx: int = 161,
+                  ny: int = 481, ratio: float = 1000.0, visc_ratio: float = 100.0,
+                  Ug: float = 0.02, W: float = 4.0, M: float = 0.02, xc: float = 80.0,
+                  yc: float = 120.0):
+    """Buoyancy-driven bubble (Sec. 6.5): light phase B (phi = 0) of diameter D in
+    liquid A, 161 x 481, free-slip walls on the vertical sides, no-slip walls at
+    the bottom and top, F_ext = -(rho - rho_A) g j.  rho_A / rho_B = 1000,
+    mu_A / mu_B = 100, Re = rho_A U_g D / mu_A, Eo = rho_A U_g^2 D / sigma with
+    U_g = sqrt(g D).  Readings: rho_B = 1, U_g = 0.02, W = 4, M = 0.02, and the
+    bubble centred horizontally at x = 80 (the paper's (40, 120) would put it 8
+    nodes from a side wall).  Time unit D / U_g."""
+    rho_A, rho_B = float(ratio), 1.0
+    g = Ug * Ug / D
+    muA = rho_A * Ug * D / Re
+    muB = muA / visc_ratio
+    sigma = rho_A * Ug * Ug * D / Eo
+    case = base_case(nx, ny, bc_x="slip", bc_y="wall", rho_A=rho_A, rho_B=rho_B,
+                     nu_A=muA / rho_A, nu_B=muB / rho_B, sigma0=sigma, W=W, M=M, gy=-g,
+                     force_ref="heavy")
+    x, y = _grid(nx, ny)
+    r = np.hypot(x - xc, y - yc)
+    return case, tanh_profile(r - D / 2.0, W)
 
 
 def reversing_shear(L0: int = 200, U0: float = 0.04, W: float = 3.0, Pe: float = 60.0):

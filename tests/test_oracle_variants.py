@@ -308,3 +308,58 @@ def test_imposed_velocity_advection_diffusion(collision):
     assert abs(np.log(A / amp) / (k2 * t) / M - 1) <= 0.03
     expect = -(kv @ U) * t
     assert abs(np.angle(np.exp(1j * (phase - expect)))) <= 0.01
+
+
+# ------------------------------------------------------------------ walls in x
+
+def _transpose_case(case):
+    t = dict(case, nx=case["ny"], ny=case["nx"], bc_x=case["bc_y"], bc_y=case["bc_x"],
+             gx=case["gy"], gy=case["gx"])
+    return t
+
+
+@pytest.mark.parametrize("bcx,bcy", [("periodic", "wall"), ("periodic", "slip"), ("slip", "wall"),
+                                     ("wall", "slip")])
+def test_walls_in_x_equal_transposed_walls_in_y(bcx, bcy):
+    """Rotating the lattice by a quarter turn (x <-> y, walls and body force with
+    it) maps the step onto itself: the x-wall paths reproduce the pinned y-wall
+    paths, to round-off, including the corners when both directions have walls."""
+    nx, ny = 40, 56
+    case = W.base_case(nx, ny, bc_x=bcx, bc_y=bcy, rho_A=10.0, rho_B=1.0, sigma0=0.01,
+                       gy=-1e-5, force_ref="mean")
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    phi0 = W.tanh_profile(11.0 - np.hypot(x - 14.2, y - 13.7), 4.0)
+    a = oracle.Oracle(case, phi0)
+    b = oracle.Oracle(_transpose_case(case), phi0.T.copy())
+    a.step(60)
+    b.step(60)
+    pa, pb = a.fields(), b.fields()
+    assert np.abs(pa[3]).max() > 1e-6  # flow develops (not vacuous)
+    assert np.abs(pb[0] - pa[0].T).max() <= 1e-12
+    assert np.abs(pb[1] - pa[1].T).max() <= 1e-12 * max(1.0, np.abs(pa[1]).max())
+    assert np.abs(pb[2] - pa[3].T).max() <= 1e-12
+    assert np.abs(pb[3] - pa[2].T).max() <= 1e-12
+
+
+@pytest.mark.parametrize("bcy", ["wall", "slip"])
+def test_slip_in_x_is_half_of_mirrored_periodic_domain(bcy):
+    """Method of images in x: specular walls at x = -1/2 and nx - 1/2 equal the left
+    half of a periodic domain of width 2 nx holding the mirror image.  With walls
+    in y as well this fixes the corner rule (the image problem reflects twice)."""
+    nx, ny = 36, 48
+    case = W.base_case(nx, ny, bc_x="slip", bc_y=bcy, rho_A=10.0, rho_B=1.0, sigma0=0.01,
+                       gy=-1e-5, force_ref="mean")
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    phi0 = W.tanh_profile(10.0 - np.hypot(x - 9.3, y - 12.1), 4.0)  # near the corner
+    big = dict(case, nx=2 * nx, bc_x="periodic")
+    a = oracle.Oracle(case, phi0)
+    b = oracle.Oracle(big, np.concatenate([phi0, phi0[:, ::-1]], axis=1))
+    a.step(80)
+    b.step(80)
+    fa, ga = a.get_dist()
+    fb, gb = b.get_dist()
+    assert np.abs(fb[:, :, :nx] - fa).max() <= 1e-13
+    assert np.abs(gb[:, :, :nx] - ga).max() <= 1e-13
+    mirx = [0, 3, 2, 1, 4, 6, 5, 8, 7]
+    assert np.abs(fb[mirx][:, :, nx:][:, :, ::-1] - fa).max() <= 1e-13
+    assert np.abs(a.fields()[2]).max() > 1e-6
