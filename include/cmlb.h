@@ -30,9 +30,10 @@
  *     storage precision.  Distribution arrays are FP64 [9][ny][nx] in the
  *     velocity order 0 rest, 1 +x, 2 +y, 3 -x, 4 -y, 5 (+,+), 6 (-,+), 7 (-,-),
  *     8 (+,-) (Eq. particlevelocities).
- *   - Node (x, y) = (i, j).  x is periodic.  y is periodic or bounded by walls
- *     at y = -1/2 and y = ny - 1/2: halfway bounce-back (no slip) or halfway
- *     specular reflection (free slip).
+ *   - Node (x, y) = (i, j).  Each direction is periodic or bounded by walls at
+ *     -1/2 and n - 1/2: halfway bounce-back (no slip) or halfway specular
+ *     reflection (free slip).  A population whose source lies beyond an x and a
+ *     y wall at once is bounced back.
  *   - A handle is not thread-safe; distinct handles are independent.
  */
 #ifndef CMLB_H
@@ -85,8 +86,7 @@ enum { LB_FP64 = 0, LB_FP32 = 1, LB_FP32_F16 = 2, LB_FP32_BF16 = 3 };
  */
 typedef struct lb_config {
     int32_t nx, ny;          /* lattice size, each >= 8 */
-    int32_t bc_x, bc_y;      /* bc_x must be LB_PERIODIC; bc_y LB_PERIODIC, LB_HALFWAY_BB or
-                                LB_FREE_SLIP */
+    int32_t bc_x, bc_y;      /* LB_PERIODIC, LB_HALFWAY_BB or LB_FREE_SLIP in x and in y */
     int32_t force_ref;       /* LB_FREF_* */
     int32_t st_form;         /* LB_ST_* */
     int32_t precision;       /* LB_FP64, LB_FP32, LB_FP32_F16, LB_FP32_BF16 */

@@ -42,7 +42,8 @@ lb_status validate(const lb_config* c) {
     if (c->nx < 8 || c->ny < 8 || c->nx > (1 << 20) || c->ny > (1 << 20)) return LB_E_INVALID_ARG;
     // every plane (storage type) and every FP64 field plane must be < 4 GiB
     if ((uint64_t)c->nx * c->ny * 8 >= ((uint64_t)1 << 32)) return LB_E_INVALID_ARG;
-    if (c->bc_x != LB_PERIODIC) return c->bc_x == LB_HALFWAY_BB ? LB_E_UNSUPPORTED : LB_E_INVALID_ARG;
+    if (c->bc_x != LB_PERIODIC && c->bc_x != LB_HALFWAY_BB && c->bc_x != LB_FREE_SLIP)
+        return LB_E_INVALID_ARG;
     if (c->bc_y != LB_PERIODIC && c->bc_y != LB_HALFWAY_BB && c->bc_y != LB_FREE_SLIP)
         return LB_E_INVALID_ARG;
     if (c->collision != LB_CASCADED && c->collision != LB_SRT) return LB_E_INVALID_ARG;
@@ -97,6 +98,7 @@ void fill_desc(const lb_config* c, LatDesc& D, void* b0, void* b1, int64_t plane
     D.nx = c->nx;
     D.ny = c->ny;
     D.wall_y = c->bc_y == LB_HALFWAY_BB ? WALL_BOUNCE : (c->bc_y == LB_FREE_SLIP ? WALL_SLIP : WALL_NONE);
+    D.wall_x = c->bc_x == LB_HALFWAY_BB ? WALL_BOUNCE : (c->bc_x == LB_FREE_SLIP ? WALL_SLIP : WALL_NONE);
     D.st_form = c->st_form;
     D.surf = c->surf == LB_SIGMA_LANGMUIR ? 1 : 0;
     D.flow = c->flow == LB_FLOW_IMPOSED ? 1 : 0;
@@ -272,10 +274,10 @@ Sched default_sched(int nx, int ny) {
 }
 
 struct TuneKey {
-    int prec, nx, ny, wall, st, kind, surf;
+    int prec, nx, ny, wall, wallx, st, kind, surf;
     bool operator<(const TuneKey& o) const {
-        return std::tie(prec, nx, ny, wall, st, kind, surf) <
-               std::tie(o.prec, o.nx, o.ny, o.wall, o.st, o.kind, o.surf);
+        return std::tie(prec, nx, ny, wall, wallx, st, kind, surf) <
+               std::tie(o.prec, o.nx, o.ny, o.wall, o.wallx, o.st, o.kind, o.surf);
     }
 };
 std::mutex g_tune_mu;
@@ -462,8 +464,8 @@ std::vector<Sched> candidates(int nx, int ny, int kind) {
 }
 
 lb_status autotune_single(lb_handle* h) {
-    const TuneKey key{h->cfg.precision, h->cfg.nx, h->cfg.ny, h->hdesc.wall_y, h->cfg.st_form, h->kind,
-                      h->cfg.surf};
+    const TuneKey key{h->cfg.precision, h->cfg.nx, h->cfg.ny, h->hdesc.wall_y, h->hdesc.wall_x,
+                      h->cfg.st_form, h->kind, h->cfg.surf};
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune.find(key);

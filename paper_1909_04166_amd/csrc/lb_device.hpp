@@ -69,6 +69,8 @@ struct alignas(16) LatDesc {
     int64_t plane;      // element stride between planes
     int32_t surf;       // kappa~(y): 0 linear, 1 Langmuir of an imposed linear psi(y)
     int32_t flow;       // 0 coupled, 1 phase field only under an imposed velocity
+    int32_t wall_x;     // walls at x = -1/2, nx - 1/2: same codes as wall_y
+    int32_t pad2;
     void* buf[2];       // 18 planes each
     double* fields;     // FP64 output planes (phi, p, ux, uy or the 9 coupling planes)
     void* vel;          // imposed velocity: planes ux, uy in the compute type (flow 1)
@@ -132,7 +134,7 @@ __device__ __forceinline__ void sto(typename ST::T* plane, uint32_t e, typename 
 // gbar); xm, xp are the periodic neighbours of x.
 template <class ST>
 __device__ __forceinline__ void pull9(const typename ST::T* __restrict__ base, int64_t P, int nx,
-                                      int ny, int wall, int x, int xm, int xp, int r,
+                                      int ny, int wall, int wallx, int x, int xm, int xp, int r,
                                       typename ST::R sh, typename ST::R out[9]) {
     using R = typename ST::R;
     const bool bot = wall && r == 0;       // sources of 2, 5, 6 lie below the wall
@@ -159,6 +161,24 @@ __device__ __forceinline__ void pull9(const typename ST::T* __restrict__ base, i
     out[4] = ldo<ST>(base + p4 * P, ot + x) + w1;
     out[7] = ldo<ST>(base + p7 * P, ot + x7) + w5;
     out[8] = ldo<ST>(base + p8 * P, ot + x8) + w5;
+    if (wallx) {
+        // Lanes on the first or last column replace what arrived from beyond an x
+        // wall: bounce-back (opposite direction, same node), or specular reflection
+        // (x-mirrored direction leaving the node of the same column one row over);
+        // beyond an x and a y wall at once, bounce-back.
+        const bool sx = wallx == WALL_SLIP;
+        const uint32_t rowb = (uint32_t)rb * (uint32_t)nx, rowt = (uint32_t)rt * (uint32_t)nx;
+        if (x == 0) {
+            out[1] = ldo<ST>(base + 3 * P, o + x) + w1;
+            out[5] = (sx && !bot) ? ldo<ST>(base + 6 * P, rowb + x) + w5 : ldo<ST>(base + 7 * P, o + x) + w5;
+            out[8] = (sx && !top) ? ldo<ST>(base + 7 * P, rowt + x) + w5 : ldo<ST>(base + 6 * P, o + x) + w5;
+        }
+        if (x == nx - 1) {
+            out[3] = ldo<ST>(base + 1 * P, o + x) + w1;
+            out[6] = (sx && !bot) ? ldo<ST>(base + 5 * P, rowb + x) + w5 : ldo<ST>(base + 8 * P, o + x) + w5;
+            out[7] = (sx && !top) ? ldo<ST>(base + 8 * P, rowt + x) + w5 : ldo<ST>(base + 5 * P, o + x) + w5;
+        }
+    }
 }
 
 template <class R>
@@ -475,7 +495,7 @@ __global__ void __launch_bounds__(TX) lb_fused(const LatDesc* __restrict__ descs
         const WorkItem it = items[wi];
         if (it.y1 <= it.y0) continue;  // padding item (uniform over the block)
         const LatDesc& D = descs[it.inst];
-        const int nx = D.nx, ny = D.ny, wall = D.wall_y, chem = D.st_form;
+        const int nx = D.nx, ny = D.ny, wall = D.wall_y, wallx = D.wall_x, chem = D.st_form;
         const int64_t P = D.plane;
         const KConst<R> K = load_const<R>(D);
         const double* ktab = D.surf ? D.ktab : nullptr;  // per-row Langmuir table
@@ -487,8 +507,9 @@ __global__ void __launch_bounds__(TX) lb_fused(const LatDesc* __restrict__ descs
         const bool inA = t < w + 4;              // phi cells
         const bool inB = t >= 1 && t < w + 3;    // pbar and normal cells
         const bool inF = t >= 2 && t < w + 2;    // collided cells
-        int xc = it.x0 - 2 + t;                  // this lane's column (halo lanes wrap)
-        xc = xc < 0 ? xc + nx : (xc >= nx ? xc - nx : xc);
+        // this lane's column: halo lanes wrap, or mirror across x walls (ghost
+        // values); lanes past the strip are idle and park on column 0
+        const int xc = inA ? map_row(it.x0 - 2 + t, nx, wallx) : 0;
         const int xm = xc == 0 ? nx - 1 : xc - 1;
         const int xp = xc == nx - 1 ? 0 : xc + 1;
 
@@ -504,13 +525,13 @@ __global__ void __launch_bounds__(TX) lb_fused(const LatDesc* __restrict__ descs
             const bool have = PF && k >= 5;  // rows already pulled during the last collision
             // ---- A: phi at the leading row
             if (inA) {
-                if (!have) pull9<ST>(src, P, nx, ny, wall, xc, xm, xp, map_row(L, ny, wall), K.shf, f0);
+                if (!have) pull9<ST>(src, P, nx, ny, wall, wallx, xc, xm, xp, map_row(L, ny, wall), K.shf, f0);
                 s_phi[L & 3][t] = sum9(f0);
             }
             // ---- B: pbar one row behind
             if (k >= 2 && inB) {
                 const int Lg = L - 1;
-                if (!have) pull9<ST>(srcg, P, nx, ny, wall, xc, xm, xp, map_row(Lg, ny, wall), K.shg, g0);
+                if (!have) pull9<ST>(srcg, P, nx, ny, wall, wallx, xc, xm, xp, map_row(Lg, ny, wall), K.shg, g0);
                 s_pb[Lg & 3][t] = sum9(g0);
             }
             __syncthreads();
@@ -579,7 +600,7 @@ __global__ void __launch_bounds__(TX) lb_fused(const LatDesc* __restrict__ descs
                         }
                     }
                     if (pre && inA)  // next leading row into the freed f registers
-                        pull9<ST>(src, P, nx, ny, wall, xc, xm, xp, map_row(L + 1, ny, wall), K.shf, f2);
+                        pull9<ST>(src, P, nx, ny, wall, wallx, xc, xm, xp, map_row(L + 1, ny, wall), K.shf, f2);
                     if (inF) {
                         if constexpr (COLL == COLL_SRT)
                             hydro_srt<R>(g1, o);
@@ -592,7 +613,7 @@ __global__ void __launch_bounds__(TX) lb_fused(const LatDesc* __restrict__ descs
                         }
                     }
                     if (pre && inB)  // next pbar row into the freed gbar registers
-                        pull9<ST>(srcg, P, nx, ny, wall, xc, xm, xp, map_row(L, ny, wall), K.shg, g1);
+                        pull9<ST>(srcg, P, nx, ny, wall, wallx, xc, xm, xp, map_row(L, ny, wall), K.shg, g1);
                 } else if constexpr (MODE == MODE_FIELDS) {
                     if (inF) {
                         double* F = D.fields;
@@ -661,7 +682,7 @@ __global__ void __launch_bounds__(TX) lb_ace(const LatDesc* __restrict__ descs,
         const WorkItem it = items[wi];
         if (it.y1 <= it.y0) continue;
         const LatDesc& D = descs[it.inst];
-        const int nx = D.nx, ny = D.ny, wall = D.wall_y;
+        const int nx = D.nx, ny = D.ny, wall = D.wall_y, wallx = D.wall_x;
         const int64_t P = D.plane;
         const R shf = R(D.shift_f), four_W = R(D.four_W), Mm = R(D.M), omphi = R(D.omphi);
         const T* __restrict__ src = reinterpret_cast<const T*>(D.buf[parity]);
@@ -670,8 +691,7 @@ __global__ void __launch_bounds__(TX) lb_ace(const LatDesc* __restrict__ descs,
         const int w = min(TX - 4, nx - it.x0);
         const bool inA = t < w + 4;
         const bool inF = t >= 2 && t < w + 2;
-        int xc = it.x0 - 2 + t;
-        xc = xc < 0 ? xc + nx : (xc >= nx ? xc - nx : xc);
+        const int xc = inA ? map_row(it.x0 - 2 + t, nx, wallx) : 0;
         const int xm = xc == 0 ? nx - 1 : xc - 1;
         const int xp = xc == nx - 1 ? 0 : xc + 1;
 
@@ -682,7 +702,7 @@ __global__ void __launch_bounds__(TX) lb_ace(const LatDesc* __restrict__ descs,
         for (int k = 0; k < H + 2; ++k) {
             const int L = it.y0 - 1 + k;
             if (inA) {
-                pull9<ST>(src, P, nx, ny, wall, xc, xm, xp, map_row(L, ny, wall), shf, f0);
+                pull9<ST>(src, P, nx, ny, wall, wallx, xc, xm, xp, map_row(L, ny, wall), shf, f0);
                 s_phi[L & 3][t] = sum9(f0);
             }
             __syncthreads();

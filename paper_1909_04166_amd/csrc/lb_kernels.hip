@@ -151,11 +151,43 @@ __device__ __forceinline__ int miry_of(int a) {
 }
 __device__ __forceinline__ int wrapx(int x, int nx) { return x < 0 ? x + nx : (x >= nx ? x - nx : x); }
 
-// Stored (pre-streaming) value of direction a at node (x, y) such that pulling
-// gives the post-streaming value val(b, x', y'):  f~_a(x) = f_a(x + e_a); when
-// x + e_a lies beyond a halfway wall, f_{opp a}(x) (bounce-back) or
-// f_{mir a}(x + e_ax, y) (specular).
-// The state at t = 0 is f_a = w_a phi0, gbar_a = 0.
+__device__ __forceinline__ int mirx_of(int a) {
+    switch (a) {
+    case 1: return 3;
+    case 3: return 1;
+    case 5: return 6;
+    case 6: return 5;
+    case 7: return 8;
+    case 8: return 7;
+    }
+    return a;
+}
+
+// Where the population arriving at node (x, y) in direction a is stored (as the
+// previous step's post-collision value): direction *b at node (*xs, *ys).
+// Inside: f~_a(x - e_a).  Beyond one wall: bounce-back takes the opposite
+// direction at the same node; specular reflection takes the mirrored direction at
+// the node the particle left along the wall.  Beyond an x and a y wall at once:
+// bounce-back.  For every lattice this is a bijection of (node, direction) onto
+// the stored values, so the set-up kernels below scatter through it.
+__device__ __forceinline__ void pull_source(const LatDesc& D, int a, int x, int y, int* b, int* xs,
+                                            int* ys) {
+    const int nx = D.nx, ny = D.ny;
+    const int is = x - ex_of(a), js = y - ey_of(a);
+    const bool outy = D.wall_y && (js < 0 || js >= ny);
+    const bool outx = D.wall_x && (is < 0 || is >= nx);
+    if ((outy && outx) || (outy && D.wall_y == WALL_BOUNCE) || (outx && D.wall_x == WALL_BOUNCE)) {
+        *b = opp_of(a); *xs = x; *ys = y;
+    } else if (outy) {
+        *b = miry_of(a); *xs = wrapx(is, nx); *ys = y;
+    } else if (outx) {
+        *b = mirx_of(a); *xs = x; *ys = wrapx(js, ny);
+    } else {
+        *b = a; *xs = wrapx(is, nx); *ys = wrapx(js, ny);
+    }
+}
+
+// State at t = 0: every arriving population is f_a = w_a phi0, gbar_a = 0.
 template <class ST>
 __global__ void k_init(const LatDesc* __restrict__ dp, const double* __restrict__ phi0, int cur) {
     const LatDesc& D = *dp;
@@ -167,30 +199,21 @@ __global__ void k_init(const LatDesc* __restrict__ dp, const double* __restrict_
          k += (int64_t)gridDim.x * blockDim.x) {
         const int y = (int)(k / nx), x = (int)(k % nx);
         for (int a = 0; a < 9; ++a) {
-            int xs = x + ex_of(a), ys = y + ey_of(a);
-            xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
-            double ph;
-            if (ys < 0 || ys >= ny) {
-                if (D.wall_y == WALL_SLIP) ph = phi0[(int64_t)y * nx + xs];  // w_mir = w_a
-                else if (D.wall_y) ph = phi0[k];  // f_{opp a}(x) = w phi0(x), w_opp = w_a
-                else ph = phi0[(int64_t)(ys < 0 ? ys + ny : ys - ny) * nx + xs];
-            } else {
-                ph = phi0[(int64_t)ys * nx + xs];
-            }
-            const double w = wgt(a);
-            buf[a * D.plane + k] = ST::st((typename ST::R)(w * ph - w * D.shift_f));
-            buf[(9 + a) * D.plane + k] = ST::st((typename ST::R)(0.0 - w * D.shift_g));
+            int b, xs, ys;
+            pull_source(D, a, x, y, &b, &xs, &ys);
+            const int64_t ks = (int64_t)ys * nx + xs;
+            const double w = wgt(a);  // w_b = w_a for opposite and mirrored directions
+            buf[b * D.plane + ks] = ST::st((typename ST::R)(w * phi0[k] - w * D.shift_f));
+            buf[(9 + b) * D.plane + ks] = ST::st((typename ST::R)(0.0 - w * D.shift_g));
         }
     }
 }
 
-// Writes the stored planes from one staged post-streaming FP64 plane b of f
-// (which = 0) or gbar (which = 1): f~_b(x) = f_b(x + e_b) where x + e_b is inside;
-// where x - e_b lies beyond a wall, f~_{opp b}(x) = f_b(x) (bounce-back) or
-// f~_{mir b}(x - e_bx, y) = f_b(x) (specular).  Every stored value is written once.
+// Stores one staged post-streaming FP64 plane a of f (which = 0) or gbar
+// (which = 1): the value arriving at each node goes where the next pull finds it.
 template <class ST>
 __global__ void k_set_plane(const LatDesc* __restrict__ dp, const double* __restrict__ stage,
-                            int b, int which, int cur) {
+                            int a, int which, int cur) {
     const LatDesc& D = *dp;
     const int nx = D.nx, ny = D.ny;
     const int64_t N = (int64_t)nx * ny;
@@ -200,24 +223,9 @@ __global__ void k_set_plane(const LatDesc* __restrict__ dp, const double* __rest
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < N;
          k += (int64_t)gridDim.x * blockDim.x) {
         const int y = (int)(k / nx), x = (int)(k % nx);
-        int xs = x + ex_of(b), ys = y + ey_of(b);
-        xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
-        const bool out = ys < 0 || ys >= ny;
-        if (!out || !D.wall_y) {
-            if (out) ys = ys < 0 ? ys + ny : ys - ny;
-            buf[b * D.plane + k] = ST::st((typename ST::R)(stage[(int64_t)ys * nx + xs] - wgt(b) * sh));
-        }
-        const int yb = y - ey_of(b);
-        if (D.wall_y && (yb < 0 || yb >= ny)) {
-            if (D.wall_y == WALL_SLIP) {
-                const int m = miry_of(b);
-                const int64_t kr = (int64_t)y * nx + wrapx(x - ex_of(b), nx);
-                buf[m * D.plane + kr] = ST::st((typename ST::R)(stage[k] - wgt(m) * sh));
-            } else {
-                const int o = opp_of(b);
-                buf[o * D.plane + k] = ST::st((typename ST::R)(stage[k] - wgt(o) * sh));
-            }
-        }
+        int b, xs, ys;
+        pull_source(D, a, x, y, &b, &xs, &ys);
+        buf[b * D.plane + (int64_t)ys * nx + xs] = ST::st((typename ST::R)(stage[k] - wgt(a) * sh));
     }
 }
 
@@ -234,21 +242,9 @@ __global__ void k_get_plane(const LatDesc* __restrict__ dp, double* __restrict__
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < N;
          k += (int64_t)gridDim.x * blockDim.x) {
         const int y = (int)(k / nx), x = (int)(k % nx);
-        int xs = x - ex_of(a), ys = y - ey_of(a);
-        xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
-        const bool outside = ys < 0 || ys >= ny;
-        double v;
-        if (outside && D.wall_y == WALL_SLIP) {
-            const int m = miry_of(a);
-            v = (double)ST::ld(buf[m * D.plane + (int64_t)y * nx + xs]) + wgt(m) * sh;
-        } else if (outside && D.wall_y) {
-            const int o = opp_of(a);
-            v = (double)ST::ld(buf[o * D.plane + k]) + wgt(o) * sh;
-        } else {
-            if (outside) ys = ys < 0 ? ys + ny : ys - ny;
-            v = (double)ST::ld(buf[a * D.plane + (int64_t)ys * nx + xs]) + wgt(a) * sh;
-        }
-        out[k] = v;
+        int b, xs, ys;
+        pull_source(D, a, x, y, &b, &xs, &ys);
+        out[k] = (double)ST::ld(buf[b * D.plane + (int64_t)ys * nx + xs]) + wgt(a) * sh;
     }
 }
 

@@ -149,7 +149,7 @@ def config_from_case(case: dict, precision: str = "fp64", diag_every: int = 0,
     """Translate a case dictionary (paper_1909_04166_amd.workloads) into lb_config."""
     c = lb_config()
     c.nx, c.ny = int(case["nx"]), int(case["ny"])
-    c.bc_x = LB_PERIODIC
+    c.bc_x = LB_BC[case.get("bc_x", "periodic")]
     c.bc_y = LB_BC[case.get("bc_y", "periodic")]
     c.force_ref = LB_FREF[case.get("force_ref", "mean")]
     c.st_form = LB_ST[case.get("st_form", "geometric")]

@@ -168,13 +168,15 @@ def falling_drop(Oh: float = 0.3, Eo: float = 43.0, D: float = 30.0, nx: int = 1
 
 def rising_bubble(Eo: float = 125.0, Re: float = 35.0, D: float = 64.0, nx: int = 161,
                   ny: int = 481, ratio: float = 1000.0, visc_ratio: float = 100.0,
-                  Ug: float = 0.02, W: float = 4.0, M: float = 0.02, xc: float = 80.0,
+                  Ug: float = 0.01, W: float = 5.0, M: float = 0.02, xc: float = 80.0,
                   yc: float = 120.0):
     """Buoyancy-driven bubble (Sec. 6.5): light phase B (phi = 0) of diameter D in
     liquid A, 161 x 481, free-slip walls on the vertical sides, no-slip walls at
     the bottom and top, F_ext = -(rho - rho_A) g j.  rho_A / rho_B = 1000,
     mu_A / mu_B = 100, Re = rho_A U_g D / mu_A, Eo = rho_A U_g^2 D / sigma with
-    U_g = sqrt(g D).  Readings: rho_B = 1, U_g = 0.02, W = 4, M = 0.02, and the
+    U_g = sqrt(g D).  Readings: rho_B = 1, U_g = 0.01 (the start-up pressure waves
+    at ratio 1000 stay below |u| ~ 0.05), M = 0.02 and W = 5 (with W = 4 this
+    curved interface at ratio 1000 diverges near t = 1.2 D / U_g), and the
     bubble centred horizontally at x = 80 (the paper's (40, 120) would put it 8
     nodes from a side wall).  Time unit D / U_g."""
     rho_A, rho_B = float(ratio), 1.0

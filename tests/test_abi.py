@@ -48,10 +48,10 @@ def test_workspace_bytes_and_validation():
             lb.lb_workspace_bytes(lb.config_from_case(c, "fp64"))
         assert e.value.code == lb.LB_E_INVALID_ARG
     c = lb.config_from_case(case, "fp64")
-    c.bc_x = lb.LB_HALFWAY_BB
+    c.bc_x = 3
     with pytest.raises(lb.LBError) as e:
         lb.lb_workspace_bytes(c)
-    assert e.value.code == lb.LB_E_UNSUPPORTED
+    assert e.value.code == lb.LB_E_INVALID_ARG
     c = lb.config_from_case(case, "fp64")
     c.tile_x = 96
     with pytest.raises(lb.LBError):
@@ -98,6 +98,7 @@ def test_option_validation():
             return e.code
 
     assert code(bc_y=lb.LB_FREE_SLIP) == lb.LB_OK
+    assert code(bc_x=lb.LB_FREE_SLIP) == lb.LB_OK and code(bc_x=lb.LB_HALFWAY_BB) == lb.LB_OK
     assert code(bc_y=3) == lb.LB_E_INVALID_ARG
     assert code(collision=2) == lb.LB_E_INVALID_ARG
     assert code(flow=2) == lb.LB_E_INVALID_ARG
