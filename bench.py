@@ -27,6 +27,40 @@ sys.path.insert(0, ROOT)
 from paper_1909_04166_amd import lb, workloads as W  # noqa: E402
 
 METRIC = "MLUPS (f+g per node-step) & % HBM roofline; p50/p99 solve latency batched vs plain"
+
+# HBM bytes per launch of the step kernel on the 8192^2 grid from two rocprofv3
+# counter passes (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0 KiB, the factors read on the
+# library's copy kernel; see profiles/lb_fused_pmc_tiled8192.md), with the workgroup
+# width the autotuner chose in those runs.  They hold only for the kernel sources
+# with this fingerprint; for any other source the roofline's traffic is null.
+KERNEL_SOURCES = ["paper_1909_04166_amd/csrc/lb_device.hpp", "paper_1909_04166_amd/csrc/lb_kernels.hip",
+                  "paper_1909_04166_amd/csrc/lb_capi.hip", "paper_1909_04166_amd/csrc/lb_internal.hpp",
+                  "paper_1909_04166_amd/build.py"]
+TRAFFIC = {
+    "fingerprint": "4e0091b19393a66f",
+    "workload": "tiled8192",
+    "fp64": {"read": 10162243968, "write": 9670152704, "tile_x": 512},
+    "fp32": {"read": 5249814080, "write": 4869588320, "tile_x": 512},
+    "fp16": {"read": 3130596544, "write": 2529167360, "tile_x": 256},
+}
+
+
+def kernel_fingerprint() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, precision: str, tile_x: int):
+    """Counter-measured bytes per launch, or None when they do not apply."""
+    rec = TRAFFIC.get(precision)
+    if (rec is None or workload != TRAFFIC["workload"] or tile_x != rec["tile_x"]
+            or kernel_fingerprint() != TRAFFIC["fingerprint"]):
+        return None
+    return rec
 HBM_PEAK_GBS = 8000.0
 STORE = {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2}
 
@@ -273,6 +307,7 @@ def main():
     s = STORE[args.precision]
     bytes_per_launch = 36 * s * N
     achieved = bytes_per_launch / (r["ms_kernel"] * 1e-3) / 1e9 if r["ms_kernel"] > 0 else None
+    traffic = measured_traffic(args.workload, args.precision, int(r["tile"][0]))
     out = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -292,7 +327,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-                     "traffic": None,
+                     "traffic": (traffic["read"] + traffic["write"]) if traffic else None,
+                     "traffic_read": traffic["read"] if traffic else None,
+                     "traffic_write": traffic["write"] if traffic else None,
                      "kernel_ms": round(r["ms_kernel"], 5),
                      "alg_bytes_per_launch": bytes_per_launch},
         "stable": r["rc"] == 0 and r["diag"]["nan_flag"] == 0.0,

@@ -71,7 +71,7 @@ lb_status validate(const lb_config* c) {
                          1.0 / (0.5 + 3.0 * c->M)};
     for (double o : om)
         if (!(o > 0.0 && o < 2.0)) return LB_E_INVALID_ARG;
-    if (c->tile_x != 0 && c->tile_x != 64 && c->tile_x != 128 && c->tile_x != 256)
+    if (c->tile_x != 0 && c->tile_x != 64 && c->tile_x != 128 && c->tile_x != 256 && c->tile_x != 512)
         return LB_E_INVALID_ARG;
     if (c->tile_h < 0 || (c->tile_h > 0 && c->tile_h < kMinH)) return LB_E_INVALID_ARG;
     if (c->diag_every < 0) return LB_E_INVALID_ARG;
@@ -445,7 +445,7 @@ double time_candidate(int prec, int kind, int tx, int pf, const LatDesc* d, cons
 std::vector<Sched> candidates(int nx, int ny, int kind) {
     std::vector<Sched> out;
     for (int pf : {0, 1})
-        for (int tx : {64, 128, 256}) {
+        for (int tx : {64, 128, 256, 512}) {
             if (pf && kind != KIND_COUPLED_CASCADED) continue;
             if (tx > 64 && nx <= strip_w(tx / 2)) continue;
             for (int th : {16, 32, 64, 128, 256}) {
@@ -1036,7 +1036,7 @@ lb_status lb_batch_create(int32_t slots, int64_t node_capacity, int32_t precisio
                           lb_batch** out) {
     if (!out || !dev_ws || slots <= 0 || node_capacity < 64 || store_bytes(precision) == 0)
         return LB_E_INVALID_ARG;
-    if (tile_x != 0 && tile_x != 64 && tile_x != 128 && tile_x != 256) return LB_E_INVALID_ARG;
+    if (tile_x != 0 && tile_x != 64 && tile_x != 128 && tile_x != 256 && tile_x != 512) return LB_E_INVALID_ARG;
     if (tile_h < 0 || (tile_h > 0 && tile_h < kMinH)) return LB_E_INVALID_ARG;
     *out = nullptr;
     const BatchLayout L = batch_layout(slots, node_capacity, precision);

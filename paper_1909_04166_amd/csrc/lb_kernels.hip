@@ -30,6 +30,7 @@ static hipError_t launch_tx(int tx, const LatDesc* d, const WorkItem* items, int
     case 64: launch_one<ST, 64, MODE, PF, KIND>(dim3(grid), d, items, n_items, parity, s); break;
     case 128: launch_one<ST, 128, MODE, PF, KIND>(dim3(grid), d, items, n_items, parity, s); break;
     case 256: launch_one<ST, 256, MODE, PF, KIND>(dim3(grid), d, items, n_items, parity, s); break;
+    case 512: launch_one<ST, 512, MODE, PF, KIND>(dim3(grid), d, items, n_items, parity, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -88,6 +89,7 @@ static int occ_st(int kind, int tx, int pf) {
     case 64: return occ_kind<ST, 64>(kind, pf);
     case 128: return occ_kind<ST, 128>(kind, pf);
     case 256: return occ_kind<ST, 256>(kind, pf);
+    case 512: return occ_kind<ST, 512>(kind, pf);
     }
     return 1;
 }

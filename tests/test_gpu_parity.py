@@ -102,7 +102,7 @@ def test_coupling_fields_match_oracle():
         assert err <= 1e-12 * scale, k
 
 
-TILES = [(64, 8), (64, 16), (128, 32), (256, 64)]
+TILES = [(64, 8), (64, 16), (128, 32), (256, 64), (512, 24)]
 
 
 @pytest.mark.parametrize("tile", TILES)
