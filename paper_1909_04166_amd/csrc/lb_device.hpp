@@ -27,27 +27,32 @@ namespace cmlb {
 
 // ------------------------------------------------------------------ storage
 
+// `shifted`: whether the storage holds f_a - w_a shift (16-bit types only).
 struct StF64 {
     using T = double;
     using R = double;
+    static constexpr bool shifted = false;
     static __device__ __forceinline__ R ld(T v) { return v; }
     static __device__ __forceinline__ T st(R v) { return v; }
 };
 struct StF32 {
     using T = float;
     using R = float;
+    static constexpr bool shifted = false;
     static __device__ __forceinline__ R ld(T v) { return v; }
     static __device__ __forceinline__ T st(R v) { return v; }
 };
 struct StF16 {
     using T = _Float16;
     using R = float;
+    static constexpr bool shifted = true;
     static __device__ __forceinline__ R ld(T v) { return (float)v; }
     static __device__ __forceinline__ T st(R v) { return (_Float16)v; }  // round to nearest even
 };
 struct StBF16 {
     using T = uint16_t;
     using R = float;
+    static constexpr bool shifted = true;
     static __device__ __forceinline__ R ld(T v) { return __uint_as_float(((uint32_t)v) << 16); }
     static __device__ __forceinline__ T st(R v) {
         uint32_t u = __float_as_uint(v);
@@ -127,7 +132,7 @@ __device__ __forceinline__ void sto(typename ST::T* plane, uint32_t e, typename 
     *reinterpret_cast<T*>(reinterpret_cast<char*>(plane) + e * (uint32_t)sizeof(T)) = ST::st(v);
 }
 
-// Pull the nine values arriving at (x, r): f_a(x, r) = f~_a(x - e_a).  A source
+// Pull the nine stored values arriving at (x, r): f_a(x, r) = f~_a(x - e_a).  A source
 // beyond a halfway wall is replaced by the opposite direction at the same node
 // (bounce-back), or by the y-mirrored direction at the node the particle left,
 // x - e_ax (specular reflection).  base points at plane 0 of the nine (f or
@@ -135,7 +140,7 @@ __device__ __forceinline__ void sto(typename ST::T* plane, uint32_t e, typename 
 template <class ST>
 __device__ __forceinline__ void pull9(const typename ST::T* __restrict__ base, int64_t P, int nx,
                                       int ny, int wall, int wallx, int x, int xm, int xp, int r,
-                                      typename ST::R sh, typename ST::R out[9]) {
+                                      typename ST::R out[9]) {
     using R = typename ST::R;
     const bool bot = wall && r == 0;       // sources of 2, 5, 6 lie below the wall
     const bool top = wall && r == ny - 1;  // sources of 4, 7, 8 lie above the wall
@@ -151,16 +156,15 @@ __device__ __forceinline__ void pull9(const typename ST::T* __restrict__ base, i
     const int p4 = top ? 2 : 4, p7 = top ? (slip ? 6 : 5) : 7, p8 = top ? (slip ? 5 : 6) : 8;
     const int x5 = (bot && !slip) ? x : xm, x6 = (bot && !slip) ? x : xp;
     const int x7 = (top && !slip) ? x : xp, x8 = (top && !slip) ? x : xm;
-    const R w0 = R(4.0 / 9.0) * sh, w1 = R(1.0 / 9.0) * sh, w5 = R(1.0 / 36.0) * sh;
-    out[0] = ldo<ST>(base, o + x) + w0;
-    out[1] = ldo<ST>(base + P, o + xm) + w1;
-    out[3] = ldo<ST>(base + 3 * P, o + xp) + w1;
-    out[2] = ldo<ST>(base + p2 * P, ob + x) + w1;
-    out[5] = ldo<ST>(base + p5 * P, ob + x5) + w5;
-    out[6] = ldo<ST>(base + p6 * P, ob + x6) + w5;
-    out[4] = ldo<ST>(base + p4 * P, ot + x) + w1;
-    out[7] = ldo<ST>(base + p7 * P, ot + x7) + w5;
-    out[8] = ldo<ST>(base + p8 * P, ot + x8) + w5;
+    out[0] = ldo<ST>(base, o + x);
+    out[1] = ldo<ST>(base + P, o + xm);
+    out[3] = ldo<ST>(base + 3 * P, o + xp);
+    out[2] = ldo<ST>(base + p2 * P, ob + x);
+    out[5] = ldo<ST>(base + p5 * P, ob + x5);
+    out[6] = ldo<ST>(base + p6 * P, ob + x6);
+    out[4] = ldo<ST>(base + p4 * P, ot + x);
+    out[7] = ldo<ST>(base + p7 * P, ot + x7);
+    out[8] = ldo<ST>(base + p8 * P, ot + x8);
     if (wallx) {
         // Lanes on the first or last column replace what arrived from beyond an x
         // wall: bounce-back (opposite direction, same node), or specular reflection
@@ -169,14 +173,14 @@ __device__ __forceinline__ void pull9(const typename ST::T* __restrict__ base, i
         const bool sx = wallx == WALL_SLIP;
         const uint32_t rowb = (uint32_t)rb * (uint32_t)nx, rowt = (uint32_t)rt * (uint32_t)nx;
         if (x == 0) {
-            out[1] = ldo<ST>(base + 3 * P, o + x) + w1;
-            out[5] = (sx && !bot) ? ldo<ST>(base + 6 * P, rowb + x) + w5 : ldo<ST>(base + 7 * P, o + x) + w5;
-            out[8] = (sx && !top) ? ldo<ST>(base + 7 * P, rowt + x) + w5 : ldo<ST>(base + 6 * P, o + x) + w5;
+            out[1] = ldo<ST>(base + 3 * P, o + x);
+            out[5] = (sx && !bot) ? ldo<ST>(base + 6 * P, rowb + x) : ldo<ST>(base + 7 * P, o + x);
+            out[8] = (sx && !top) ? ldo<ST>(base + 7 * P, rowt + x) : ldo<ST>(base + 6 * P, o + x);
         }
         if (x == nx - 1) {
-            out[3] = ldo<ST>(base + 1 * P, o + x) + w1;
-            out[6] = (sx && !bot) ? ldo<ST>(base + 5 * P, rowb + x) + w5 : ldo<ST>(base + 8 * P, o + x) + w5;
-            out[7] = (sx && !top) ? ldo<ST>(base + 8 * P, rowt + x) + w5 : ldo<ST>(base + 5 * P, o + x) + w5;
+            out[3] = ldo<ST>(base + 1 * P, o + x);
+            out[6] = (sx && !bot) ? ldo<ST>(base + 5 * P, rowb + x) : ldo<ST>(base + 8 * P, o + x);
+            out[7] = (sx && !top) ? ldo<ST>(base + 8 * P, rowt + x) : ldo<ST>(base + 5 * P, o + x);
         }
     }
 }
@@ -329,12 +333,18 @@ __device__ __forceinline__ void add_Kc(R v[9], R c0, R c1, R c2, R c3, R c4, R c
     v[8] += (B - c5) - (y2 - x2);
 }
 
+// Stored values of shifted 16-bit storage are s_a = f_a - w_a sh.  The shift's raw
+// moments are (sh, 0, 0, sh/3, sh/3, 0, 0, 0, sh/9), so a collision works on s
+// directly: it adds sh/3 to the two second-order and sh/9 to the fourth-order raw
+// moment, and the update s + K c needs no correction (the shift cancels).  With
+// SH false no instruction is spent on it.
+
 // Pressure-based cascaded collision with its cumulative source (Sec. 4), with
 // omega_0..3 = omega_6..8 = 1 and omega_4 = omega_5 = omv.  The source term
 // K^{-1}(I - Lambda/2) K S and the collision K h are folded into one K c with
 // c_j = h_j + m^s'_j / |K_j|^2 (for j = 0, 1, 2 the omega dependence cancels).
-template <class R>
-__device__ __forceinline__ void hydro_collide(R g[9], const NodeOut<R>& o) {
+template <class R, bool SH = false>
+__device__ __forceinline__ void hydro_collide(R g[9], const NodeOut<R>& o, R sh = R(0)) {
     const R ux = o.ux, uy = o.uy, ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy;
     const R third = R(1.0 / 3.0);
     const R Gam = o.Fpx * ux + o.Fpy * uy;
@@ -346,12 +356,17 @@ __device__ __forceinline__ void hydro_collide(R g[9], const NodeOut<R>& o) {
     const R hw = R(1) - R(0.5) * o.omv;
     // raw moments of gbar
     const R d = (g[5] + g[6]) + (g[7] + g[8]);
-    const R e20 = (g[1] + g[3]) + d;
-    const R e02 = (g[2] + g[4]) + d;
+    R e20 = (g[1] + g[3]) + d;
+    R e02 = (g[2] + g[4]) + d;
     const R e11 = (g[5] - g[6]) + (g[7] - g[8]);
     const R e21 = (g[5] + g[6]) - (g[7] + g[8]);
     const R e12 = (g[5] - g[6]) + (g[8] - g[7]);
-    const R e22 = d;
+    R e22 = d;
+    if constexpr (SH) {
+        e20 += sh * R(1.0 / 3.0);
+        e02 += sh * R(1.0 / 3.0);
+        e22 += sh * R(1.0 / 9.0);
+    }
     const R rc2 = o.rho * third, p = o.p, psi = o.psi;
     const R q4 = R(0.25) * o.omv;
     const R h3 = R(1.0 / 12.0) * (R(2.0 / 3.0) * p + rc2 * (ux2 + uy2) - (e20 + e02));
@@ -385,19 +400,24 @@ __device__ __forceinline__ void hydro_collide(R g[9], const NodeOut<R>& o) {
 
 // Conservative Allen-Cahn cascaded collision (Sec. 5) with omega_1 = omega_2 =
 // omphi and the other rates 1; the first-order equilibria carry M theta n.
-template <class R>
+template <class R, bool SH = false>
 __device__ __forceinline__ void ace_collide(R f[9], R phi, R ux, R uy, R Mth_x, R Mth_y,
-                                            R omphi) {
+                                            R omphi, R sh = R(0)) {
     const R ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy;
     const R k10 = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
     const R k01 = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
     const R d = (f[5] + f[6]) + (f[7] + f[8]);
-    const R k20 = (f[1] + f[3]) + d;
-    const R k02 = (f[2] + f[4]) + d;
+    R k20 = (f[1] + f[3]) + d;
+    R k02 = (f[2] + f[4]) + d;
     const R k11 = (f[5] - f[6]) + (f[7] - f[8]);
     const R k21 = (f[5] + f[6]) - (f[7] + f[8]);
     const R k12 = (f[5] - f[6]) + (f[8] - f[7]);
-    const R k22 = d;
+    R k22 = d;
+    if constexpr (SH) {  // phi already includes the shift
+        k20 += sh * R(1.0 / 3.0);
+        k02 += sh * R(1.0 / 3.0);
+        k22 += sh * R(1.0 / 9.0);
+    }
     const R w6 = omphi * R(1.0 / 6.0);
     const R G1 = w6 * (phi * ux + Mth_x - k10);
     const R G2 = w6 * (phi * uy + Mth_y - k01);
@@ -435,8 +455,8 @@ __device__ __forceinline__ void ace_collide(R f[9], R phi, R ux, R uy, R Mth_x, 
 // Hydrodynamic: equilibrium w_a [p + rho (e.u) + rho (1.5 (e.u)^2 - 0.5 u^2)];
 // source w_a [F_p.u + e.F_t + 4.5 A:(e e) - 1.5 tr A] with A the second-order
 // source moments less c^2 F_p.u I.  Rate omv = omega(nu(phi)).
-template <class R>
-__device__ __forceinline__ void hydro_srt(R g[9], const NodeOut<R>& o) {
+template <class R, bool SH = false>
+__device__ __forceinline__ void hydro_srt(R g[9], const NodeOut<R>& o, R sh = R(0)) {
     const R ux = o.ux, uy = o.uy, om = o.omv, hw = R(1) - R(0.5) * om;
     const R Sx = o.Ftx + o.Fpx, Sy = o.Fty + o.Fpy;
     const R Axx = R(2.0 / 3.0) * Sx * ux, Ayy = R(2.0 / 3.0) * Sy * uy;
@@ -449,7 +469,8 @@ __device__ __forceinline__ void hydro_srt(R g[9], const NodeOut<R>& o) {
         const R AE = R(ex * ex) * Axx + R(ey * ey) * Ayy + R(2 * ex * ey) * Axy;
         const R geq = w * (peq + o.rho * (eu + R(1.5) * eu * eu));
         const R src = w * (s0 + eF + R(4.5) * AE);
-        g[a] += om * (geq - g[a]) + hw * src;
+        const R ga = SH ? g[a] + w * sh : g[a];  // unshifted value
+        g[a] += om * (geq - ga) + hw * src;
     };
     const R w0 = R(4.0 / 9.0), w1 = R(1.0 / 9.0), w5 = R(1.0 / 36.0);
     upd(0, w0, 0, 0);
@@ -459,14 +480,16 @@ __device__ __forceinline__ void hydro_srt(R g[9], const NodeOut<R>& o) {
 
 // Conservative Allen-Cahn: equilibrium w_a [phi (1 + 3 e.u + 4.5 (e.u)^2 - 1.5 u^2)
 // + 3 e.(M theta n)], every moment at rate omphi.
-template <class R>
-__device__ __forceinline__ void ace_srt(R f[9], R phi, R ux, R uy, R Mth_x, R Mth_y, R om) {
+template <class R, bool SH = false>
+__device__ __forceinline__ void ace_srt(R f[9], R phi, R ux, R uy, R Mth_x, R Mth_y, R om,
+                                        R sh = R(0)) {
     const R base = phi * (R(1) - R(1.5) * (ux * ux + uy * uy));
     auto upd = [&](int a, R w, int ex, int ey) {
         const R eu = R(ex) * ux + R(ey) * uy;
         const R en = R(ex) * Mth_x + R(ey) * Mth_y;
         const R feq = w * (base + phi * (R(3) * eu + R(4.5) * eu * eu) + R(3) * en);
-        f[a] += om * (feq - f[a]);
+        const R fa = SH ? f[a] + w * sh : f[a];  // unshifted value
+        f[a] += om * (feq - fa);
     };
     const R w0 = R(4.0 / 9.0), w1 = R(1.0 / 9.0), w5 = R(1.0 / 36.0);
     upd(0, w0, 0, 0);
@@ -525,14 +548,18 @@ __global__ void __launch_bounds__(TX) lb_fused(const LatDesc* __restrict__ descs
             const bool have = PF && k >= 5;  // rows already pulled during the last collision
             // ---- A: phi at the leading row
             if (inA) {
-                if (!have) pull9<ST>(src, P, nx, ny, wall, wallx, xc, xm, xp, map_row(L, ny, wall), K.shf, f0);
-                s_phi[L & 3][t] = sum9(f0);
+                if (!have) pull9<ST>(src, P, nx, ny, wall, wallx, xc, xm, xp, map_row(L, ny, wall), f0);
+                R ph = sum9(f0);
+                if constexpr (ST::shifted) ph += K.shf;
+                s_phi[L & 3][t] = ph;
             }
             // ---- B: pbar one row behind
             if (k >= 2 && inB) {
                 const int Lg = L - 1;
-                if (!have) pull9<ST>(srcg, P, nx, ny, wall, wallx, xc, xm, xp, map_row(Lg, ny, wall), K.shg, g0);
-                s_pb[Lg & 3][t] = sum9(g0);
+                if (!have) pull9<ST>(srcg, P, nx, ny, wall, wallx, xc, xm, xp, map_row(Lg, ny, wall), g0);
+                R pb = sum9(g0);
+                if constexpr (ST::shifted) pb += K.shg;
+                s_pb[Lg & 3][t] = pb;
             }
             __syncthreads();
             // ---- D: gradient, normal or chemical potential at row L-1
@@ -586,34 +613,28 @@ __global__ void __launch_bounds__(TX) lb_fused(const LatDesc* __restrict__ descs
                     idx = (uint32_t)C * (uint32_t)nx + (uint32_t)xc;
                 }
                 if constexpr (MODE == MODE_STEP) {
-                    const R w0 = R(4.0 / 9.0), w1 = R(1.0 / 9.0), w5 = R(1.0 / 36.0);
                     if (inF) {
                         const R Mth = K.M * (K.four_W * in.phi * (R(1) - in.phi));
                         if constexpr (COLL == COLL_SRT)
-                            ace_srt<R>(f2, in.phi, o.ux, o.uy, Mth * in.nx, Mth * in.ny, K.omphi);
+                            ace_srt<R, ST::shifted>(f2, in.phi, o.ux, o.uy, Mth * in.nx, Mth * in.ny, K.omphi, K.shf);
                         else
-                            ace_collide<R>(f2, in.phi, o.ux, o.uy, Mth * in.nx, Mth * in.ny, K.omphi);
+                            ace_collide<R, ST::shifted>(f2, in.phi, o.ux, o.uy, Mth * in.nx, Mth * in.ny, K.omphi,
+                                                        K.shf);
 #pragma unroll
-                        for (int a = 0; a < 9; ++a) {
-                            const R wa = a == 0 ? w0 : (a < 5 ? w1 : w5);
-                            sto<ST>(dst + a * P, idx, f2[a] - wa * K.shf);
-                        }
+                        for (int a = 0; a < 9; ++a) sto<ST>(dst + a * P, idx, f2[a]);
                     }
                     if (pre && inA)  // next leading row into the freed f registers
-                        pull9<ST>(src, P, nx, ny, wall, wallx, xc, xm, xp, map_row(L + 1, ny, wall), K.shf, f2);
+                        pull9<ST>(src, P, nx, ny, wall, wallx, xc, xm, xp, map_row(L + 1, ny, wall), f2);
                     if (inF) {
                         if constexpr (COLL == COLL_SRT)
-                            hydro_srt<R>(g1, o);
+                            hydro_srt<R, ST::shifted>(g1, o, K.shg);
                         else
-                            hydro_collide<R>(g1, o);
+                            hydro_collide<R, ST::shifted>(g1, o, K.shg);
 #pragma unroll
-                        for (int a = 0; a < 9; ++a) {
-                            const R wa = a == 0 ? w0 : (a < 5 ? w1 : w5);
-                            sto<ST>(dstg + a * P, idx, g1[a] - wa * K.shg);
-                        }
+                        for (int a = 0; a < 9; ++a) sto<ST>(dstg + a * P, idx, g1[a]);
                     }
                     if (pre && inB)  // next pbar row into the freed gbar registers
-                        pull9<ST>(srcg, P, nx, ny, wall, wallx, xc, xm, xp, map_row(L, ny, wall), K.shg, g1);
+                        pull9<ST>(srcg, P, nx, ny, wall, wallx, xc, xm, xp, map_row(L, ny, wall), g1);
                 } else if constexpr (MODE == MODE_FIELDS) {
                     if (inF) {
                         double* F = D.fields;
@@ -702,8 +723,10 @@ __global__ void __launch_bounds__(TX) lb_ace(const LatDesc* __restrict__ descs,
         for (int k = 0; k < H + 2; ++k) {
             const int L = it.y0 - 1 + k;
             if (inA) {
-                pull9<ST>(src, P, nx, ny, wall, wallx, xc, xm, xp, map_row(L, ny, wall), shf, f0);
-                s_phi[L & 3][t] = sum9(f0);
+                pull9<ST>(src, P, nx, ny, wall, wallx, xc, xm, xp, map_row(L, ny, wall), f0);
+                R ph = sum9(f0);
+                if constexpr (ST::shifted) ph += shf;
+                s_phi[L & 3][t] = ph;
             }
             __syncthreads();
             if (k >= 2 && inF) {
@@ -718,15 +741,11 @@ __global__ void __launch_bounds__(TX) lb_ace(const LatDesc* __restrict__ descs,
                 if constexpr (MODE == MODE_STEP) {
                     const R Mth = Mm * (four_W * phi * (R(1) - phi));
                     if constexpr (COLL == COLL_SRT)
-                        ace_srt<R>(f1, phi, ux, uy, Mth * ix, Mth * iy, omphi);
+                        ace_srt<R, ST::shifted>(f1, phi, ux, uy, Mth * ix, Mth * iy, omphi, shf);
                     else
-                        ace_collide<R>(f1, phi, ux, uy, Mth * ix, Mth * iy, omphi);
-                    const R w0 = R(4.0 / 9.0), w1 = R(1.0 / 9.0), w5 = R(1.0 / 36.0);
+                        ace_collide<R, ST::shifted>(f1, phi, ux, uy, Mth * ix, Mth * iy, omphi, shf);
 #pragma unroll
-                    for (int a = 0; a < 9; ++a) {
-                        const R wa = a == 0 ? w0 : (a < 5 ? w1 : w5);
-                        sto<ST>(dst + a * P, idx, f1[a] - wa * shf);
-                    }
+                    for (int a = 0; a < 9; ++a) sto<ST>(dst + a * P, idx, f1[a]);
                 } else {
                     double* F = D.fields;
                     const int64_t N = (int64_t)nx * ny;
