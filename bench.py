@@ -37,11 +37,11 @@ KERNEL_SOURCES = ["paper_1909_04166_amd/csrc/lb_device.hpp", "paper_1909_04166_a
                   "paper_1909_04166_amd/csrc/lb_capi.hip", "paper_1909_04166_amd/csrc/lb_internal.hpp",
                   "paper_1909_04166_amd/build.py"]
 TRAFFIC = {
-    "fingerprint": "4e0091b19393a66f",
+    "fingerprint": "0e2e6067741cd245",
     "workload": "tiled8192",
-    "fp64": {"read": 10162243968, "write": 9670152704, "tile_x": 512},
-    "fp32": {"read": 5249814080, "write": 4869588320, "tile_x": 512},
-    "fp16": {"read": 3130596544, "write": 2529167360, "tile_x": 256},
+    "fp64": {"read": 10163072832, "write": 9696698080, "tile_x": 512},
+    "fp32": {"read": 5250255936, "write": 4875280720, "tile_x": 512},
+    "fp16": {"read": 2824307648, "write": 2472623088, "tile_x": 512},
 }
 
 
