@@ -230,21 +230,36 @@ def bench_stability(steps: int = 20000):
 
 
 def cpu_baseline(target_s: float = 15.0):
+    """The FP64 oracle as it stands, on the host cores: a bounded sample (about
+    target_s seconds) of the workload's 128^2 droplet tile with OpenMP over rows on
+    all cores, then the same tile single-threaded for a shorter sample."""
+    import ctypes
     import oracle
     case, phi0 = W.droplet(128, 25.0, W=5.0)
-    o = oracle.Oracle(case, phi0)
-    t0 = time.perf_counter()
-    o.step(20)
-    dt = time.perf_counter() - t0
     n_nodes = case["nx"] * case["ny"]
-    steps = int(max(50, min(20000, target_s / max(dt / 20, 1e-9))))
-    t0 = time.perf_counter()
-    o.step(steps)
-    dt = time.perf_counter() - t0
+
+    def timed(threads, budget_s):
+        gomp = ctypes.CDLL("libgomp.so.1")
+        gomp.omp_set_num_threads(int(threads))
+        o = oracle.Oracle(case, phi0)
+        o.step(10)  # thread start-up
+        t0 = time.perf_counter()
+        o.step(40)
+        dt = time.perf_counter() - t0
+        steps = int(max(50, min(500000, budget_s / max(dt / 40, 1e-9))))
+        t0 = time.perf_counter()
+        o.step(steps)
+        dt = time.perf_counter() - t0
+        return steps, dt
+
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    steps, dt = timed(cores, target_s)
+    steps1, dt1 = timed(1, target_s / 3)
     return {"value": n_nodes * steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
             "sample": f"FP64 oracle, 128x128 droplet tile of the workload (R=25, ratio 1000, W 5), "
-                      f"{steps} steps in {dt:.1f} s, OpenMP over rows"}
+                      f"{steps} steps in {dt:.1f} s, OpenMP over rows on {cores} threads",
+            "single_thread_MLUPS": round(n_nodes * steps1 / dt1 / 1e6, 2),
+            "single_thread_sample": f"{steps1} steps in {dt1:.1f} s, 1 thread"}
 
 
 def main():
