@@ -31,6 +31,7 @@ namespace cmlb {
 struct StF64 {
     using T = double;
     using R = double;
+    static constexpr int waves = 2;  // resident waves per SIMD the kernels are built for
     static constexpr bool shifted = false;
     static __device__ __forceinline__ R ld(T v) { return v; }
     static __device__ __forceinline__ T st(R v) { return v; }
@@ -38,6 +39,7 @@ struct StF64 {
 struct StF32 {
     using T = float;
     using R = float;
+    static constexpr int waves = 4;  // resident waves per SIMD the kernels are built for
     static constexpr bool shifted = false;
     static __device__ __forceinline__ R ld(T v) { return v; }
     static __device__ __forceinline__ T st(R v) { return v; }
@@ -45,6 +47,7 @@ struct StF32 {
 struct StF16 {
     using T = _Float16;
     using R = float;
+    static constexpr int waves = 4;  // resident waves per SIMD the kernels are built for
     static constexpr bool shifted = true;
     static __device__ __forceinline__ R ld(T v) { return (float)v; }
     static __device__ __forceinline__ T st(R v) { return (_Float16)v; }  // round to nearest even
@@ -52,6 +55,7 @@ struct StF16 {
 struct StBF16 {
     using T = uint16_t;
     using R = float;
+    static constexpr int waves = 4;  // resident waves per SIMD the kernels are built for
     static constexpr bool shifted = true;
     static __device__ __forceinline__ R ld(T v) { return __uint_as_float(((uint32_t)v) << 16); }
     static __device__ __forceinline__ T st(R v) {
@@ -71,12 +75,12 @@ struct alignas(16) LatDesc {
     int32_t wall_y;     // walls at y = -1/2, ny - 1/2: 0 none (periodic), 1 halfway
                         // bounce-back, 2 halfway specular reflection (free slip)
     int32_t st_form;    // 0 geometric (+ Marangoni), 1 chemical potential
-    int64_t plane;      // element stride between planes
+    int64_t plane;      // nodes per plane rounded up to 64 (buffer sizes, velocity planes)
     int32_t surf;       // kappa~(y): 0 linear, 1 Langmuir of an imposed linear psi(y)
     int32_t flow;       // 0 coupled, 1 phase field only under an imposed velocity
     int32_t wall_x;     // walls at x = -1/2, nx - 1/2: same codes as wall_y
     int32_t pad2;
-    void* buf[2];       // 18 planes each
+    void* buf[2];       // 18 stored values per node each, row-interleaved (see row_stride)
     double* fields;     // FP64 output planes (phi, p, ux, uy or the 9 coupling planes)
     void* vel;          // imposed velocity: planes ux, uy in the compute type (flow 1)
     double* ktab;       // Langmuir law: kappa~(y) for y < ny, then d kappa~/dy (surf 1)
@@ -132,55 +136,64 @@ __device__ __forceinline__ void sto(typename ST::T* plane, uint32_t e, typename 
     *reinterpret_cast<T*>(reinterpret_cast<char*>(plane) + e * (uint32_t)sizeof(T)) = ST::st(v);
 }
 
+// Buffer layout: the 18 stored values of a lattice are row-interleaved, value q
+// (0..8 f, 9..17 gbar) of node (x, y) at element (18 y + q) nx + x.  The nine f
+// (or gbar) rows of one lattice row form one contiguous block, so a workgroup
+// streams three blocks per row instead of eighteen scattered planes.  Row bases
+// are formed in 64-bit uniform arithmetic, lane offsets within a block in 32 bits.
+__device__ __forceinline__ int64_t row_stride(int nx) { return 18 * (int64_t)nx; }
+
 // Pull the nine stored values arriving at (x, r): f_a(x, r) = f~_a(x - e_a).  A source
 // beyond a halfway wall is replaced by the opposite direction at the same node
 // (bounce-back), or by the y-mirrored direction at the node the particle left,
-// x - e_ax (specular reflection).  base points at plane 0 of the nine (f or
-// gbar); xm, xp are the periodic neighbours of x.
+// x - e_ax (specular reflection).  base points at value 0 of row 0 of the group
+// (f or gbar); xm, xp are the periodic neighbours of x.
 template <class ST>
-__device__ __forceinline__ void pull9(const typename ST::T* __restrict__ base, int64_t P, int nx,
-                                      int ny, int wall, int wallx, int x, int xm, int xp, int r,
+__device__ __forceinline__ void pull9(const typename ST::T* __restrict__ base, int nx, int ny,
+                                      int wall, int wallx, int x, int xm, int xp, int r,
                                       typename ST::R out[9]) {
-    using R = typename ST::R;
+    using T = typename ST::T;
     const bool bot = wall && r == 0;       // sources of 2, 5, 6 lie below the wall
     const bool top = wall && r == ny - 1;  // sources of 4, 7, 8 lie above the wall
     const bool slip = wall == WALL_SLIP;
     const int rb = r == 0 ? ny - 1 : r - 1;
     const int rt = r == ny - 1 ? 0 : r + 1;
-    const uint32_t o = (uint32_t)r * (uint32_t)nx;
-    // Every source is selected (uniform plane and row, per-lane column) so that
-    // the nine loads issue together without branches.
-    const uint32_t ob = bot ? o : (uint32_t)rb * (uint32_t)nx;
-    const uint32_t ot = top ? o : (uint32_t)rt * (uint32_t)nx;
+    const int64_t RS = row_stride(nx);
+    const T* ro = base + r * RS;
+    const T* rbp = base + rb * RS;  // row below (periodic image)
+    const T* rtp = base + rt * RS;  // row above
+    // Every source is selected (uniform value block and row, per-lane column) so
+    // that the nine loads issue together without branches.
+    const T* sb = bot ? ro : rbp;
+    const T* st = top ? ro : rtp;
     const int p2 = bot ? 4 : 2, p5 = bot ? (slip ? 8 : 7) : 5, p6 = bot ? (slip ? 7 : 8) : 6;
     const int p4 = top ? 2 : 4, p7 = top ? (slip ? 6 : 5) : 7, p8 = top ? (slip ? 5 : 6) : 8;
     const int x5 = (bot && !slip) ? x : xm, x6 = (bot && !slip) ? x : xp;
     const int x7 = (top && !slip) ? x : xp, x8 = (top && !slip) ? x : xm;
-    out[0] = ldo<ST>(base, o + x);
-    out[1] = ldo<ST>(base + P, o + xm);
-    out[3] = ldo<ST>(base + 3 * P, o + xp);
-    out[2] = ldo<ST>(base + p2 * P, ob + x);
-    out[5] = ldo<ST>(base + p5 * P, ob + x5);
-    out[6] = ldo<ST>(base + p6 * P, ob + x6);
-    out[4] = ldo<ST>(base + p4 * P, ot + x);
-    out[7] = ldo<ST>(base + p7 * P, ot + x7);
-    out[8] = ldo<ST>(base + p8 * P, ot + x8);
+    out[0] = ldo<ST>(ro, x);
+    out[1] = ldo<ST>(ro + nx, xm);
+    out[3] = ldo<ST>(ro + 3 * nx, xp);
+    out[2] = ldo<ST>(sb + p2 * nx, x);
+    out[5] = ldo<ST>(sb + p5 * nx, x5);
+    out[6] = ldo<ST>(sb + p6 * nx, x6);
+    out[4] = ldo<ST>(st + p4 * nx, x);
+    out[7] = ldo<ST>(st + p7 * nx, x7);
+    out[8] = ldo<ST>(st + p8 * nx, x8);
     if (wallx) {
         // Lanes on the first or last column replace what arrived from beyond an x
         // wall: bounce-back (opposite direction, same node), or specular reflection
         // (x-mirrored direction leaving the node of the same column one row over);
         // beyond an x and a y wall at once, bounce-back.
         const bool sx = wallx == WALL_SLIP;
-        const uint32_t rowb = (uint32_t)rb * (uint32_t)nx, rowt = (uint32_t)rt * (uint32_t)nx;
         if (x == 0) {
-            out[1] = ldo<ST>(base + 3 * P, o + x);
-            out[5] = (sx && !bot) ? ldo<ST>(base + 6 * P, rowb + x) : ldo<ST>(base + 7 * P, o + x);
-            out[8] = (sx && !top) ? ldo<ST>(base + 7 * P, rowt + x) : ldo<ST>(base + 6 * P, o + x);
+            out[1] = ldo<ST>(ro + 3 * nx, x);
+            out[5] = (sx && !bot) ? ldo<ST>(rbp + 6 * nx, x) : ldo<ST>(ro + 7 * nx, x);
+            out[8] = (sx && !top) ? ldo<ST>(rtp + 7 * nx, x) : ldo<ST>(ro + 6 * nx, x);
         }
         if (x == nx - 1) {
-            out[3] = ldo<ST>(base + 1 * P, o + x);
-            out[6] = (sx && !bot) ? ldo<ST>(base + 5 * P, rowb + x) : ldo<ST>(base + 8 * P, o + x);
-            out[7] = (sx && !top) ? ldo<ST>(base + 8 * P, rowt + x) : ldo<ST>(base + 5 * P, o + x);
+            out[3] = ldo<ST>(ro + 1 * nx, x);
+            out[6] = (sx && !bot) ? ldo<ST>(rbp + 5 * nx, x) : ldo<ST>(ro + 8 * nx, x);
+            out[7] = (sx && !top) ? ldo<ST>(rtp + 8 * nx, x) : ldo<ST>(ro + 5 * nx, x);
         }
     }
 }
@@ -503,7 +516,7 @@ __device__ __forceinline__ void ace_srt(R f[9], R phi, R ux, R uy, R Mth_x, R Mt
 // registers receive the next row's pulled values, so those loads are in flight
 // while the rest of the collision computes (no extra registers).
 template <class ST, int TX, int MODE, bool PF, int COLL = COLL_CASCADED>
-__global__ void __launch_bounds__(TX) lb_fused(const LatDesc* __restrict__ descs,
+__global__ void __launch_bounds__(TX) __attribute__((amdgpu_waves_per_eu(ST::waves))) lb_fused(const LatDesc* __restrict__ descs,
                                                const WorkItem* __restrict__ items, int n_items,
                                                int parity) {
     using R = typename ST::R;
@@ -519,13 +532,12 @@ __global__ void __launch_bounds__(TX) lb_fused(const LatDesc* __restrict__ descs
         if (it.y1 <= it.y0) continue;  // padding item (uniform over the block)
         const LatDesc& D = descs[it.inst];
         const int nx = D.nx, ny = D.ny, wall = D.wall_y, wallx = D.wall_x, chem = D.st_form;
-        const int64_t P = D.plane;
         const KConst<R> K = load_const<R>(D);
         const double* ktab = D.surf ? D.ktab : nullptr;  // per-row Langmuir table
         const T* __restrict__ src = reinterpret_cast<const T*>(D.buf[parity]);
         T* __restrict__ dst = reinterpret_cast<T*>(D.buf[parity ^ 1]);
-        const T* __restrict__ srcg = src + 9 * P;
-        T* __restrict__ dstg = dst + 9 * P;
+        const T* __restrict__ srcg = src + 9 * nx;  // gbar values of row 0
+        const int64_t RS = row_stride(nx);
         const int w = min(TX - 4, nx - it.x0);  // interior columns of this strip
         const bool inA = t < w + 4;              // phi cells
         const bool inB = t >= 1 && t < w + 3;    // pbar and normal cells
@@ -548,7 +560,7 @@ __global__ void __launch_bounds__(TX) lb_fused(const LatDesc* __restrict__ descs
             const bool have = PF && k >= 5;  // rows already pulled during the last collision
             // ---- A: phi at the leading row
             if (inA) {
-                if (!have) pull9<ST>(src, P, nx, ny, wall, wallx, xc, xm, xp, map_row(L, ny, wall), f0);
+                if (!have) pull9<ST>(src, nx, ny, wall, wallx, xc, xm, xp, map_row(L, ny, wall), f0);
                 R ph = sum9(f0);
                 if constexpr (ST::shifted) ph += K.shf;
                 s_phi[L & 3][t] = ph;
@@ -556,7 +568,7 @@ __global__ void __launch_bounds__(TX) lb_fused(const LatDesc* __restrict__ descs
             // ---- B: pbar one row behind
             if (k >= 2 && inB) {
                 const int Lg = L - 1;
-                if (!have) pull9<ST>(srcg, P, nx, ny, wall, wallx, xc, xm, xp, map_row(Lg, ny, wall), g0);
+                if (!have) pull9<ST>(srcg, nx, ny, wall, wallx, xc, xm, xp, map_row(Lg, ny, wall), g0);
                 R pb = sum9(g0);
                 if constexpr (ST::shifted) pb += K.shg;
                 s_pb[Lg & 3][t] = pb;
@@ -620,21 +632,23 @@ __global__ void __launch_bounds__(TX) lb_fused(const LatDesc* __restrict__ descs
                         else
                             ace_collide<R, ST::shifted>(f2, in.phi, o.ux, o.uy, Mth * in.nx, Mth * in.ny, K.omphi,
                                                         K.shf);
+                        T* drow = dst + C * RS;
 #pragma unroll
-                        for (int a = 0; a < 9; ++a) sto<ST>(dst + a * P, idx, f2[a]);
+                        for (int a = 0; a < 9; ++a) sto<ST>(drow + a * nx, (uint32_t)xc, f2[a]);
                     }
                     if (pre && inA)  // next leading row into the freed f registers
-                        pull9<ST>(src, P, nx, ny, wall, wallx, xc, xm, xp, map_row(L + 1, ny, wall), f2);
+                        pull9<ST>(src, nx, ny, wall, wallx, xc, xm, xp, map_row(L + 1, ny, wall), f2);
                     if (inF) {
                         if constexpr (COLL == COLL_SRT)
                             hydro_srt<R, ST::shifted>(g1, o, K.shg);
                         else
                             hydro_collide<R, ST::shifted>(g1, o, K.shg);
+                        T* drow = dst + C * RS + 9 * nx;
 #pragma unroll
-                        for (int a = 0; a < 9; ++a) sto<ST>(dstg + a * P, idx, g1[a]);
+                        for (int a = 0; a < 9; ++a) sto<ST>(drow + a * nx, (uint32_t)xc, g1[a]);
                     }
                     if (pre && inB)  // next pbar row into the freed gbar registers
-                        pull9<ST>(srcg, P, nx, ny, wall, wallx, xc, xm, xp, map_row(L, ny, wall), g1);
+                        pull9<ST>(srcg, nx, ny, wall, wallx, xc, xm, xp, map_row(L, ny, wall), g1);
                 } else if constexpr (MODE == MODE_FIELDS) {
                     if (inF) {
                         double* F = D.fields;
@@ -704,7 +718,8 @@ __global__ void __launch_bounds__(TX) lb_ace(const LatDesc* __restrict__ descs,
         if (it.y1 <= it.y0) continue;
         const LatDesc& D = descs[it.inst];
         const int nx = D.nx, ny = D.ny, wall = D.wall_y, wallx = D.wall_x;
-        const int64_t P = D.plane;
+        const int64_t P = D.plane;  // stride of the two velocity planes
+        const int64_t RS = row_stride(nx);
         const R shf = R(D.shift_f), four_W = R(D.four_W), Mm = R(D.M), omphi = R(D.omphi);
         const T* __restrict__ src = reinterpret_cast<const T*>(D.buf[parity]);
         T* __restrict__ dst = reinterpret_cast<T*>(D.buf[parity ^ 1]);
@@ -723,7 +738,7 @@ __global__ void __launch_bounds__(TX) lb_ace(const LatDesc* __restrict__ descs,
         for (int k = 0; k < H + 2; ++k) {
             const int L = it.y0 - 1 + k;
             if (inA) {
-                pull9<ST>(src, P, nx, ny, wall, wallx, xc, xm, xp, map_row(L, ny, wall), f0);
+                pull9<ST>(src, nx, ny, wall, wallx, xc, xm, xp, map_row(L, ny, wall), f0);
                 R ph = sum9(f0);
                 if constexpr (ST::shifted) ph += shf;
                 s_phi[L & 3][t] = ph;
@@ -744,8 +759,9 @@ __global__ void __launch_bounds__(TX) lb_ace(const LatDesc* __restrict__ descs,
                         ace_srt<R, ST::shifted>(f1, phi, ux, uy, Mth * ix, Mth * iy, omphi, shf);
                     else
                         ace_collide<R, ST::shifted>(f1, phi, ux, uy, Mth * ix, Mth * iy, omphi, shf);
+                    T* drow = dst + C * RS;
 #pragma unroll
-                    for (int a = 0; a < 9; ++a) sto<ST>(dst + a * P, idx, f1[a]);
+                    for (int a = 0; a < 9; ++a) sto<ST>(drow + a * nx, (uint32_t)xc, f1[a]);
                 } else {
                     double* F = D.fields;
                     const int64_t N = (int64_t)nx * ny;

@@ -189,6 +189,12 @@ __device__ __forceinline__ void pull_source(const LatDesc& D, int a, int x, int 
     }
 }
 
+// Element of stored value q (0..8 f, 9..17 gbar) of node (x, y): the row-interleaved
+// layout of the step kernels.
+__device__ __forceinline__ int64_t sidx(int nx, int q, int y, int x) {
+    return ((int64_t)y * 18 + q) * nx + x;
+}
+
 // State at t = 0: every arriving population is f_a = w_a phi0, gbar_a = 0.
 template <class ST>
 __global__ void k_init(const LatDesc* __restrict__ dp, const double* __restrict__ phi0, int cur) {
@@ -203,10 +209,9 @@ __global__ void k_init(const LatDesc* __restrict__ dp, const double* __restrict_
         for (int a = 0; a < 9; ++a) {
             int b, xs, ys;
             pull_source(D, a, x, y, &b, &xs, &ys);
-            const int64_t ks = (int64_t)ys * nx + xs;
             const double w = wgt(a);  // w_b = w_a for opposite and mirrored directions
-            buf[b * D.plane + ks] = ST::st((typename ST::R)(w * phi0[k] - w * D.shift_f));
-            buf[(9 + b) * D.plane + ks] = ST::st((typename ST::R)(0.0 - w * D.shift_g));
+            buf[sidx(nx, b, ys, xs)] = ST::st((typename ST::R)(w * phi0[k] - w * D.shift_f));
+            buf[sidx(nx, 9 + b, ys, xs)] = ST::st((typename ST::R)(0.0 - w * D.shift_g));
         }
     }
 }
@@ -220,14 +225,15 @@ __global__ void k_set_plane(const LatDesc* __restrict__ dp, const double* __rest
     const int nx = D.nx, ny = D.ny;
     const int64_t N = (int64_t)nx * ny;
     using T = typename ST::T;
-    T* buf = reinterpret_cast<T*>(D.buf[cur]) + (which ? 9 * D.plane : 0);
+    T* buf = reinterpret_cast<T*>(D.buf[cur]);
+    const int q0 = which ? 9 : 0;
     const double sh = which ? D.shift_g : D.shift_f;
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < N;
          k += (int64_t)gridDim.x * blockDim.x) {
         const int y = (int)(k / nx), x = (int)(k % nx);
         int b, xs, ys;
         pull_source(D, a, x, y, &b, &xs, &ys);
-        buf[b * D.plane + (int64_t)ys * nx + xs] = ST::st((typename ST::R)(stage[k] - wgt(a) * sh));
+        buf[sidx(nx, q0 + b, ys, xs)] = ST::st((typename ST::R)(stage[k] - wgt(a) * sh));
     }
 }
 
@@ -239,14 +245,15 @@ __global__ void k_get_plane(const LatDesc* __restrict__ dp, double* __restrict__
     const int nx = D.nx, ny = D.ny;
     const int64_t N = (int64_t)nx * ny;
     using T = typename ST::T;
-    const T* buf = reinterpret_cast<const T*>(D.buf[cur]) + (which ? 9 * D.plane : 0);
+    const T* buf = reinterpret_cast<const T*>(D.buf[cur]);
+    const int q0 = which ? 9 : 0;
     const double sh = which ? D.shift_g : D.shift_f;
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < N;
          k += (int64_t)gridDim.x * blockDim.x) {
         const int y = (int)(k / nx), x = (int)(k % nx);
         int b, xs, ys;
         pull_source(D, a, x, y, &b, &xs, &ys);
-        out[k] = (double)ST::ld(buf[b * D.plane + (int64_t)ys * nx + xs]) + wgt(a) * sh;
+        out[k] = (double)ST::ld(buf[sidx(nx, q0 + b, ys, xs)]) + wgt(a) * sh;
     }
 }
 
