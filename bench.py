@@ -142,12 +142,7 @@ def bench_served(precision: str, n_req: int, rate: float, budget_gb: float = 24.
     500-20000 steps, aspect 1.1-1.5, ratio 1000, W 5), continuous batching."""
     from paper_1909_04166_amd import serve
     trace = W.serve_arrivals(n_req, seed, rate)
-    reqs = []
-    for i, a in enumerate(trace):
-        case, _ = W.ellipse(8, a["aspect"])  # parameters only; the field is built at admission
-        case.update(nx=a["side"], ny=a["side"], W=5.0)
-        reqs.append(serve.Request(rid=i, case=case, phi0=None, steps=a["steps"], arrival=a["t"],
-                                  make=(lambda s=a["side"], r=a["aspect"]: W.ellipse(s, r, W=5.0)[1])))
+    reqs = served_requests(n_req, rate, seed)
     per_node = 2 * 18 * STORE[precision] + 32
     cap = int(budget_gb * 1e9 / per_node)
     S = serve.Server(slots=512, node_capacity=cap, precision=precision, tick=128)
@@ -160,6 +155,71 @@ def bench_served(precision: str, n_req: int, rate: float, budget_gb: float = 24.
         if stats.get(k) is not None:
             stats[k] = round(stats[k], 3)
     return stats
+
+
+def served_requests(n_req: int, rate: float, seed: int = 5):
+    """The served stream's requests (elliptic drops, W 5), fields built on demand."""
+    from paper_1909_04166_amd import serve
+    trace = W.serve_arrivals(n_req, seed, rate)
+    reqs = []
+    for i, a in enumerate(trace):
+        case, _ = W.ellipse(8, a["aspect"])
+        case.update(nx=a["side"], ny=a["side"], W=5.0)
+        reqs.append(serve.Request(rid=i, case=case, phi0=None, steps=a["steps"], arrival=a["t"],
+                                  make=(lambda s=a["side"], r=a["aspect"]: W.ellipse(s, r, W=5.0)[1])))
+    return reqs
+
+
+def bench_plain_fifo(n_req: int, rate: float):
+    """The plain form of the served stream: requests solved one at a time in FP64,
+    first come first served, each on its own lattice (no batching)."""
+    import torch
+    reqs = served_requests(n_req, rate)
+    t0 = time.perf_counter()
+    lat, updates = [], 0
+    for r in reqs:
+        now = time.perf_counter() - t0
+        if now < r.arrival:
+            time.sleep(r.arrival - now)
+        side = r.case["nx"]  # fixed tile (no per-shape autotuning in the plain form)
+        tile = (64 if side < 256 else (128 if side < 1024 else 256), 32)
+        L = lb.Lattice(r.case, r.make(), "fp64", tile=tile)
+        L.step(r.steps)
+        L.diagnostics()  # synchronizes
+        L.close()
+        done = time.perf_counter() - t0
+        lat.append(done - r.arrival)
+        updates += r.nodes * r.steps
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = np.array(lat)
+    return {"requests": n_req, "rate_per_s": rate, "MLUPS": round(updates / wall / 1e6, 1),
+            "p50_s": round(float(np.percentile(lat, 50)), 3), "p99_s": round(float(np.percentile(lat, 99)), 3),
+            "wall_s": round(wall, 2)}
+
+
+def bench_batched_same(n_req: int, rate: float, precision: str = "fp16"):
+    """The same requests as bench_plain_fifo through the continuous-batching server."""
+    from paper_1909_04166_amd import serve
+    reqs = served_requests(n_req, rate)
+    per_node = 2 * 18 * STORE[precision] + 32
+    S = serve.Server(slots=512, node_capacity=int(24e9 / per_node), precision=precision, tick=128)
+    st = S.run(reqs)
+    S.close()
+    return {"requests": n_req, "rate_per_s": rate, "MLUPS": round(st["MLUPS"], 1),
+            "p50_s": round(st["p50_s"], 3), "p99_s": round(st["p99_s"], 3), "wall_s": round(st["wall_s"], 2)}
+
+
+def bench_configs():
+    """The paper's configurations that fit the MALL (accuracy runs; launch and
+    latency bound): MLUPS in FP64 and FP32."""
+    out = {}
+    for name, steps in (("droplet128", 1000), ("rt256", 2000)):
+        c, p, _ = make_workload(name)
+        for prec in ("fp64", "fp32"):
+            rr = time_lattice(c, p, prec, steps, 50)
+            out[f"{name}_{prec}"] = round(c["nx"] * c["ny"] * steps / rr["wall_s"] / 1e6, 1)
+    return out
 
 
 def bench_variants(side: int, steps: int, warmup: int):
@@ -255,11 +315,21 @@ def cpu_baseline(target_s: float = 15.0):
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     steps, dt = timed(cores, target_s)
     steps1, dt1 = timed(1, target_s / 3)
+    # config 2 (Rayleigh-Taylor 256 x 1024), all cores, a short sample
+    gomp = ctypes.CDLL("libgomp.so.1")
+    gomp.omp_set_num_threads(int(cores))
+    rc, rp = W.config("rt256")
+    o = oracle.Oracle(rc, rp)
+    o.step(5)
+    t0 = time.perf_counter()
+    o.step(40)
+    rt_dt = time.perf_counter() - t0
     return {"value": n_nodes * steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
             "sample": f"FP64 oracle, 128x128 droplet tile of the workload (R=25, ratio 1000, W 5), "
                       f"{steps} steps in {dt:.1f} s, OpenMP over rows on {cores} threads",
             "single_thread_MLUPS": round(n_nodes * steps1 / dt1 / 1e6, 2),
-            "single_thread_sample": f"{steps1} steps in {dt1:.1f} s, 1 thread"}
+            "single_thread_sample": f"{steps1} steps in {dt1:.1f} s, 1 thread",
+            "rt256x1024_MLUPS": round(rc["nx"] * rc["ny"] * 40 / rt_dt / 1e6, 2)}
 
 
 def main():
@@ -349,6 +419,7 @@ def main():
                      "alg_bytes_per_launch": bytes_per_launch},
         "stable": r["rc"] == 0 and r["diag"]["nan_flag"] == 0.0,
     }
+    out["paper_configs"] = bench_configs()
     if args.extra:
         extra = {}
         for prec in ("fp32", "fp16", "bf16"):
@@ -358,12 +429,6 @@ def main():
             extra[prec] = {"MLUPS": round(N * args.steps / rr["wall_s"] / 1e6, 1),
                            "kernel_GBs": round(36 * STORE[prec] * N / (rr["ms_kernel"] * 1e-3) / 1e9, 1),
                            "tile": list(rr["tile"])}
-        for wl in ("rt256", "droplet128"):
-            c2, p2, d2 = make_workload(wl)
-            for prec in ("fp64", "fp32"):
-                rr = time_lattice(c2, p2, prec, 2000, 50)
-                extra[f"{wl}_{prec}"] = {"MLUPS": round(c2["nx"] * c2["ny"] * 2000 / rr["wall_s"] / 1e6, 1),
-                                         "tile": list(rr["tile"])}
         out["extra"] = extra
     if args.batched:
         out["batched"] = {p: bench_batched(p, 5000) for p in ("fp16", "bf16", "fp32")}
@@ -375,8 +440,13 @@ def main():
         # a second stream at 70 % of the measured capacity, so latency is not pure queue growth
         mean_work = 1.93e9
         low = bench_served("fp16", 200, 0.7 * cap_glups * 1e9 / mean_work)
+        # plain form of the same stream: 60 requests of the 0.7-load trace, FP64,
+        # one lattice at a time, beside the same 60 through the batching server
+        rate7 = 0.7 * cap_glups * 1e9 / mean_work
         out["served"] = {"saturated": sat, "load_0.7": low,
-                         "vs_plain_fp64": round(sat["MLUPS"] / out["value"], 3)}
+                         "vs_plain_fp64": round(sat["MLUPS"] / out["value"], 3),
+                         "latency_batched_vs_plain": {"batched_fp16": bench_batched_same(60, rate7),
+                                                      "plain_fp64_fifo": bench_plain_fifo(60, rate7)}}
     if args.variants:
         side = case["nx"] if args.workload.startswith("tiled") else 8192
         out["variants"] = bench_variants(side, args.steps, args.warmup)

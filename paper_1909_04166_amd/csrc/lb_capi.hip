@@ -962,13 +962,16 @@ lb_status batch_set_sched(lb_batch* b, Sched sc) {
 lb_status batch_autotune(lb_batch* b) {
     std::vector<LatShape> lats = batch_shapes(b);
     if (lats.empty()) return batch_set_sched(b, b->sc);
-    int min_nx = 1 << 30;
     int max_ny = 0;
-    for (auto& l : lats) { min_nx = std::min(min_nx, l.nx); max_ny = std::max(max_ny, l.ny); }
+    std::vector<int> widths;
+    for (auto& l : lats) { widths.push_back(l.nx); max_ny = std::max(max_ny, l.ny); }
+    // candidate widths are filtered on the median lattice width: narrower lattices
+    // then run one strip with idle lanes, which the timing weighs
+    std::nth_element(widths.begin(), widths.begin() + widths.size() / 2, widths.end());
+    const int med_nx = widths[widths.size() / 2];
     Sched best_sc = b->sc;
     double best = 1e30;
-    for (Sched sc : candidates(min_nx, max_ny, b->kind)) {
-        if (sc.tx > 128) continue;
+    for (Sched sc : candidates(med_nx, max_ny, b->kind)) {
         std::vector<WorkItem> items;
         if (!build_schedule(lats, b->prec, b->kind, sc, b->max_items, items)) continue;
         HIPC(hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(WorkItem),
