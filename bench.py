@@ -313,6 +313,15 @@ def cpu_baseline(target_s: float = 15.0):
         return steps, dt
 
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     steps, dt = timed(cores, target_s)
     steps1, dt1 = timed(1, target_s / 3)
     # config 2 (Rayleigh-Taylor 256 x 1024), all cores, a short sample
@@ -329,7 +338,8 @@ def cpu_baseline(target_s: float = 15.0):
                       f"{steps} steps in {dt:.1f} s, OpenMP over rows on {cores} threads",
             "single_thread_MLUPS": round(n_nodes * steps1 / dt1 / 1e6, 2),
             "single_thread_sample": f"{steps1} steps in {dt1:.1f} s, 1 thread",
-            "rt256x1024_MLUPS": round(rc["nx"] * rc["ny"] * 40 / rt_dt / 1e6, 2)}
+            "rt256x1024_MLUPS": round(rc["nx"] * rc["ny"] * 40 / rt_dt / 1e6, 2),
+            "host": f"{model}, {os.cpu_count()} logical CPUs visible"}
 
 
 def main():

@@ -255,3 +255,77 @@ def test_checkpoint_resume_is_bit_identical():
     b.step(20)
     fb, gb = b.get_dist()
     assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 2e-5)])
+def test_bench_grid_tiles_equal_and_match_oracle(precision, tol):
+    """The benchmark's own workload and launch configuration (the 8192^2 grid of
+    64 x 64 periodic tiles of the 128^2 droplet, autotuned schedule): nothing in
+    the step depends on absolute position here, so every tile stays bit-identical
+    to every other, and the first tile matches the oracle's 128^2 run (FP64 within
+    1e-10; FP32 phi within 2e-5)."""
+    case, phi0 = W.droplet(128, 25.0, W=5.0)
+    big, bphi = W.tiled(case, phi0, 64, 64)
+    _print_case("bench grid", big, precision=precision)
+    g = lb.Lattice(big, bphi, precision)
+    del bphi
+    g.step(20)
+    print(f"   schedule {g.tile}", flush=True)
+    phi, p, ux, uy = g.fields()
+    g.close()
+    o = oracle.Oracle(case, phi0)
+    o.step(20)
+    ref = o.fields()
+    for a, b in zip((phi, p, ux, uy), ref):
+        t = a.reshape(64, 128, 64, 128)
+        first = t[0, :, 0, :]
+        assert np.array_equal(t, np.broadcast_to(first[None, :, None, :], t.shape)), "tiles differ"
+    err = np.abs(phi[:128, :128] - ref[0]).max()
+    print(f"   tile vs oracle: phi {err:.3e}", flush=True)
+    assert err <= tol
+
+
+@pytest.mark.parametrize("shape", [(8, 8), (9, 13), (13, 8), (70, 8), (8, 70)])
+@pytest.mark.parametrize("bcx,bcy", [("periodic", "periodic"), ("periodic", "wall"), ("slip", "wall"),
+                                     ("wall", "slip")])
+def test_smallest_lattices(shape, bcx, bcy):
+    """Lattices at the minimum size (8 in either direction) and ragged small
+    shapes, every wall kind: one strip, halo lanes wrapping or mirroring onto the
+    few columns there are."""
+    nx, ny = shape
+    case = W.base_case(nx, ny, bc_x=bcx, bc_y=bcy, rho_A=10.0, rho_B=1.0, sigma0=0.01,
+                       gy=-1e-5 if bcy != "periodic" else 0.0)
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    phi0 = W.tanh_profile(3.0 - np.hypot(x - nx / 2 + 0.3, y - ny / 2 + 0.2), 4.0)
+    _print_case("smallest", case)
+    g = lb.Lattice(case, phi0, "fp64")
+    o = oracle.Oracle(case, phi0)
+    g.step(40)
+    o.step(40)
+    fg, gg = g.get_dist()
+    fo, go = o.get_dist()
+    assert np.abs(fg - fo).max() <= 1e-10
+    assert np.abs(gg - go).max() <= 1e-10 * max(1.0, np.abs(go).max())
+
+
+def test_degenerate_calls():
+    """Zero steps leave the state and step count unchanged; an empty batch steps
+    without work; a batch emptied by removals keeps working when refilled."""
+    case, phi0 = W.droplet(64, 12.0)
+    L = lb.Lattice(case, phi0, "fp64")
+    f0, g0 = L.get_dist()
+    assert L.step(0) == lb.LB_OK and L.t == 0
+    f1, g1 = L.get_dist()
+    assert np.array_equal(f0, f1) and np.array_equal(g0, g1)
+    B = lb.Batch(2, 10000, "fp64")
+    B.step(3)
+    assert B.usage() == (0, 0)
+    s = B.add(case, phi0)
+    B.remove(s)
+    B.step(2)
+    s = B.add(case, phi0)
+    B.step(5)
+    L.step(5)
+    for a, b in zip(B.fields(s), L.fields()):
+        assert np.array_equal(a, b)
+    B.close()
