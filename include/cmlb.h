@@ -105,7 +105,10 @@ typedef struct lb_config {
     int32_t collision;       /* LB_CASCADED or LB_SRT */
     int32_t flow;            /* LB_FLOW_COUPLED or LB_FLOW_IMPOSED */
     int32_t surf;            /* LB_SIGMA_LINEAR or LB_SIGMA_LANGMUIR */
-    int32_t reserved;        /* must be 0 */
+    int32_t tile_pf;         /* with tile_x and tile_h both set: 1 selects the kernel
+                                variant that prefetches the next rows during the
+                                collision (LB_CASCADED with LB_FLOW_COUPLED only);
+                                must be 0 otherwise */
     double beta, psi_a, psi_G; /* Langmuir law parameters */
 } lb_config;
 

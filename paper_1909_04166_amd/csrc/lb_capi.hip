@@ -49,7 +49,10 @@ lb_status validate(const lb_config* c) {
     if (c->collision != LB_CASCADED && c->collision != LB_SRT) return LB_E_INVALID_ARG;
     if (c->flow != LB_FLOW_COUPLED && c->flow != LB_FLOW_IMPOSED) return LB_E_INVALID_ARG;
     if (c->surf != LB_SIGMA_LINEAR && c->surf != LB_SIGMA_LANGMUIR) return LB_E_INVALID_ARG;
-    if (c->reserved != 0) return LB_E_INVALID_ARG;
+    if (c->tile_pf < 0 || c->tile_pf > 1) return LB_E_INVALID_ARG;
+    if (c->tile_pf != 0 && (c->tile_x == 0 || c->tile_h == 0 || c->collision != LB_CASCADED ||
+                            c->flow != LB_FLOW_COUPLED))
+        return LB_E_INVALID_ARG;
     if (c->force_ref < LB_FREF_MEAN || c->force_ref > LB_FREF_NONE) return LB_E_INVALID_ARG;
     if (c->st_form != LB_ST_GEOMETRIC && c->st_form != LB_ST_CHEMPOT) return LB_E_INVALID_ARG;
     if (store_bytes(c->precision) == 0) return LB_E_INVALID_ARG;
@@ -444,9 +447,9 @@ double time_candidate(int prec, int kind, int tx, int pf, const LatDesc* d, cons
 // the coupled cascaded kernel only).
 std::vector<Sched> candidates(int nx, int ny, int kind) {
     std::vector<Sched> out;
-    for (int pf : {0, 1})
+    for (int pf : {PF_HOLD, PF_PREFETCH})
         for (int tx : {64, 128, 256, 512}) {
-            if (pf && kind != KIND_COUPLED_CASCADED) continue;
+            if (pf != PF_HOLD && kind != KIND_COUPLED_CASCADED) continue;
             if (tx > 64 && nx <= strip_w(tx / 2)) continue;
             for (int th : {16, 32, 64, 128, 256}) {
                 if (th > ny && th != 16) continue;
@@ -571,6 +574,7 @@ lb_status lb_create(const lb_config* cfg, void* dev_ws, uint64_t ws_bytes, void*
     Sched sc = default_sched(cfg->nx, cfg->ny);
     if (cfg->tile_x) sc.tx = cfg->tile_x;
     if (cfg->tile_h) sc.th = cfg->tile_h;
+    sc.pf = cfg->tile_pf;
     h->tuned = (cfg->tile_x != 0 && cfg->tile_h != 0) || (int64_t)cfg->nx * cfg->ny < (1 << 16);
     st = set_sched(h, sc);
     if (st != LB_OK) return fail(st);

@@ -107,6 +107,7 @@ enum { MODE_STEP = 0, MODE_FIELDS = 1, MODE_COUPLING = 2 };
 // Collision models of the coupled step: the cascaded pair, or the SRT pair of the
 // stability comparison.
 enum { COLL_CASCADED = 0, COLL_SRT = 1 };
+enum { PF_HOLD = 0, PF_PREFETCH = 1 };
 enum { WALL_NONE = 0, WALL_BOUNCE = 1, WALL_SLIP = 2 };
 // Kernel behind a step: coupled pair or phase field alone, cascaded or SRT.
 enum { KIND_COUPLED_CASCADED = 0, KIND_COUPLED_SRT = 1, KIND_ACE_CASCADED = 2, KIND_ACE_SRT = 3 };
@@ -123,17 +124,23 @@ __device__ __forceinline__ int map_row(int L, int ny, int wall) {
 }
 
 // Element access through a uniform plane base and a 32-bit byte offset (every
-// plane is < 4 GiB), so addresses are one VALU add on top of a scalar base.
+// row block is < 4 GiB).  The pointers reach the kernels through the descriptor,
+// so the compiler cannot see that they are global; naming the global address
+// space here gives global (not flat) loads and stores with the base in scalar
+// registers and a 32-bit per-lane offset, and keeps them off the LDS wait counter.
+template <class T>
+using gmem_t = __attribute__((address_space(1))) T;
 template <class ST>
 __device__ __forceinline__ typename ST::R ldo(const typename ST::T* plane, uint32_t e) {
     using T = typename ST::T;
-    return ST::ld(*reinterpret_cast<const T*>(reinterpret_cast<const char*>(plane) +
-                                              e * (uint32_t)sizeof(T)));
+    const gmem_t<const char>* p = (const gmem_t<const char>*)plane;
+    return ST::ld(*(const gmem_t<const T>*)(p + e * (uint32_t)sizeof(T)));
 }
 template <class ST>
 __device__ __forceinline__ void sto(typename ST::T* plane, uint32_t e, typename ST::R v) {
     using T = typename ST::T;
-    *reinterpret_cast<T*>(reinterpret_cast<char*>(plane) + e * (uint32_t)sizeof(T)) = ST::st(v);
+    gmem_t<char>* p = (gmem_t<char>*)plane;
+    *(gmem_t<T>*)(p + e * (uint32_t)sizeof(T)) = ST::st(v);
 }
 
 // Buffer layout: the 18 stored values of a lattice are row-interleaved, value q
@@ -512,13 +519,14 @@ __device__ __forceinline__ void ace_srt(R f[9], R phi, R ux, R uy, R Mth_x, R Mt
 
 // ------------------------------------------------------------- fused kernel
 
-// PF: once a lane has stored its post-collision f (and later gbar), the freed
-// registers receive the next row's pulled values, so those loads are in flight
-// while the rest of the collision computes (no extra registers).
-template <class ST, int TX, int MODE, bool PF, int COLL = COLL_CASCADED>
-__global__ void __launch_bounds__(TX) __attribute__((amdgpu_waves_per_eu(ST::waves))) lb_fused(const LatDesc* __restrict__ descs,
-                                               const WorkItem* __restrict__ items, int n_items,
-                                               int parity) {
+// The values pulled for phi (two rows ahead of the collision) and for pbar (one
+// row ahead) stay in registers until their row collides.  PF_PREFETCH: once a lane
+// has stored its post-collision f (and later gbar), the freed registers receive
+// the next row's pulled values, so those loads are in flight while the rest of
+// the collision computes (no extra registers).
+template <class ST, int TX, int MODE, int PF, int COLL = COLL_CASCADED>
+__global__ void __launch_bounds__(TX) __attribute__((amdgpu_waves_per_eu(ST::waves)))
+lb_fused(const LatDesc* __restrict__ descs, const WorkItem* __restrict__ items, int n_items, int parity) {
     using R = typename ST::R;
     using T = typename ST::T;
     __shared__ R s_phi[4][TX];
@@ -557,7 +565,7 @@ __global__ void __launch_bounds__(TX) __attribute__((amdgpu_waves_per_eu(ST::wav
         const int H = it.y1 - it.y0;
         for (int k = 0; k < H + 4; ++k) {
             const int L = it.y0 - 2 + k;
-            const bool have = PF && k >= 5;  // rows already pulled during the last collision
+            const bool have = PF == PF_PREFETCH && k >= 5;  // rows already pulled during the last collision
             // ---- A: phi at the leading row
             if (inA) {
                 if (!have) pull9<ST>(src, nx, ny, wall, wallx, xc, xm, xp, map_row(L, ny, wall), f0);
@@ -602,7 +610,7 @@ __global__ void __launch_bounds__(TX) __attribute__((amdgpu_waves_per_eu(ST::wav
             // ---- F: collide row C = L - 2
             if (k >= 4) {
                 const int C = L - 2;
-                const bool pre = PF && MODE == MODE_STEP && k + 1 < H + 4;
+                const bool pre = PF == PF_PREFETCH && MODE == MODE_STEP && k + 1 < H + 4;
                 NodeIn<R> in;
                 NodeOut<R> o;
                 uint32_t idx = 0;
@@ -675,7 +683,7 @@ __global__ void __launch_bounds__(TX) __attribute__((amdgpu_waves_per_eu(ST::wav
                 }
             }
             // ---- rotate the register pipeline
-            if (PF && MODE == MODE_STEP && k >= 4) {
+            if (PF == PF_PREFETCH && MODE == MODE_STEP && k >= 4) {
 #pragma unroll
                 for (int a = 0; a < 9; ++a) {
                     const R nf = f2[a];  // prefetched leading row

@@ -6,22 +6,22 @@ namespace cmlb {
 // ------------------------------------------------------------ fused step
 
 // The kernel behind a step: the coupled pair (lb_fused) or the phase field alone
-// (lb_ace), with the cascaded or the SRT collisions.  The SRT variants exist
-// without row prefetching only.
-template <class ST, int TX, int MODE, bool PF, int KIND>
+// (lb_ace), with the cascaded or the SRT collisions.  The variant that prefetches
+// rows (PF_PREFETCH) exists for the coupled cascaded kernel only.
+template <class ST, int TX, int MODE, int PF, int KIND>
 static void launch_one(dim3 grid, const LatDesc* d, const WorkItem* items, int n_items, int parity,
                        hipStream_t s) {
     if constexpr (KIND == KIND_COUPLED_CASCADED)
         hipLaunchKernelGGL((lb_fused<ST, TX, MODE, PF, COLL_CASCADED>), grid, dim3(TX), 0, s, d, items, n_items, parity);
     else if constexpr (KIND == KIND_COUPLED_SRT)
-        hipLaunchKernelGGL((lb_fused<ST, TX, MODE, false, COLL_SRT>), grid, dim3(TX), 0, s, d, items, n_items, parity);
+        hipLaunchKernelGGL((lb_fused<ST, TX, MODE, PF_HOLD, COLL_SRT>), grid, dim3(TX), 0, s, d, items, n_items, parity);
     else if constexpr (KIND == KIND_ACE_CASCADED)
         hipLaunchKernelGGL((lb_ace<ST, TX, MODE, COLL_CASCADED>), grid, dim3(TX), 0, s, d, items, n_items, parity);
     else
         hipLaunchKernelGGL((lb_ace<ST, TX, MODE, COLL_SRT>), grid, dim3(TX), 0, s, d, items, n_items, parity);
 }
 
-template <class ST, int MODE, bool PF, int KIND>
+template <class ST, int MODE, int PF, int KIND>
 static hipError_t launch_tx(int tx, const LatDesc* d, const WorkItem* items, int n_items, int grid,
                             int parity, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
@@ -41,14 +41,15 @@ static hipError_t launch_step_st(int kind, int tx, int pf, const LatDesc* d, con
                                  int n_items, int grid, int parity, hipStream_t s) {
     switch (kind) {
     case KIND_COUPLED_CASCADED:
-        return pf ? launch_tx<ST, MODE_STEP, true, KIND_COUPLED_CASCADED>(tx, d, items, n_items, grid, parity, s)
-                  : launch_tx<ST, MODE_STEP, false, KIND_COUPLED_CASCADED>(tx, d, items, n_items, grid, parity, s);
+        if (pf == PF_PREFETCH)
+            return launch_tx<ST, MODE_STEP, PF_PREFETCH, KIND_COUPLED_CASCADED>(tx, d, items, n_items, grid, parity, s);
+        return launch_tx<ST, MODE_STEP, PF_HOLD, KIND_COUPLED_CASCADED>(tx, d, items, n_items, grid, parity, s);
     case KIND_COUPLED_SRT:
-        return launch_tx<ST, MODE_STEP, false, KIND_COUPLED_SRT>(tx, d, items, n_items, grid, parity, s);
+        return launch_tx<ST, MODE_STEP, PF_HOLD, KIND_COUPLED_SRT>(tx, d, items, n_items, grid, parity, s);
     case KIND_ACE_CASCADED:
-        return launch_tx<ST, MODE_STEP, false, KIND_ACE_CASCADED>(tx, d, items, n_items, grid, parity, s);
+        return launch_tx<ST, MODE_STEP, PF_HOLD, KIND_ACE_CASCADED>(tx, d, items, n_items, grid, parity, s);
     case KIND_ACE_SRT:
-        return launch_tx<ST, MODE_STEP, false, KIND_ACE_SRT>(tx, d, items, n_items, grid, parity, s);
+        return launch_tx<ST, MODE_STEP, PF_HOLD, KIND_ACE_SRT>(tx, d, items, n_items, grid, parity, s);
     }
     return hipErrorInvalidValue;
 }
@@ -74,9 +75,9 @@ template <class ST, int TX>
 static int occ_kind(int kind, int pf) {
     switch (kind) {
     case KIND_COUPLED_CASCADED:
-        return pf ? occ_of(lb_fused<ST, TX, MODE_STEP, true, COLL_CASCADED>, TX)
-                  : occ_of(lb_fused<ST, TX, MODE_STEP, false, COLL_CASCADED>, TX);
-    case KIND_COUPLED_SRT: return occ_of(lb_fused<ST, TX, MODE_STEP, false, COLL_SRT>, TX);
+        if (pf == PF_PREFETCH) return occ_of(lb_fused<ST, TX, MODE_STEP, PF_PREFETCH, COLL_CASCADED>, TX);
+        return occ_of(lb_fused<ST, TX, MODE_STEP, PF_HOLD, COLL_CASCADED>, TX);
+    case KIND_COUPLED_SRT: return occ_of(lb_fused<ST, TX, MODE_STEP, PF_HOLD, COLL_SRT>, TX);
     case KIND_ACE_CASCADED: return occ_of(lb_ace<ST, TX, MODE_STEP, COLL_CASCADED>, TX);
     case KIND_ACE_SRT: return occ_of(lb_ace<ST, TX, MODE_STEP, COLL_SRT>, TX);
     }
@@ -111,10 +112,10 @@ static hipError_t launch_extract_st(int kind, int mode, const LatDesc* d, const 
                                     int n_items, int parity, hipStream_t s) {
     const bool ace = kind == KIND_ACE_CASCADED || kind == KIND_ACE_SRT;
     if (mode == MODE_FIELDS)
-        return ace ? launch_tx<ST, MODE_FIELDS, false, KIND_ACE_CASCADED>(64, d, items64, n_items, 0, parity, s)
-                   : launch_tx<ST, MODE_FIELDS, false, KIND_COUPLED_CASCADED>(64, d, items64, n_items, 0, parity, s);
-    return ace ? launch_tx<ST, MODE_COUPLING, false, KIND_ACE_CASCADED>(64, d, items64, n_items, 0, parity, s)
-               : launch_tx<ST, MODE_COUPLING, false, KIND_COUPLED_CASCADED>(64, d, items64, n_items, 0, parity, s);
+        return ace ? launch_tx<ST, MODE_FIELDS, PF_HOLD, KIND_ACE_CASCADED>(64, d, items64, n_items, 0, parity, s)
+                   : launch_tx<ST, MODE_FIELDS, PF_HOLD, KIND_COUPLED_CASCADED>(64, d, items64, n_items, 0, parity, s);
+    return ace ? launch_tx<ST, MODE_COUPLING, PF_HOLD, KIND_ACE_CASCADED>(64, d, items64, n_items, 0, parity, s)
+               : launch_tx<ST, MODE_COUPLING, PF_HOLD, KIND_COUPLED_CASCADED>(64, d, items64, n_items, 0, parity, s);
 }
 
 hipError_t launch_extract(int prec, int kind, int mode, const LatDesc* d, const WorkItem* items64,

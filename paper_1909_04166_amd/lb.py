@@ -45,7 +45,7 @@ class lb_config(ctypes.Structure):
         ("u_max", ctypes.c_double),
         ("tile_x", ctypes.c_int32), ("tile_h", ctypes.c_int32),
         ("collision", ctypes.c_int32), ("flow", ctypes.c_int32),
-        ("surf", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("surf", ctypes.c_int32), ("tile_pf", ctypes.c_int32),
         ("beta", ctypes.c_double), ("psi_a", ctypes.c_double), ("psi_G", ctypes.c_double),
     ]
 
@@ -144,9 +144,10 @@ def _dptr(a: np.ndarray | None):
 
 
 def config_from_case(case: dict, precision: str = "fp64", diag_every: int = 0,
-                     tile: tuple[int, int] = (0, 0), shift_f: float = 0.5, shift_g: float = 0.0,
+                     tile: tuple = (0, 0), shift_f: float = 0.5, shift_g: float = 0.0,
                      u_max: float = 0.0) -> lb_config:
-    """Translate a case dictionary (paper_1909_04166_amd.workloads) into lb_config."""
+    """Translate a case dictionary (paper_1909_04166_amd.workloads) into lb_config.
+    tile: (tile_x, tile_h) or (tile_x, tile_h, tile_pf); zeros autotune."""
     c = lb_config()
     c.nx, c.ny = int(case["nx"]), int(case["ny"])
     c.bc_x = LB_BC[case.get("bc_x", "periodic")]
@@ -163,6 +164,7 @@ def config_from_case(case: dict, precision: str = "fp64", diag_every: int = 0,
     c.gx, c.gy = float(case.get("gx", 0.0)), float(case.get("gy", 0.0))
     c.shift_f, c.shift_g, c.u_max = float(shift_f), float(shift_g), float(u_max)
     c.tile_x, c.tile_h = int(tile[0]), int(tile[1])
+    c.tile_pf = int(tile[2]) if len(tile) > 2 else 0
     c.collision = LB_COLLISION[case.get("collision", "cascaded")]
     c.flow = LB_FLOW[case.get("flow", "coupled")]
     c.surf = LB_SIGMA[case.get("surf", "linear")]
@@ -367,7 +369,7 @@ class Lattice:
     """One lattice in a torch-allocated device workspace on the current stream."""
 
     def __init__(self, case: dict, phi0: np.ndarray | None = None, precision: str = "fp64",
-                 diag_every: int = 0, tile: tuple[int, int] = (0, 0), shift_f: float = 0.5,
+                 diag_every: int = 0, tile: tuple = (0, 0), shift_f: float = 0.5,
                  shift_g: float = 0.0, u_max: float = 0.0, device: str = "cuda:0"):
         torch = _torch()
         self.case = dict(case)

@@ -103,7 +103,10 @@ def test_option_validation():
     assert code(collision=2) == lb.LB_E_INVALID_ARG
     assert code(flow=2) == lb.LB_E_INVALID_ARG
     assert code(surf=2) == lb.LB_E_INVALID_ARG
-    assert code(reserved=1) == lb.LB_E_INVALID_ARG
+    assert code(tile_pf=1) == lb.LB_E_INVALID_ARG  # row variant without a fixed tile
+    assert code(tile_pf=1, tile_x=128, tile_h=16) == lb.LB_OK
+    assert code(tile_pf=2, tile_x=128, tile_h=16) == lb.LB_E_INVALID_ARG
+    assert code(tile_pf=1, tile_x=128, tile_h=16, collision=1) == lb.LB_E_INVALID_ARG
     assert code(st_form=1) == lb.LB_E_UNSUPPORTED  # Langmuir with the chemical-potential form
     assert code(psi_a=1.0) == lb.LB_E_INVALID_ARG
     assert code(psi_G=1.0 / 200.0) == lb.LB_E_INVALID_ARG  # psi reaches 1 on the last row
