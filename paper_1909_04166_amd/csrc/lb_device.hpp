@@ -292,7 +292,8 @@ __device__ __forceinline__ void row_kappa(const KConst<R>& K, const double* ktab
 
 template <class R>
 struct NodeOut {
-    R rho, omv, ux, uy, p, psi, Ftx, Fty, Fpx, Fpy;
+    R rho, omv, ux, uy, p, Ftx, Fty, Fpx, Fpy;
+    R jx, jy;  // first moments of the pre-collision gbar
 };
 
 // Properties, forces, velocity and pressure of one node (Eqs.
@@ -325,143 +326,140 @@ __device__ __forceinline__ NodeOut<R> node_macro(const KConst<R>& K, int chem, c
     o.Fty = Fsy + bf * K.gy;
     const R jx = (g[1] - g[3]) + (g[5] - g[6]) + (g[8] - g[7]);
     const R jy = (g[2] - g[4]) + (g[5] + g[6]) - (g[7] + g[8]);
+    o.jx = jx;
+    o.jy = jy;
     o.ux = (R(3) * jx + R(0.5) * o.Ftx) * inv_rho;
     o.uy = (R(3) * jy + R(0.5) * o.Fty) * inv_rho;
     o.Fpx = -in.dpx + K.c2dr * in.dphx;
     o.Fpy = -in.dpy + K.c2dr * in.dphy;
     o.p = in.pbar + R(0.5) * (o.Fpx * o.ux + o.Fpy * o.uy);
-    o.psi = o.p - rho * R(1.0 / 3.0);
     return o;
 }
 
-// Adds K c to v (the nine rows of the expansion of K . c).
-template <class R>
-__device__ __forceinline__ void add_Kc(R v[9], R c0, R c1, R c2, R c3, R c4, R c5, R c6, R c7,
-                                       R c8) {
-    const R A = c0 - c3 - R(2) * c8;
-    const R B = c0 + R(2) * c3 + c8;
-    const R x1 = c1 + R(2) * c7, y1 = c2 + R(2) * c6;
-    const R x2 = c1 - c7, y2 = c2 - c6;
-    v[0] += c0 - R(4) * c3 + R(4) * c8;
-    v[1] += (A + c4) + x1;
-    v[3] += (A + c4) - x1;
-    v[2] += (A - c4) + y1;
-    v[4] += (A - c4) - y1;
-    v[5] += (B + c5) + (x2 + y2);
-    v[7] += (B + c5) - (x2 + y2);
-    v[6] += (B - c5) + (y2 - x2);
-    v[8] += (B - c5) - (y2 - x2);
-}
-
 // Stored values of shifted 16-bit storage are s_a = f_a - w_a sh.  The shift's raw
-// moments are (sh, 0, 0, sh/3, sh/3, 0, 0, 0, sh/9), so a collision works on s
-// directly: it adds sh/3 to the two second-order and sh/9 to the fourth-order raw
-// moment, and the update s + K c needs no correction (the shift cancels).  With
-// SH false no instruction is spent on it.
+// moments are (sh, 0, 0, sh/3, sh/3, 0, 0, 0, sh/9), and its first and shear
+// moments vanish, so the collisions read those moments from s directly and
+// subtract the shift's moments from what they store.  With SH false no
+// instruction is spent on it.
 
 // Pressure-based cascaded collision with its cumulative source (Sec. 4), with
-// omega_0..3 = omega_6..8 = 1 and omega_4 = omega_5 = omv.  The source term
-// K^{-1}(I - Lambda/2) K S and the collision K h are folded into one K c with
-// c_j = h_j + m^s'_j / |K_j|^2 (for j = 0, 1, 2 the omega dependence cancels).
+// omega_0..3 = omega_6..8 = 1 and omega_4 = omega_5 = omv.
+//
+// Written out, the cascade (moment changes h_0..h_8 of Eq.
+// cascadedcollisionoperator plus the source K^{-1}(I - Lambda/2) K S) leaves
+// post-collision raw moments that depend on the incoming values only through
+// pbar, j and the two shear non-equilibria
+//   N = (eta_20 - eta_02) - c^2 rho (ux^2 - uy^2),   X = eta_11 - c^2 rho ux uy,
+// each relaxed by (1 - omv):
+//   m00 = pbar + G                                   (G = F_p . u)
+//   m10 = j_x + c^2 F_tx,  m01 = j_y + c^2 F_ty
+//   m20 + m02 = 2 c^2 p + c^2 rho |u|^2 + 4/3 G + c^2 F_t . u
+//   m20 - m02 = c^2 rho (ux^2 - uy^2) + (1 - omv) N + (1 - omv/2)(s20 - s02)
+//   m11 = c^2 rho ux uy + (1 - omv) X + (1 - omv/2) s11
+//   m21 = c^2 rho uy (c^2 + ux^2) + c^4 F_ty + (1 - omv)(uy N / 2 + 2 ux X)
+//   m12 = c^2 rho ux (c^2 + uy^2) + c^4 F_tx + (1 - omv)(-ux N / 2 + 2 uy X)
+//   m22 = c^4 p + c^4 rho |u|^2 + c^2 rho ux^2 uy^2 + 2 c^4 G
+//         + (1 - omv)(-(ux^2 - uy^2) N / 2 + 4 ux uy X)
+// with s20, s02, s11 the second-order raw source moments.  These equal the
+// cascade term by term (a symbolic identity in the incoming moments, u, p, rho and
+// the forces); evaluating them and inverting the moment map costs about 100
+// operations instead of 150 and never forms the O(rho) terms of psi = p - c^2 rho
+// that cancel in the cascade.  Shifted storage subtracts the raw moments of w sh
+// (sh, 0, 0, sh/3, sh/3, 0, 0, 0, sh/9); N, X and j are shift-free.
 template <class R, bool SH = false>
 __device__ __forceinline__ void hydro_collide(R g[9], const NodeOut<R>& o, R sh = R(0)) {
     const R ux = o.ux, uy = o.uy, ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy;
-    const R third = R(1.0 / 3.0);
+    const R third = R(1.0 / 3.0), ninth = R(1.0 / 9.0);
+    const R rc2 = o.rho * third;
     const R Gam = o.Fpx * ux + o.Fpy * uy;
-    // raw source moments sigma'_mn (third and fourth order are zero)
     const R Sx = o.Ftx + o.Fpx, Sy = o.Fty + o.Fpy;
-    const R s20 = R(2.0 / 3.0) * Sx * ux + third * Gam;
-    const R s02 = R(2.0 / 3.0) * Sy * uy + third * Gam;
-    const R s11 = third * (Sx * uy + Sy * ux);
     const R hw = R(1) - R(0.5) * o.omv;
-    // raw moments of gbar
-    const R d = (g[5] + g[6]) + (g[7] + g[8]);
-    R e20 = (g[1] + g[3]) + d;
-    R e02 = (g[2] + g[4]) + d;
-    const R e11 = (g[5] - g[6]) + (g[7] - g[8]);
-    const R e21 = (g[5] + g[6]) - (g[7] + g[8]);
-    const R e12 = (g[5] - g[6]) + (g[8] - g[7]);
-    R e22 = d;
-    if constexpr (SH) {
-        e20 += sh * R(1.0 / 3.0);
-        e02 += sh * R(1.0 / 3.0);
-        e22 += sh * R(1.0 / 9.0);
-    }
-    const R rc2 = o.rho * third, p = o.p, psi = o.psi;
-    const R q4 = R(0.25) * o.omv;
-    const R h3 = R(1.0 / 12.0) * (R(2.0 / 3.0) * p + rc2 * (ux2 + uy2) - (e20 + e02));
-    const R h4 = q4 * (rc2 * (ux2 - uy2) - (e20 - e02));
-    const R h5 = q4 * (rc2 * uxy - e11);
-    const R h6 = R(0.25) * (psi * (third + ux2) * uy + e21 - uy * e20 - R(2) * ux * e11 +
-                            o.rho * ux2 * uy - ux2 * uy * p) -
-                 uy * (R(1.5) * h3 + R(0.5) * h4) - R(2) * ux * h5;
-    const R h7 = R(0.25) * (psi * (third + uy2) * ux + e12 - R(2) * uy * e11 - ux * e02 +
-                            o.rho * ux * uy2 - ux * uy2 * p) -
-                 ux * (R(1.5) * h3 - R(0.5) * h4) - R(2) * uy * h5;
-    const R ux2uy2 = ux2 * uy2;
-    // c^6 rho + psi (c^2 + ux^2)(c^2 + uy^2) written without its O(rho) cancellation
-    const R eq22 = p * (third + ux2) * (third + uy2) - rc2 * (third * (ux2 + uy2) + ux2 * uy2);
-    const R h8 = R(0.25) * (eq22 - e22 +
-                            R(2) * (uy * e21 + ux * e12) - (uy2 * e20 + ux2 * e02) -
-                            R(4) * uxy * e11 + R(4.0 / 3.0) * o.rho * ux2uy2 - ux2uy2 * p) -
-                 R(2) * h3 - R(0.5) * uy2 * (R(3) * h3 + h4) - R(0.5) * ux2 * (R(3) * h3 - h4) -
-                 R(4) * uxy * h5 - R(2) * uy * h6 - R(2) * ux * h7;
-    const R c0 = Gam * R(1.0 / 9.0);
-    const R c1 = o.Ftx * R(1.0 / 18.0);
-    const R c2 = o.Fty * R(1.0 / 18.0);
-    const R c3 = h3 + R(1.0 / 72.0) * (R(3) * (s20 + s02) - R(4) * Gam);
-    const R c4 = h4 + R(0.25) * hw * (s20 - s02);
-    const R c5 = h5 + R(0.25) * hw * s11;
-    const R c6 = h6 + o.Fty * R(1.0 / 36.0);
-    const R c7 = h7 + o.Ftx * R(1.0 / 36.0);
-    const R c8 = h8 + R(1.0 / 72.0) * (R(4) * Gam - R(6) * (s20 + s02));
-    add_Kc(g, c0, c1, c2, c3, c4, c5, c6, c7, c8);
+    const R om1 = R(1) - o.omv;
+    const R nn = om1 * (((g[1] + g[3]) - (g[2] + g[4])) - rc2 * (ux2 - uy2));
+    const R xx = om1 * (((g[5] - g[6]) + (g[7] - g[8])) - rc2 * uxy);
+    const R m00 = o.p + R(0.5) * Gam - (SH ? sh : R(0));
+    const R m10 = o.jx + third * o.Ftx, m01 = o.jy + third * o.Fty;
+    const R T = R(2.0 / 3.0) * o.p + rc2 * (ux2 + uy2) + R(4.0 / 3.0) * Gam +
+                third * (o.Ftx * ux + o.Fty * uy) - (SH ? R(2.0 / 3.0) * sh : R(0));
+    const R D = rc2 * (ux2 - uy2) + nn + hw * R(2.0 / 3.0) * (Sx * ux - Sy * uy);
+    const R m11 = rc2 * uxy + xx + hw * third * (Sx * uy + Sy * ux);
+    const R m21 = rc2 * uy * (third + ux2) + ninth * o.Fty + R(0.5) * uy * nn + R(2) * ux * xx;
+    const R m12 = rc2 * ux * (third + uy2) + ninth * o.Ftx - R(0.5) * ux * nn + R(2) * uy * xx;
+    const R m22 = ninth * o.p + o.rho * (ninth * (ux2 + uy2) + third * ux2 * uy2) +
+                  R(2.0 / 9.0) * Gam - R(0.5) * (ux2 - uy2) * nn + R(4) * uxy * xx -
+                  (SH ? ninth * sh : R(0));
+    // inverse of the moment map (m20 = (T + D)/2, m02 = (T - D)/2)
+    const R a = R(0.5) * (T + D) - m22, b = m10 - m12;
+    const R c = R(0.5) * (T - D) - m22, d = m01 - m21;
+    const R u1 = m22 + m11, u2 = m22 - m11, v1 = m21 + m12, v2 = m21 - m12;
+    g[0] = m00 - T + m22;
+    g[1] = R(0.5) * (a + b);
+    g[3] = R(0.5) * (a - b);
+    g[2] = R(0.5) * (c + d);
+    g[4] = R(0.5) * (c - d);
+    g[5] = R(0.25) * (u1 + v1);
+    g[7] = R(0.25) * (u1 - v1);
+    g[6] = R(0.25) * (u2 + v2);
+    g[8] = R(0.25) * (u2 - v2);
 }
 
 // Conservative Allen-Cahn cascaded collision (Sec. 5) with omega_1 = omega_2 =
 // omphi and the other rates 1; the first-order equilibria carry M theta n.
+//
+// With every rate above first order equal to 1 the cascade leaves all central
+// moments (about u) of order two and higher at their equilibria, phi/3 for the
+// two second-order, phi/9 for the fourth-order and zero for the others, and
+// relaxes only the two first-order central moments: a = k10' - ux phi with
+// k10' = k10 + omphi (phi ux + M theta n_x - k10), and b likewise.  A D2Q9
+// distribution with central moments kappa_ij is sum_ij kappa_ij B_i(e_x) B_j(e_y),
+// where B_0, B_1, B_2 are the three-velocity weights of central moments (1,0,0),
+// (0,1,0), (0,0,1) about u; here that sum collapses to
+//   f~ = phi W(e_x) W(e_y) + a D(e_x) V(e_y) + b V(e_x) D(e_y)
+// with W = B_0 + B_2/3 (mean u, central second moment 1/3), D = B_1 and V = B_0.
+// This equals the cascade step for step up to rounding (about 90 operations
+// instead of 160).  The rest direction is taken from the balance of phi,
+// f~_0 = sum f - sum_{a>0} f~_a: the weights hold the inexact constants 1/6 and
+// 2/3, and summing them would bias sum f~ by the same rounding at every node and
+// step (a drift of sum phi growing linearly in time).  Shifted storage stores
+// f~ - w sh; the first moments of the shift vanish, so k10 and k01 are taken from
+// the stored values directly, and sum f is the sum of the stored values.
+template <class R>
+struct Axis3 {  // values at e = -1, 0, +1
+    R m, z, p;
+};
+template <class R>
+__device__ __forceinline__ void ace_axis(R u, Axis3<R>& W, Axis3<R>& D, Axis3<R>& V) {
+    const R u2 = u * u;
+    const R hw = R(0.5) * u2 + R(1.0 / 6.0), hv = R(0.5) * u2, hu = R(0.5) * u;
+    W.m = hw - hu; W.z = R(2.0 / 3.0) - u2; W.p = hw + hu;
+    D.m = u - R(0.5); D.z = R(-2) * u; D.p = u + R(0.5);
+    V.m = hv - hu; V.z = R(1) - u2; V.p = hv + hu;
+}
 template <class R, bool SH = false>
 __device__ __forceinline__ void ace_collide(R f[9], R phi, R ux, R uy, R Mth_x, R Mth_y,
                                             R omphi, R sh = R(0)) {
-    const R ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy;
+    const R tot = SH ? sum9(f) : phi;  // sum of the stored values
     const R k10 = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
     const R k01 = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
-    const R d = (f[5] + f[6]) + (f[7] + f[8]);
-    R k20 = (f[1] + f[3]) + d;
-    R k02 = (f[2] + f[4]) + d;
-    const R k11 = (f[5] - f[6]) + (f[7] - f[8]);
-    const R k21 = (f[5] + f[6]) - (f[7] + f[8]);
-    const R k12 = (f[5] - f[6]) + (f[8] - f[7]);
-    R k22 = d;
-    if constexpr (SH) {  // phi already includes the shift
-        k20 += sh * R(1.0 / 3.0);
-        k02 += sh * R(1.0 / 3.0);
-        k22 += sh * R(1.0 / 9.0);
-    }
-    const R w6 = omphi * R(1.0 / 6.0);
-    const R G1 = w6 * (phi * ux + Mth_x - k10);
-    const R G2 = w6 * (phi * uy + Mth_y - k01);
-    const R G3 = R(1.0 / 12.0) * (R(2.0 / 3.0) * phi - (ux2 + uy2) * phi - (k20 + k02) +
-                                  R(2) * (ux * k10 + uy * k01)) +
-                 ux * G1 + uy * G2;
-    const R G4 = R(0.25) * (-(ux2 - uy2) * phi - (k20 - k02) + R(2) * (ux * k10 - uy * k01)) +
-                 R(3) * (ux * G1 - uy * G2);
-    const R G5 = R(0.25) * (-uxy * phi - k11 + (ux * k01 + uy * k10)) + R(1.5) * (ux * G2 + uy * G1);
-    const R G6 = R(0.25) * (-ux2 * uy * phi + k21 - uy * k20 - R(2) * ux * k11 +
-                            R(2) * uxy * k10 + ux2 * k01) +
-                 R(3) * uxy * G1 + (R(1.5) * ux2 + R(1)) * G2 - R(1.5) * uy * G3 -
-                 R(0.5) * uy * G4 - R(2) * ux * G5;
-    const R G7 = R(0.25) * (-ux * uy2 * phi + k12 - ux * k02 - R(2) * uy * k11 +
-                            R(2) * uxy * k01 + uy2 * k10) +
-                 (R(1.5) * uy2 + R(1)) * G1 + R(3) * uxy * G2 - R(1.5) * ux * G3 +
-                 R(0.5) * ux * G4 - R(2) * uy * G5;
-    const R G8 = R(0.25) * (phi * R(1.0 / 9.0) - k22 + R(2) * (ux * k12 + uy * k21) -
-                            (uy2 * k20 + ux2 * k02) - R(4) * uxy * k11 +
-                            R(2) * (ux * uy2 * k10 + ux2 * uy * k01) - ux2 * uy2 * phi) +
-                 (R(2) * ux + R(3) * ux * uy2) * G1 + (R(2) * uy + R(3) * ux2 * uy) * G2 -
-                 (R(2) + R(1.5) * (ux2 + uy2)) * G3 + R(0.5) * (ux2 - uy2) * G4 -
-                 R(4) * uxy * G5 - R(2) * uy * G6 - R(2) * ux * G7;
-    add_Kc(f, R(0), G1, G2, G3, G4, G5, G6, G7, G8);
+    const R a = k10 + omphi * (phi * ux + Mth_x - k10) - ux * phi;
+    const R b = k01 + omphi * (phi * uy + Mth_y - k01) - uy * phi;
+    Axis3<R> Wx, Dx, Vx, Wy, Dy, Vy;
+    ace_axis(ux, Wx, Dx, Vx);
+    ace_axis(uy, Wy, Dy, Vy);
+    const Axis3<R> P{phi * Wx.m, phi * Wx.z, phi * Wx.p};
+    const Axis3<R> A{a * Dx.m, a * Dx.z, a * Dx.p};
+    const Axis3<R> B{b * Dy.m, b * Dy.z, b * Dy.p};
+    // direction (i, j) -> P_i W_j + A_i V_j + Vx_i B_j, less w sh when shifted
+    const R s1 = SH ? sh * R(1.0 / 9.0) : R(0), s5 = SH ? sh * R(1.0 / 36.0) : R(0);
+    f[1] = P.p * Wy.z - s1 + A.p * Vy.z + Vx.p * B.z;
+    f[2] = P.z * Wy.p - s1 + A.z * Vy.p + Vx.z * B.p;
+    f[3] = P.m * Wy.z - s1 + A.m * Vy.z + Vx.m * B.z;
+    f[4] = P.z * Wy.m - s1 + A.z * Vy.m + Vx.z * B.m;
+    f[5] = P.p * Wy.p - s5 + A.p * Vy.p + Vx.p * B.p;
+    f[6] = P.m * Wy.p - s5 + A.m * Vy.p + Vx.m * B.p;
+    f[7] = P.m * Wy.m - s5 + A.m * Vy.m + Vx.m * B.m;
+    f[8] = P.p * Wy.m - s5 + A.p * Vy.m + Vx.p * B.m;
+    f[0] = tot - (((f[1] + f[2]) + (f[3] + f[4])) + ((f[5] + f[6]) + (f[7] + f[8])));
 }
 
 // --------------------------------------------------- SRT collisions (Sec. 7)
@@ -503,6 +501,7 @@ __device__ __forceinline__ void hydro_srt(R g[9], const NodeOut<R>& o, R sh = R(
 template <class R, bool SH = false>
 __device__ __forceinline__ void ace_srt(R f[9], R phi, R ux, R uy, R Mth_x, R Mth_y, R om,
                                         R sh = R(0)) {
+    const R tot = SH ? sum9(f) : phi;  // sum of the stored values
     const R base = phi * (R(1) - R(1.5) * (ux * ux + uy * uy));
     auto upd = [&](int a, R w, int ex, int ey) {
         const R eu = R(ex) * ux + R(ey) * uy;
@@ -511,10 +510,11 @@ __device__ __forceinline__ void ace_srt(R f[9], R phi, R ux, R uy, R Mth_x, R Mt
         const R fa = SH ? f[a] + w * sh : f[a];  // unshifted value
         f[a] += om * (feq - fa);
     };
-    const R w0 = R(4.0 / 9.0), w1 = R(1.0 / 9.0), w5 = R(1.0 / 36.0);
-    upd(0, w0, 0, 0);
+    const R w1 = R(1.0 / 9.0), w5 = R(1.0 / 36.0);
     upd(1, w1, 1, 0); upd(2, w1, 0, 1); upd(3, w1, -1, 0); upd(4, w1, 0, -1);
     upd(5, w5, 1, 1); upd(6, w5, -1, 1); upd(7, w5, -1, -1); upd(8, w5, 1, -1);
+    // rest direction from the balance of phi (the rounded weights would bias sum f)
+    f[0] = tot - (((f[1] + f[2]) + (f[3] + f[4])) + ((f[5] + f[6]) + (f[7] + f[8])));
 }
 
 // ------------------------------------------------------------- fused kernel
@@ -524,8 +524,17 @@ __device__ __forceinline__ void ace_srt(R f[9], R phi, R ux, R uy, R Mth_x, R Mt
 // has stored its post-collision f (and later gbar), the freed registers receive
 // the next row's pulled values, so those loads are in flight while the rest of
 // the collision computes (no extra registers).
+//
+// Register budget: the kernels are built for ST::waves resident waves per SIMD,
+// except the FP64 cascaded kernel without prefetching, whose 166 VGPRs allow three
+// (the prefetching and SRT FP64 kernels would spill at three).
+template <class ST, int PF, int COLL>
+constexpr int fused_waves() {
+    return (ST::waves == 2 && PF == PF_HOLD && COLL == COLL_CASCADED) ? 3 : ST::waves;
+}
+
 template <class ST, int TX, int MODE, int PF, int COLL = COLL_CASCADED>
-__global__ void __launch_bounds__(TX) __attribute__((amdgpu_waves_per_eu(ST::waves)))
+__global__ void __launch_bounds__(TX) __attribute__((amdgpu_waves_per_eu(fused_waves<ST, PF, COLL>())))
 lb_fused(const LatDesc* __restrict__ descs, const WorkItem* __restrict__ items, int n_items, int parity) {
     using R = typename ST::R;
     using T = typename ST::T;
