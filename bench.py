@@ -130,9 +130,10 @@ def bench_batched(precision: str, steps: int, n: int = 256, seed: int = 20190909
     wall = time.perf_counter() - t0
     ms, _ = lb.lb_batch_timing_read(B.b)
     unstable = sum(1 for s in range(n) if B.diagnostics(s)["nan_flag"] != 0.0)
+    sched = list(lb.lb_batch_get_schedule(B.b))
     B.close()
     return {"MLUPS": round(nodes * steps / wall / 1e6, 1), "nodes": nodes, "instances": n,
-            "steps": steps, "kernel_ms": round(ms, 4),
+            "steps": steps, "kernel_ms": round(ms, 4), "schedule": sched,
             "kernel_GBs": round(36 * STORE[precision] * nodes / (ms * 1e-3) / 1e9, 1),
             "unstable_instances": unstable}
 

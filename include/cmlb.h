@@ -257,6 +257,10 @@ lb_status lb_batch_timing_read(lb_batch* b, double* ms_per_step, int64_t* steps)
  * the next rows during the collision is used (1) or not (0). */
 lb_status lb_get_schedule(lb_handle* h, int32_t* tile_x, int32_t* rows, int32_t* grid,
                           int32_t* prefetch);
+/* The same for a batch: the schedule of its persistent step (rows is the segment
+ * length; 0 until the batch has stepped with at least one occupied slot). */
+lb_status lb_batch_get_schedule(lb_batch* b, int32_t* tile_x, int32_t* rows, int32_t* grid,
+                                int32_t* prefetch);
 
 /* sizeof(lb_config) and sizeof(lb_diag) as compiled, for binding checks. */
 lb_status lb_struct_sizes(uint64_t* config_bytes, uint64_t* diag_bytes);

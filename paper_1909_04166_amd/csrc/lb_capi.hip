@@ -1266,4 +1266,14 @@ lb_status lb_batch_timing_read(lb_batch* b, double* ms_per_step, int64_t* steps)
     return LB_OK;
 }
 
+lb_status lb_batch_get_schedule(lb_batch* b, int32_t* tile_x, int32_t* rows, int32_t* grid,
+                                int32_t* prefetch) {
+    if (!b || !tile_x || !rows || !grid || !prefetch) return LB_E_INVALID_ARG;
+    *tile_x = b->sc.tx;
+    *rows = b->sc.rows;
+    *grid = b->sc.mode == 1 ? b->sc.grid : 0;
+    *prefetch = b->sc.pf;
+    return LB_OK;
+}
+
 }  // extern "C"

@@ -106,6 +106,7 @@ _SIGS = {
     "lb_batch_timing_enable": ([_vp, ctypes.c_int32], ctypes.c_int32),
     "lb_batch_timing_read": ([_vp, _dp, _i64p], ctypes.c_int32),
     "lb_get_schedule": ([_vp, _i32p, _i32p, _i32p, _i32p], ctypes.c_int32),
+    "lb_batch_get_schedule": ([_vp, _i32p, _i32p, _i32p, _i32p], ctypes.c_int32),
     "lb_struct_sizes": ([_u64p, _u64p], ctypes.c_int32),
     "lb_copy_kernel": ([_vp, _vp, ctypes.c_uint64, _vp], ctypes.c_int32),
 }
@@ -280,6 +281,14 @@ def lb_get_schedule(h: int) -> tuple[int, int, int, int]:
     _check("lb_get_schedule", lib().lb_get_schedule(_vp(h), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
                                                     ctypes.byref(d)))
     return int(a.value), int(b.value), int(c.value), int(d.value)
+
+
+def lb_batch_get_schedule(b: int) -> tuple[int, int, int, int]:
+    """(workgroup width, rows per segment, persistent grid or 0, prefetch) of a batch."""
+    a, r, g, p = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check("lb_batch_get_schedule", lib().lb_batch_get_schedule(_vp(b), ctypes.byref(a), ctypes.byref(r),
+                                                                ctypes.byref(g), ctypes.byref(p)))
+    return int(a.value), int(r.value), int(g.value), int(p.value)
 
 
 def lb_copy_kernel(dst: int, src: int, n: int, stream: int) -> None:
@@ -474,6 +483,11 @@ class Batch:
         slot = lb_batch_add(self.b, cfg, np.asarray(phi0, dtype=np.float64).reshape(shape))
         self.shapes[slot] = shape
         return slot
+
+    @property
+    def tile(self):
+        """Schedule of the persistent step (see lb_batch_get_schedule)."""
+        return lb_batch_get_schedule(self.b)
 
     def remove(self, slot: int) -> None:
         lb_batch_remove(self.b, slot)
