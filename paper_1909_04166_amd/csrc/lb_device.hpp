@@ -1,9 +1,9 @@
 // lb_device.hpp -- device side of the fused stream-collide step for the coupled
 // D2Q9 cascaded central-moment schemes (arXiv:1909.04166, Secs. 2-5), gfx950.
 //
-// Data layout (HBM): one lattice = two buffers (ping-pong) of 18 planes,
-// planes 0..8 hold f_a, planes 9..17 hold gbar_a, each plane [y][x] with x
-// contiguous and a plane stride rounded up to 64 elements.  A buffer holds the
+// Data layout (HBM): one lattice = two buffers (ping-pong) of the 18 stored
+// values per node, f_0..f_8 then gbar_0..gbar_8, row-interleaved: value q of
+// node (x, y) at element (18 y + q) nx + x (see row_stride).  A buffer holds the
 // POST-COLLISION values of the previous step; the kernel pulls them
 // (f_a(x) = f~_a(x - e_a)), so streaming costs nothing extra.
 //
@@ -15,7 +15,7 @@
 //   B  lanes 1..w+2: pull gbar at row L-1             -> pbar(L-1) (LDS ring)
 //   D  lanes 1..w+2: grad phi, n (or mu_phi) at row L-1           (LDS ring)
 //   F  lanes 2..w+1: collide row L-2: div n (or grad mu), forces, u, p, both
-//      cascaded collisions, store the 18 post-collision values
+//      collisions (the cascades in closed form), store the 18 post-collision values
 // The pulled f and gbar of a lane stay in registers until their row is
 // collided, so each stored value is read from HBM once per step (halo columns
 // and the rows shared by neighbouring work items come from L2 / MALL).
