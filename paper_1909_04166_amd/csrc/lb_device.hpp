@@ -23,6 +23,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace cmlb {
 
 // ------------------------------------------------------------------ storage
@@ -130,11 +132,15 @@ __device__ __forceinline__ int map_row(int L, int ny, int wall) {
 // registers and a 32-bit per-lane offset, and keeps them off the LDS wait counter.
 template <class T>
 using gmem_t = __attribute__((address_space(1))) T;
-template <class ST>
-__device__ __forceinline__ typename ST::R ldo(const typename ST::T* plane, uint32_t e) {
+// RAW: return the stored value as it is; the caller converts it later, so that a
+// prefetch does not wait for its own load.
+template <class ST, bool RAW = false>
+__device__ __forceinline__ std::conditional_t<RAW, typename ST::T, typename ST::R> ldo(
+    const typename ST::T* plane, uint32_t e) {
     using T = typename ST::T;
     const gmem_t<const char>* p = (const gmem_t<const char>*)plane;
-    return ST::ld(*(const gmem_t<const T>*)(p + e * (uint32_t)sizeof(T)));
+    const T v = *(const gmem_t<const T>*)(p + e * (uint32_t)sizeof(T));
+    if constexpr (RAW) return v; else return ST::ld(v);
 }
 template <class ST>
 __device__ __forceinline__ void sto(typename ST::T* plane, uint32_t e, typename ST::R v) {
@@ -155,10 +161,10 @@ __device__ __forceinline__ int64_t row_stride(int nx) { return 18 * (int64_t)nx;
 // (bounce-back), or by the y-mirrored direction at the node the particle left,
 // x - e_ax (specular reflection).  base points at value 0 of row 0 of the group
 // (f or gbar); xm, xp are the periodic neighbours of x.
-template <class ST>
+template <class ST, bool RAW = false>
 __device__ __forceinline__ void pull9(const typename ST::T* __restrict__ base, int nx, int ny,
                                       int wall, int wallx, int x, int xm, int xp, int r,
-                                      typename ST::R out[9]) {
+                                      std::conditional_t<RAW, typename ST::T, typename ST::R> out[9]) {
     using T = typename ST::T;
     const bool bot = wall && r == 0;       // sources of 2, 5, 6 lie below the wall
     const bool top = wall && r == ny - 1;  // sources of 4, 7, 8 lie above the wall
@@ -177,15 +183,15 @@ __device__ __forceinline__ void pull9(const typename ST::T* __restrict__ base, i
     const int p4 = top ? 2 : 4, p7 = top ? (slip ? 6 : 5) : 7, p8 = top ? (slip ? 5 : 6) : 8;
     const int x5 = (bot && !slip) ? x : xm, x6 = (bot && !slip) ? x : xp;
     const int x7 = (top && !slip) ? x : xp, x8 = (top && !slip) ? x : xm;
-    out[0] = ldo<ST>(ro, x);
-    out[1] = ldo<ST>(ro + nx, xm);
-    out[3] = ldo<ST>(ro + 3 * nx, xp);
-    out[2] = ldo<ST>(sb + p2 * nx, x);
-    out[5] = ldo<ST>(sb + p5 * nx, x5);
-    out[6] = ldo<ST>(sb + p6 * nx, x6);
-    out[4] = ldo<ST>(st + p4 * nx, x);
-    out[7] = ldo<ST>(st + p7 * nx, x7);
-    out[8] = ldo<ST>(st + p8 * nx, x8);
+    out[0] = ldo<ST, RAW>(ro, x);
+    out[1] = ldo<ST, RAW>(ro + nx, xm);
+    out[3] = ldo<ST, RAW>(ro + 3 * nx, xp);
+    out[2] = ldo<ST, RAW>(sb + p2 * nx, x);
+    out[5] = ldo<ST, RAW>(sb + p5 * nx, x5);
+    out[6] = ldo<ST, RAW>(sb + p6 * nx, x6);
+    out[4] = ldo<ST, RAW>(st + p4 * nx, x);
+    out[7] = ldo<ST, RAW>(st + p7 * nx, x7);
+    out[8] = ldo<ST, RAW>(st + p8 * nx, x8);
     if (wallx) {
         // Lanes on the first or last column replace what arrived from beyond an x
         // wall: bounce-back (opposite direction, same node), or specular reflection
@@ -193,14 +199,14 @@ __device__ __forceinline__ void pull9(const typename ST::T* __restrict__ base, i
         // beyond an x and a y wall at once, bounce-back.
         const bool sx = wallx == WALL_SLIP;
         if (x == 0) {
-            out[1] = ldo<ST>(ro + 3 * nx, x);
-            out[5] = (sx && !bot) ? ldo<ST>(rbp + 6 * nx, x) : ldo<ST>(ro + 7 * nx, x);
-            out[8] = (sx && !top) ? ldo<ST>(rtp + 7 * nx, x) : ldo<ST>(ro + 6 * nx, x);
+            out[1] = ldo<ST, RAW>(ro + 3 * nx, x);
+            out[5] = (sx && !bot) ? ldo<ST, RAW>(rbp + 6 * nx, x) : ldo<ST, RAW>(ro + 7 * nx, x);
+            out[8] = (sx && !top) ? ldo<ST, RAW>(rtp + 7 * nx, x) : ldo<ST, RAW>(ro + 6 * nx, x);
         }
         if (x == nx - 1) {
-            out[3] = ldo<ST>(ro + 1 * nx, x);
-            out[6] = (sx && !bot) ? ldo<ST>(rbp + 5 * nx, x) : ldo<ST>(ro + 8 * nx, x);
-            out[7] = (sx && !top) ? ldo<ST>(rtp + 8 * nx, x) : ldo<ST>(ro + 5 * nx, x);
+            out[3] = ldo<ST, RAW>(ro + 1 * nx, x);
+            out[6] = (sx && !bot) ? ldo<ST, RAW>(rbp + 5 * nx, x) : ldo<ST, RAW>(ro + 8 * nx, x);
+            out[7] = (sx && !top) ? ldo<ST, RAW>(rtp + 8 * nx, x) : ldo<ST, RAW>(ro + 5 * nx, x);
         }
     }
 }
@@ -520,17 +526,21 @@ __device__ __forceinline__ void ace_srt(R f[9], R phi, R ux, R uy, R Mth_x, R Mt
 // ------------------------------------------------------------- fused kernel
 
 // The values pulled for phi (two rows ahead of the collision) and for pbar (one
-// row ahead) stay in registers until their row collides.  PF_PREFETCH: once a lane
-// has stored its post-collision f (and later gbar), the freed registers receive
-// the next row's pulled values, so those loads are in flight while the rest of
-// the collision computes (no extra registers).
+// row ahead) stay in registers until their row collides.  PF_PREFETCH: each row
+// iteration starts by issuing the pulls of the next one (f at the next leading
+// row, gbar at the next pbar row) into registers of the stored type; they are
+// converted when the iteration ends, so those loads are in flight through the
+// barriers, the stencils and both collisions (18 values more per lane).
 //
 // Register budget: the kernels are built for ST::waves resident waves per SIMD,
 // except the FP64 cascaded kernel without prefetching, whose 166 VGPRs allow three
-// (the prefetching and SRT FP64 kernels would spill at three).
+// (the prefetching and SRT FP64 kernels would spill at three), and the prefetching
+// 16-bit kernels, which would spill at four and are built for three.
 template <class ST, int PF, int COLL>
 constexpr int fused_waves() {
-    return (ST::waves == 2 && PF == PF_HOLD && COLL == COLL_CASCADED) ? 3 : ST::waves;
+    if (ST::waves == 2) return (PF == PF_HOLD && COLL == COLL_CASCADED) ? 3 : 2;
+    if (ST::shifted && PF == PF_PREFETCH) return 3;
+    return ST::waves;
 }
 
 template <class ST, int TX, int MODE, int PF, int COLL = COLL_CASCADED>
@@ -566,18 +576,26 @@ lb_fused(const LatDesc* __restrict__ descs, const WorkItem* __restrict__ items, 
         const int xp = xc == nx - 1 ? 0 : xc + 1;
 
         R f0[9], f1[9], f2[9], g0[9], g1[9];
+        T nf[9], ng[9];  // next rows' pulls in flight (PF_PREFETCH)
         R cdx = 0, cdy = 0, cm2 = 0, cnx = 0, cny = 0;  // grad / normal at row L-1
         R pdx = 0, pdy = 0, pm2 = 0, pnx = 0, pny = 0;  // the same one row below
 #pragma unroll
-        for (int a = 0; a < 9; ++a) { f0[a] = f1[a] = f2[a] = g0[a] = g1[a] = R(0); }
+        for (int a = 0; a < 9; ++a) {
+            f0[a] = f1[a] = f2[a] = g0[a] = g1[a] = R(0);
+            nf[a] = ng[a] = T(0);
+        }
 
         const int H = it.y1 - it.y0;
         for (int k = 0; k < H + 4; ++k) {
             const int L = it.y0 - 2 + k;
-            const bool have = PF == PF_PREFETCH && k >= 5;  // rows already pulled during the last collision
+            constexpr bool ahead = PF == PF_PREFETCH && MODE == MODE_STEP;
+            if (ahead && k + 1 < H + 4) {  // the next iteration's pulls
+                if (inA) pull9<ST, true>(src, nx, ny, wall, wallx, xc, xm, xp, map_row(L + 1, ny, wall), nf);
+                if (k >= 2 && inB) pull9<ST, true>(srcg, nx, ny, wall, wallx, xc, xm, xp, map_row(L, ny, wall), ng);
+            }
             // ---- A: phi at the leading row
             if (inA) {
-                if (!have) pull9<ST>(src, nx, ny, wall, wallx, xc, xm, xp, map_row(L, ny, wall), f0);
+                if (!ahead || k == 0) pull9<ST>(src, nx, ny, wall, wallx, xc, xm, xp, map_row(L, ny, wall), f0);
                 R ph = sum9(f0);
                 if constexpr (ST::shifted) ph += K.shf;
                 s_phi[L & 3][t] = ph;
@@ -585,7 +603,7 @@ lb_fused(const LatDesc* __restrict__ descs, const WorkItem* __restrict__ items, 
             // ---- B: pbar one row behind
             if (k >= 2 && inB) {
                 const int Lg = L - 1;
-                if (!have) pull9<ST>(srcg, nx, ny, wall, wallx, xc, xm, xp, map_row(Lg, ny, wall), g0);
+                if (!ahead || k == 2) pull9<ST>(srcg, nx, ny, wall, wallx, xc, xm, xp, map_row(Lg, ny, wall), g0);
                 R pb = sum9(g0);
                 if constexpr (ST::shifted) pb += K.shg;
                 s_pb[Lg & 3][t] = pb;
@@ -619,7 +637,6 @@ lb_fused(const LatDesc* __restrict__ descs, const WorkItem* __restrict__ items, 
             // ---- F: collide row C = L - 2
             if (k >= 4) {
                 const int C = L - 2;
-                const bool pre = PF == PF_PREFETCH && MODE == MODE_STEP && k + 1 < H + 4;
                 NodeIn<R> in;
                 NodeOut<R> o;
                 uint32_t idx = 0;
@@ -653,8 +670,6 @@ lb_fused(const LatDesc* __restrict__ descs, const WorkItem* __restrict__ items, 
 #pragma unroll
                         for (int a = 0; a < 9; ++a) sto<ST>(drow + a * nx, (uint32_t)xc, f2[a]);
                     }
-                    if (pre && inA)  // next leading row into the freed f registers
-                        pull9<ST>(src, nx, ny, wall, wallx, xc, xm, xp, map_row(L + 1, ny, wall), f2);
                     if (inF) {
                         if constexpr (COLL == COLL_SRT)
                             hydro_srt<R, ST::shifted>(g1, o, K.shg);
@@ -664,8 +679,6 @@ lb_fused(const LatDesc* __restrict__ descs, const WorkItem* __restrict__ items, 
 #pragma unroll
                         for (int a = 0; a < 9; ++a) sto<ST>(drow + a * nx, (uint32_t)xc, g1[a]);
                     }
-                    if (pre && inB)  // next pbar row into the freed gbar registers
-                        pull9<ST>(srcg, nx, ny, wall, wallx, xc, xm, xp, map_row(L, ny, wall), g1);
                 } else if constexpr (MODE == MODE_FIELDS) {
                     if (inF) {
                         double* F = D.fields;
@@ -692,20 +705,15 @@ lb_fused(const LatDesc* __restrict__ descs, const WorkItem* __restrict__ items, 
                 }
             }
             // ---- rotate the register pipeline
-            if (PF == PF_PREFETCH && MODE == MODE_STEP && k >= 4) {
 #pragma unroll
-                for (int a = 0; a < 9; ++a) {
-                    const R nf = f2[a];  // prefetched leading row
-                    f2[a] = f1[a];
-                    f1[a] = f0[a];
-                    f0[a] = nf;
-                    const R ng = g1[a];  // prefetched pbar row
-                    g1[a] = g0[a];
-                    g0[a] = ng;
+            for (int a = 0; a < 9; ++a) {
+                f2[a] = f1[a];
+                f1[a] = f0[a];
+                g1[a] = g0[a];
+                if constexpr (ahead) {
+                    f0[a] = ST::ld(nf[a]);
+                    g0[a] = ST::ld(ng[a]);
                 }
-            } else {
-#pragma unroll
-                for (int a = 0; a < 9; ++a) { f2[a] = f1[a]; f1[a] = f0[a]; g1[a] = g0[a]; }
             }
             pdx = cdx; pdy = cdy; pm2 = cm2; pnx = cnx; pny = cny;
         }
