@@ -74,8 +74,11 @@ lb_status validate(const lb_config* c) {
                          1.0 / (0.5 + 3.0 * c->M)};
     for (double o : om)
         if (!(o > 0.0 && o < 2.0)) return LB_E_INVALID_ARG;
-    if (c->tile_x != 0 && c->tile_x != 64 && c->tile_x != 128 && c->tile_x != 256 && c->tile_x != 512)
+    if (c->tile_x != 0 && c->tile_x != 64 && c->tile_x != 128 && c->tile_x != 256 && c->tile_x != 512 &&
+        c->tile_x != 1024)
         return LB_E_INVALID_ARG;
+    // 1024 lanes = 16 waves per CU: only the FP32-compute kernels without prefetching fit
+    if (c->tile_x == 1024 && (c->precision == LB_FP64 || c->tile_pf != 0)) return LB_E_INVALID_ARG;
     if (c->tile_h < 0 || (c->tile_h > 0 && c->tile_h < kMinH)) return LB_E_INVALID_ARG;
     if (c->diag_every < 0) return LB_E_INVALID_ARG;
     return LB_OK;
@@ -445,11 +448,12 @@ double time_candidate(int prec, int kind, int tx, int pf, const LatDesc* d, cons
 
 // Candidate schedules for one lattice shape (the prefetching variant exists for
 // the coupled cascaded kernel only).
-std::vector<Sched> candidates(int nx, int ny, int kind) {
+std::vector<Sched> candidates(int prec, int nx, int ny, int kind) {
     std::vector<Sched> out;
     for (int pf : {PF_HOLD, PF_PREFETCH})
-        for (int tx : {64, 128, 256, 512}) {
+        for (int tx : {64, 128, 256, 512, 1024}) {
             if (pf != PF_HOLD && kind != KIND_COUPLED_CASCADED) continue;
+            if (tx == 1024 && (prec == LB_FP64 || pf != PF_HOLD)) continue;
             if (tx > 64 && nx <= strip_w(tx / 2)) continue;
             for (int th : {16, 32, 64, 128, 256}) {
                 if (th > ny && th != 16) continue;
@@ -478,7 +482,7 @@ lb_status autotune_single(lb_handle* h) {
     double best = 1e30;
     const int64_t N = (int64_t)h->cfg.nx * h->cfg.ny;
     const int reps = N >= (1 << 22) ? 3 : 10;
-    for (Sched sc : candidates(h->cfg.nx, h->cfg.ny, h->kind)) {
+    for (Sched sc : candidates(h->cfg.precision, h->cfg.nx, h->cfg.ny, h->kind)) {
         std::vector<WorkItem> items;
         if (!build_schedule({{0, h->cfg.nx, h->cfg.ny}}, h->cfg.precision, h->kind, sc, h->max_items, items))
             continue;
@@ -975,7 +979,7 @@ lb_status batch_autotune(lb_batch* b) {
     const int med_nx = widths[widths.size() / 2];
     Sched best_sc = b->sc;
     double best = 1e30;
-    for (Sched sc : candidates(med_nx, max_ny, b->kind)) {
+    for (Sched sc : candidates(b->prec, med_nx, max_ny, b->kind)) {
         std::vector<WorkItem> items;
         if (!build_schedule(lats, b->prec, b->kind, sc, b->max_items, items)) continue;
         HIPC(hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(WorkItem),
@@ -1043,7 +1047,9 @@ lb_status lb_batch_create(int32_t slots, int64_t node_capacity, int32_t precisio
                           lb_batch** out) {
     if (!out || !dev_ws || slots <= 0 || node_capacity < 64 || store_bytes(precision) == 0)
         return LB_E_INVALID_ARG;
-    if (tile_x != 0 && tile_x != 64 && tile_x != 128 && tile_x != 256 && tile_x != 512) return LB_E_INVALID_ARG;
+    if (tile_x != 0 && tile_x != 64 && tile_x != 128 && tile_x != 256 && tile_x != 512 && tile_x != 1024)
+        return LB_E_INVALID_ARG;
+    if (tile_x == 1024 && precision == LB_FP64) return LB_E_INVALID_ARG;
     if (tile_h < 0 || (tile_h > 0 && tile_h < kMinH)) return LB_E_INVALID_ARG;
     *out = nullptr;
     const BatchLayout L = batch_layout(slots, node_capacity, precision);

@@ -31,6 +31,12 @@ static hipError_t launch_tx(int tx, const LatDesc* d, const WorkItem* items, int
     case 128: launch_one<ST, 128, MODE, PF, KIND>(dim3(grid), d, items, n_items, parity, s); break;
     case 256: launch_one<ST, 256, MODE, PF, KIND>(dim3(grid), d, items, n_items, parity, s); break;
     case 512: launch_one<ST, 512, MODE, PF, KIND>(dim3(grid), d, items, n_items, parity, s); break;
+    case 1024:  // 16 waves: FP32 compute without prefetching only (4 waves per SIMD)
+        if constexpr (sizeof(typename ST::R) == 4 && PF == PF_HOLD && MODE == MODE_STEP)
+            launch_one<ST, 1024, MODE, PF, KIND>(dim3(grid), d, items, n_items, parity, s);
+        else
+            return hipErrorInvalidValue;
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -91,6 +97,17 @@ static int occ_st(int kind, int tx, int pf) {
     case 128: return occ_kind<ST, 128>(kind, pf);
     case 256: return occ_kind<ST, 256>(kind, pf);
     case 512: return occ_kind<ST, 512>(kind, pf);
+    case 1024:
+        if constexpr (sizeof(typename ST::R) == 4) {
+            if (pf != PF_HOLD) return 0;
+            switch (kind) {
+            case KIND_COUPLED_CASCADED: return occ_of(lb_fused<ST, 1024, MODE_STEP, PF_HOLD, COLL_CASCADED>, 1024);
+            case KIND_COUPLED_SRT: return occ_of(lb_fused<ST, 1024, MODE_STEP, PF_HOLD, COLL_SRT>, 1024);
+            case KIND_ACE_CASCADED: return occ_of(lb_ace<ST, 1024, MODE_STEP, COLL_CASCADED>, 1024);
+            case KIND_ACE_SRT: return occ_of(lb_ace<ST, 1024, MODE_STEP, COLL_SRT>, 1024);
+            }
+        }
+        return 0;
     }
     return 1;
 }

@@ -107,6 +107,13 @@ def test_option_validation():
     assert code(tile_pf=1, tile_x=128, tile_h=16) == lb.LB_OK
     assert code(tile_pf=2, tile_x=128, tile_h=16) == lb.LB_E_INVALID_ARG
     assert code(tile_pf=1, tile_x=128, tile_h=16, collision=1) == lb.LB_E_INVALID_ARG
+    assert code(tile_x=1024, tile_h=16) == lb.LB_E_INVALID_ARG  # 16 waves per CU: not in FP64
+    assert code(tile_x=768, tile_h=16) == lb.LB_E_INVALID_ARG
+    c32 = lb.config_from_case(case, "fp32", tile=(1024, 16))
+    assert lb.lb_workspace_bytes(c32) > 0
+    c32.tile_pf = 1  # no prefetching variant at 1024 lanes
+    with pytest.raises(lb.LBError):
+        lb.lb_workspace_bytes(c32)
     assert code(st_form=1) == lb.LB_E_UNSUPPORTED  # Langmuir with the chemical-potential form
     assert code(psi_a=1.0) == lb.LB_E_INVALID_ARG
     assert code(psi_G=1.0 / 200.0) == lb.LB_E_INVALID_ARG  # psi reaches 1 on the last row

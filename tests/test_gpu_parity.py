@@ -278,6 +278,33 @@ def test_row_variants_each_precision(prec, tol, pf):
     assert err <= tol
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
+def test_wide_workgroups_bit_identical(prec):
+    """1024-lane workgroups (FP32-compute precisions only) across a ragged width of
+    three strips, walls in y: bit-identical to 512- and 64-lane tilings (every
+    instantiation rounds the same), and FP32 within the stated 1e-4 of the oracle."""
+    case, phi0 = W.random_case(2100, 40, seed=51, bc_y="wall")
+    case.update(gy=-2e-5, rho_A=10.0)
+    _print_case(f"1024 lanes {prec}", case)
+    runs = []
+    for tile in [(1024, 24), (512, 24), (64, 16)]:
+        g = lb.Lattice(case, phi0, prec, tile=tile)
+        assert g.tile[0] == tile[0]
+        g.step(30)
+        runs.append(g.get_dist())
+        g.close()
+    for f, gb in runs[1:]:
+        assert np.array_equal(f, runs[0][0]) and np.array_equal(gb, runs[0][1])
+    if prec == "fp32":
+        o = oracle.Oracle(case, phi0)
+        o.step(30)
+        g = lb.Lattice(case, phi0, prec, tile=(1024, 24))
+        g.step(30)
+        err = np.abs(g.fields()[0] - o.fields()[0]).max()
+        print(f"   fp32 phi vs oracle {err:.2e}", flush=True)
+        assert err <= 1e-4
+
+
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 2e-5)])
 def test_bench_grid_tiles_equal_and_match_oracle(precision, tol):
     """The benchmark's own workload and launch configuration (the 8192^2 grid of
