@@ -37,11 +37,11 @@ KERNEL_SOURCES = ["paper_1909_04166_amd/csrc/lb_device.hpp", "paper_1909_04166_a
                   "paper_1909_04166_amd/csrc/lb_capi.hip", "paper_1909_04166_amd/csrc/lb_internal.hpp",
                   "paper_1909_04166_amd/build.py"]
 TRAFFIC = {
-    "fingerprint": "28bf602138117896",
+    "fingerprint": "8d9d67d8f5eb6fa4",
     "workload": "tiled8192",
-    "fp64": {"read": 10162257728, "write": 9670373328, "tile_x": 512},
-    "fp32": {"read": 5307404160, "write": 4872935760, "tile_x": 512},
-    "fp16": {"read": 2824310720, "write": 2472623648, "tile_x": 512},
+    "fp64": {"read": 10162257472, "write": 9670357232, "tile_x": 512},
+    "fp32": {"read": 5492667520, "write": 4860965360, "tile_x": 1024},
+    "fp16": {"read": 2824307200, "write": 2472627216, "tile_x": 512},
 }
 
 
