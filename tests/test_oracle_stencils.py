@@ -43,3 +43,18 @@ def test_gradient_rotation_covariance():
         rx, ry = oracle.grad9(qr)
         assert abs(rx + gy) < 1e-14 and abs(ry - gx) < 1e-14
         assert abs(oracle.lap9(q) - oracle.lap9(qr)) < 1e-14
+
+
+def test_divergence_of_normal_is_circle_curvature():
+    """div n on a tanh droplet (phi = 1 inside, so n = grad phi / |grad phi| points
+    inward and div n = -1/r): at every interface node (0.25 < phi < 0.75) of
+    R = 12, 25, 40 drops, div n * r = -1 within 1%."""
+    from paper_1909_04166_amd import workloads as W
+    for R in (12.0, 25.0, 40.0):
+        case, phi0 = W.droplet(128, R, W=4.0)
+        divn = oracle.Oracle(case, phi0).coupling()["divn"]
+        y, x = np.mgrid[0:128, 0:128].astype(float)
+        r = np.hypot(x - 64, y - 64)
+        band = (phi0 > 0.25) & (phi0 < 0.75)
+        assert band.sum() > 100
+        assert np.abs(divn[band] * r[band] + 1).max() <= 0.01
