@@ -127,9 +127,30 @@ class Server:
                     req.phi0 = None  # rebuilt on demand; keeps host memory flat
                 self.finished.append(req)
 
-    def run(self, arrivals: list[Request], max_wall_s: float = 1e9) -> dict:
+    def cancel(self, rid: int) -> bool:
+        """Withdraws a queued or resident request: it finishes with the error
+        "cancelled", and a resident one frees its slot and nodes at once (the
+        other lattices are not touched).  Returns False if rid is not pending."""
+        for r in self.queue:
+            if r.rid == rid:
+                self.queue.remove(r)
+                break
+        else:
+            r = next((q for q in self.active.values() if q.rid == rid), None)
+            if r is None:
+                return False
+            self.batch.remove(r.slot)
+            del self.active[r.slot]
+        r.error = "cancelled"
+        r.done = self.now()
+        self.finished.append(r)
+        return True
+
+    def run(self, arrivals: list[Request], max_wall_s: float = 1e9,
+            on_tick: Callable[["Server"], None] | None = None) -> dict:
         """Replays an arrival trace in real time (request.arrival in seconds from
-        start) until every request is finished."""
+        start) until every request is finished.  on_tick(server) runs after every
+        tick (e.g. to cancel requests)."""
         pending = collections.deque(sorted(arrivals, key=lambda r: r.arrival))
         self.t0 = self.clock()
         total_updates = 0
@@ -154,6 +175,8 @@ class Server:
             total_updates += n * self.used_nodes()
             self.batch.step(n, use_graph=True)
             self._retire()
+            if on_tick is not None:
+                on_tick(self)
             if self.now() > max_wall_s:
                 break
         wall = self.now()
