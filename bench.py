@@ -31,17 +31,18 @@ METRIC = "MLUPS (f+g per node-step) & % HBM roofline; p50/p99 solve latency batc
 # HBM bytes per launch of the step kernel on the 8192^2 grid from two rocprofv3
 # counter passes (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0 KiB, the factors read on the
 # library's copy kernel; see profiles/lb_fused_pmc_tiled8192.md), with the workgroup
-# width the autotuner chose in those runs.  They hold only for the kernel sources
-# with this fingerprint; for any other source the roofline's traffic is null.
+# schedule the autotuner chose in those runs (workgroup width, rows, grid, prefetch).
+# They hold only for that schedule and the kernel code with this fingerprint;
+# otherwise the roofline's traffic is null.
 KERNEL_SOURCES = ["paper_1909_04166_amd/csrc/lb_device.hpp", "paper_1909_04166_amd/csrc/lb_kernels.hip",
                   "paper_1909_04166_amd/csrc/lb_capi.hip", "paper_1909_04166_amd/csrc/lb_internal.hpp",
                   "paper_1909_04166_amd/build.py"]
 TRAFFIC = {
-    "fingerprint": "8d9d67d8f5eb6fa4",
+    "fingerprint": "5d0e5179c043f472",
     "workload": "tiled8192",
-    "fp64": {"read": 10162257472, "write": 9670357232, "tile_x": 512},
-    "fp32": {"read": 5492667520, "write": 4860965360, "tile_x": 1024},
-    "fp16": {"read": 2824307200, "write": 2472627216, "tile_x": 512},
+    "fp64": {"read": 10162261568, "write": 9670417984, "tile": [512, 272, 512, 0]},
+    "fp32": {"read": 5492773376, "write": 4861179296, "tile": [1024, 32, 0, 0]},
+    "fp16": {"read": 2824307584, "write": 2472627216, "tile": [512, 136, 1024, 0]},
 }
 
 
@@ -68,10 +69,11 @@ def kernel_fingerprint() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, precision: str, tile_x: int):
-    """Counter-measured bytes per launch, or None when they do not apply."""
+def measured_traffic(workload: str, precision: str, tile) -> dict | None:
+    """Counter-measured bytes per launch, or None when they do not apply (other
+    workload, other schedule, or other kernel code)."""
     rec = TRAFFIC.get(precision)
-    if (rec is None or workload != TRAFFIC["workload"] or tile_x != rec["tile_x"]
+    if (rec is None or workload != TRAFFIC["workload"] or list(tile) != rec.get("tile")
             or kernel_fingerprint() != TRAFFIC["fingerprint"]):
         return None
     return rec
@@ -419,7 +421,7 @@ def main():
     s = STORE[args.precision]
     bytes_per_launch = 36 * s * N
     achieved = bytes_per_launch / (r["ms_kernel"] * 1e-3) / 1e9 if r["ms_kernel"] > 0 else None
-    traffic = measured_traffic(args.workload, args.precision, int(r["tile"][0]))
+    traffic = measured_traffic(args.workload, args.precision, r["tile"])
     out = {
         "metric": METRIC,
         "value": round(mlups, 1),

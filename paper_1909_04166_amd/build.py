@@ -16,16 +16,20 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcmlb.so")
 SOURCES = ["lb_kernels.hip", "lb_capi.hip"]
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-ffp-contract=on", "-Wno-unused-command-line-argument"]
+# roctx ranges around the stepping calls (marker traces)
+LIBS = ["-L" + os.path.join(ROCM, "lib"), "-Wl,-rpath," + os.path.join(ROCM, "lib"),
+        "-lrocprofiler-sdk-roctx"]
 
 
 def build(verbose: bool = False, extra: list[str] | None = None, out: str | None = None) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     lib = out or LIB
     tmp = lib + ".tmp"
-    cmd = [hipcc] + FLAGS + (extra or []) + ["-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES]
+    cmd = [hipcc] + FLAGS + (extra or []) + ["-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES] + LIBS
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
