@@ -458,6 +458,15 @@ def main():
             extra[prec] = {"MLUPS": round(N * args.steps / rr["wall_s"] / 1e6, 1),
                            "kernel_GBs": round(36 * STORE[prec] * N / (rr["ms_kernel"] * 1e-3) / 1e9, 1),
                            "tile": list(rr["tile"])}
+        if args.workload == "tiled8192":  # the smaller roofline grid of the same tiling
+            c4, p4, _ = make_workload("tiled4096")
+            n4 = c4["nx"] * c4["ny"]
+            for prec in ("fp64", "fp32", "fp16"):
+                rr = time_lattice(c4, p4, prec, args.steps, args.warmup)
+                extra[f"tiled4096_{prec}"] = {
+                    "MLUPS": round(n4 * args.steps / rr["wall_s"] / 1e6, 1),
+                    "kernel_GBs": round(36 * STORE[prec] * n4 / (rr["ms_kernel"] * 1e-3) / 1e9, 1),
+                    "tile": list(rr["tile"])}
         out["extra"] = extra
     if args.batched:
         out["batched"] = {p: bench_batched(p, 5000) for p in ("fp16", "bf16", "fp32")}
