@@ -46,6 +46,18 @@ int64_t plane_elems(int nx, int ny) { return (int64_t)align_up((uint64_t)nx * ny
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0; }
 
+// Workgroup widths with a step kernel: powers of two, 64k + 4 (strips of whole
+// cache lines), and 1024 (16 waves per CU: FP32-compute kernels without
+// prefetching only).  FP64 prefetching has no 516-lane kernel (it would spill).
+bool valid_width(int tx, int prec, int pf) {
+    switch (tx) {
+    case 64: case 128: case 132: case 256: case 260: case 512: return true;
+    case 516: return !(prec == LB_FP64 && pf != 0);
+    case 1024: return prec != LB_FP64 && pf == 0;
+    }
+    return false;
+}
+
 lb_status validate(const lb_config* c) {
     if (!c) return LB_E_INVALID_ARG;
     if (c->nx < 8 || c->ny < 8 || c->nx > (1 << 20) || c->ny > (1 << 20)) return LB_E_INVALID_ARG;
@@ -83,11 +95,7 @@ lb_status validate(const lb_config* c) {
                          1.0 / (0.5 + 3.0 * c->M)};
     for (double o : om)
         if (!(o > 0.0 && o < 2.0)) return LB_E_INVALID_ARG;
-    if (c->tile_x != 0 && c->tile_x != 64 && c->tile_x != 128 && c->tile_x != 256 && c->tile_x != 512 &&
-        c->tile_x != 1024)
-        return LB_E_INVALID_ARG;
-    // 1024 lanes = 16 waves per CU: only the FP32-compute kernels without prefetching fit
-    if (c->tile_x == 1024 && (c->precision == LB_FP64 || c->tile_pf != 0)) return LB_E_INVALID_ARG;
+    if (c->tile_x != 0 && !valid_width(c->tile_x, c->precision, c->tile_pf)) return LB_E_INVALID_ARG;
     if (c->tile_h < 0 || (c->tile_h > 0 && c->tile_h < kMinH)) return LB_E_INVALID_ARG;
     if (c->diag_every < 0) return LB_E_INVALID_ARG;
     return LB_OK;
@@ -460,9 +468,9 @@ double time_candidate(int prec, int kind, int tx, int pf, const LatDesc* d, cons
 std::vector<Sched> candidates(int prec, int nx, int ny, int kind) {
     std::vector<Sched> out;
     for (int pf : {PF_HOLD, PF_PREFETCH})
-        for (int tx : {64, 128, 256, 512, 1024}) {
+        for (int tx : {64, 128, 132, 256, 260, 512, 516, 1024}) {
             if (pf != PF_HOLD && kind != KIND_COUPLED_CASCADED) continue;
-            if (tx == 1024 && (prec == LB_FP64 || pf != PF_HOLD)) continue;
+            if (!valid_width(tx, prec, pf)) continue;
             if (tx > 64 && nx <= strip_w(tx / 2)) continue;
             for (int th : {16, 32, 64, 128, 256}) {
                 if (th > ny && th != 16) continue;
@@ -1092,9 +1100,7 @@ lb_status lb_batch_create(int32_t slots, int64_t node_capacity, int32_t precisio
                           lb_batch** out) {
     if (!out || !dev_ws || slots <= 0 || node_capacity < 64 || store_bytes(precision) == 0)
         return LB_E_INVALID_ARG;
-    if (tile_x != 0 && tile_x != 64 && tile_x != 128 && tile_x != 256 && tile_x != 512 && tile_x != 1024)
-        return LB_E_INVALID_ARG;
-    if (tile_x == 1024 && precision == LB_FP64) return LB_E_INVALID_ARG;
+    if (tile_x != 0 && !valid_width(tile_x, precision, 0)) return LB_E_INVALID_ARG;
     if (tile_h < 0 || (tile_h > 0 && tile_h < kMinH)) return LB_E_INVALID_ARG;
     *out = nullptr;
     const BatchLayout L = batch_layout(slots, node_capacity, precision);

@@ -8,8 +8,9 @@
 // (f_a(x) = f~_a(x - e_a)), so streaming costs nothing extra.
 //
 // One workgroup of TX lanes owns a strip of TX - 4 columns and a run of rows of
-// one lattice (a work item); lane t sits on column x0 - 2 + t, so the two halo
-// columns on each side are ordinary lanes.  The workgroup marches upward one
+// one lattice (a work item); column slot t sits on column x0 - 2 + t, so the two
+// halo columns on each side are ordinary lanes (see lane_slot for which lane holds
+// which slot).  The workgroup marches upward one
 // row per iteration:
 //   A  every lane: pull f at the leading row L        -> phi(L)    (LDS ring)
 //   B  lanes 1..w+2: pull gbar at row L-1             -> pbar(L-1) (LDS ring)
@@ -209,6 +210,16 @@ __device__ __forceinline__ void pull9(const typename ST::T* __restrict__ base, i
             out[7] = (sx && !top) ? ldo<ST, RAW>(rtp + 8 * nx, x) : ldo<ST, RAW>(ro + 5 * nx, x);
         }
     }
+}
+
+// Column slot of a lane in a TX-lane workgroup: slots 0, 1 and TX-2, TX-1 hold the
+// halo columns, slots 2..TX-3 the strip (slot s sits on column x0 - 2 + s).  Lanes
+// 0..TX-5 take the strip (slot = lane + 2) and the last four lanes the halo, so with
+// TX - 4 a multiple of 64 every wave but the last starts its loads and stores of the
+// strip on a cache-line boundary (x0 is then a multiple of 64).
+template <int TX>
+__device__ __forceinline__ int lane_slot(int lane) {
+    return lane < TX - 4 ? lane + 2 : (lane < TX - 2 ? lane - (TX - 4) : lane);
 }
 
 template <class R>
@@ -552,7 +563,7 @@ lb_fused(const LatDesc* __restrict__ descs, const WorkItem* __restrict__ items, 
     __shared__ R s_pb[4][TX];
     __shared__ R s_na[4][TX];  // n_x (geometric) or mu_phi (chemical potential)
     __shared__ R s_nb[4][TX];  // n_y (geometric)
-    const int t = threadIdx.x;
+    const int t = lane_slot<TX>(threadIdx.x);  // column slot of this lane
 
     for (int wi = blockIdx.x; wi < n_items; wi += gridDim.x) {
         const WorkItem it = items[wi];
@@ -725,7 +736,7 @@ lb_fused(const LatDesc* __restrict__ descs, const WorkItem* __restrict__ items, 
 
 // The conservative Allen-Cahn step alone under an imposed velocity (planes ux, uy
 // of the compute type at D.vel, stride D.plane).  Same work items and lane layout
-// as lb_fused (lane t at column x0 - 2 + t, strips of TX - 4 columns); the
+// as lb_fused (slot t at column x0 - 2 + t, strips of TX - 4 columns); the
 // pipeline lags one row: pull f at row L into the phi ring, then take grad phi,
 // n and theta at row L - 1 and collide it.  One barrier per row suffices with a
 // ring of four rows.  COLL selects the cascaded or the SRT collision.
@@ -736,7 +747,7 @@ __global__ void __launch_bounds__(TX) lb_ace(const LatDesc* __restrict__ descs,
     using R = typename ST::R;
     using T = typename ST::T;
     __shared__ R s_phi[4][TX];
-    const int t = threadIdx.x;
+    const int t = lane_slot<TX>(threadIdx.x);  // column slot of this lane
 
     for (int wi = blockIdx.x; wi < n_items; wi += gridDim.x) {
         const WorkItem it = items[wi];

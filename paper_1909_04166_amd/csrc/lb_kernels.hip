@@ -31,6 +31,26 @@ static hipError_t launch_tx(int tx, const LatDesc* d, const WorkItem* items, int
     case 128: launch_one<ST, 128, MODE, PF, KIND>(dim3(grid), d, items, n_items, parity, s); break;
     case 256: launch_one<ST, 256, MODE, PF, KIND>(dim3(grid), d, items, n_items, parity, s); break;
     case 512: launch_one<ST, 512, MODE, PF, KIND>(dim3(grid), d, items, n_items, parity, s); break;
+    // 64k + 4 lanes: strips of 64k columns, so every wave but the last works on
+    // whole cache lines (see lane_slot); step kernels only
+    case 132:
+        if constexpr (MODE == MODE_STEP)
+            launch_one<ST, 132, MODE, PF, KIND>(dim3(grid), d, items, n_items, parity, s);
+        else
+            return hipErrorInvalidValue;
+        break;
+    case 260:
+        if constexpr (MODE == MODE_STEP)
+            launch_one<ST, 260, MODE, PF, KIND>(dim3(grid), d, items, n_items, parity, s);
+        else
+            return hipErrorInvalidValue;
+        break;
+    case 516:  // 9 waves: FP64 prefetching would spill at the 3 waves per SIMD this needs
+        if constexpr (MODE == MODE_STEP && !(sizeof(typename ST::R) == 8 && PF == PF_PREFETCH))
+            launch_one<ST, 516, MODE, PF, KIND>(dim3(grid), d, items, n_items, parity, s);
+        else
+            return hipErrorInvalidValue;
+        break;
     case 1024:  // 16 waves: FP32 compute without prefetching only (4 waves per SIMD)
         if constexpr (sizeof(typename ST::R) == 4 && PF == PF_HOLD && MODE == MODE_STEP)
             launch_one<ST, 1024, MODE, PF, KIND>(dim3(grid), d, items, n_items, parity, s);
@@ -97,6 +117,21 @@ static int occ_st(int kind, int tx, int pf) {
     case 128: return occ_kind<ST, 128>(kind, pf);
     case 256: return occ_kind<ST, 256>(kind, pf);
     case 512: return occ_kind<ST, 512>(kind, pf);
+    case 132: return occ_kind<ST, 132>(kind, pf);
+    case 260: return occ_kind<ST, 260>(kind, pf);
+    case 516:
+        if constexpr (sizeof(typename ST::R) == 8) {
+            if (pf == PF_PREFETCH) return 0;
+            switch (kind) {
+            case KIND_COUPLED_CASCADED: return occ_of(lb_fused<ST, 516, MODE_STEP, PF_HOLD, COLL_CASCADED>, 516);
+            case KIND_COUPLED_SRT: return occ_of(lb_fused<ST, 516, MODE_STEP, PF_HOLD, COLL_SRT>, 516);
+            case KIND_ACE_CASCADED: return occ_of(lb_ace<ST, 516, MODE_STEP, COLL_CASCADED>, 516);
+            case KIND_ACE_SRT: return occ_of(lb_ace<ST, 516, MODE_STEP, COLL_SRT>, 516);
+            }
+            return 0;
+        } else {
+            return occ_kind<ST, 516>(kind, pf);
+        }
     case 1024:
         if constexpr (sizeof(typename ST::R) == 4) {
             if (pf != PF_HOLD) return 0;

@@ -103,7 +103,8 @@ def test_coupling_fields_match_oracle():
 
 
 # (workgroup width, rows per item[, 1 = the variant that prefetches the next rows])
-TILES = [(64, 8), (64, 16), (128, 32), (256, 64), (512, 24), (64, 16, 1), (256, 64, 1), (512, 24, 1)]
+TILES = [(64, 8), (64, 16), (128, 32), (132, 16), (256, 64), (260, 40), (512, 24), (516, 24),
+         (64, 16, 1), (256, 64, 1), (260, 40, 1), (512, 24, 1)]
 
 
 @pytest.mark.parametrize("tile", TILES)
@@ -278,16 +279,18 @@ def test_row_variants_each_precision(prec, tol, pf):
     assert err <= tol
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
-def test_wide_workgroups_bit_identical(prec):
-    """1024-lane workgroups (FP32-compute precisions only) across a ragged width of
-    three strips, walls in y: bit-identical to 512- and 64-lane tilings (every
-    instantiation rounds the same), and FP32 within the stated 1e-4 of the oracle."""
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16", "bf16"])
+def test_workgroup_widths_bit_identical(prec):
+    """Every workgroup width (1024 lanes for the FP32-compute precisions only; the
+    64k + 4 widths with their halo lanes last) across a ragged width of several
+    strips, walls in y: bit-identical to the 64-lane tiling (every instantiation
+    rounds the same), and FP32 within the stated 1e-4 of the oracle."""
     case, phi0 = W.random_case(2100, 40, seed=51, bc_y="wall")
     case.update(gy=-2e-5, rho_A=10.0)
-    _print_case(f"1024 lanes {prec}", case)
+    _print_case(f"workgroup widths {prec}", case)
     runs = []
-    for tile in [(1024, 24), (512, 24), (64, 16)]:
+    tiles = [(64, 16), (132, 16), (260, 40), (512, 24), (516, 24)] + ([(1024, 24)] if prec != "fp64" else [])
+    for tile in tiles:
         g = lb.Lattice(case, phi0, prec, tile=tile)
         assert g.tile[0] == tile[0]
         g.step(30)
@@ -298,7 +301,7 @@ def test_wide_workgroups_bit_identical(prec):
     if prec == "fp32":
         o = oracle.Oracle(case, phi0)
         o.step(30)
-        g = lb.Lattice(case, phi0, prec, tile=(1024, 24))
+        g = lb.Lattice(case, phi0, prec, tile=(516, 24))
         g.step(30)
         err = np.abs(g.fields()[0] - o.fields()[0]).max()
         print(f"   fp32 phi vs oracle {err:.2e}", flush=True)

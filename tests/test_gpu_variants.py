@@ -91,7 +91,7 @@ def test_one_step_imposed_flow(coll):
     _cmp_dist(g, o, 1e-14)
 
 
-TILES = [(64, 8), (128, 32), (256, 64), (512, 16)]
+TILES = [(64, 8), (128, 32), (256, 64), (260, 12), (512, 16), (516, 16)]
 
 
 @pytest.mark.parametrize("tile", TILES)
