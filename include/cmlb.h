@@ -99,7 +99,7 @@ typedef struct lb_config {
     double gx, gy;           /* body-force acceleration */
     double shift_f, shift_g; /* 16-bit storage stores f_a - w_a shift_f and g_a - w_a shift_g */
     double u_max;            /* stability limit for diagnostics (0: 0.3) */
-    int32_t tile_x;          /* workgroup width in lanes: 64, 128, 132, 256, 260, 512,
+    int32_t tile_x;          /* workgroup width in lanes: 64, 128, 132, 256, 260, 452, 512,
                                 516 (not with FP64 prefetching), or 1024 (FP32-compute
                                 precisions without prefetching); strips of tile_x - 4
                                 columns; 0: autotuned */

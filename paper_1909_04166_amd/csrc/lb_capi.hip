@@ -47,11 +47,12 @@ int64_t plane_elems(int nx, int ny) { return (int64_t)align_up((uint64_t)nx * ny
 bool finite_pos(double v) { return std::isfinite(v) && v > 0; }
 
 // Workgroup widths with a step kernel: powers of two, 64k + 4 (strips of whole
-// cache lines), and 1024 (16 waves per CU: FP32-compute kernels without
+// 64-column blocks: 132, 260, 516, and 452 = two 8-wave workgroups per CU at four
+// waves per SIMD), and 1024 (16 waves per CU: FP32-compute kernels without
 // prefetching only).  FP64 prefetching has no 516-lane kernel (it would spill).
 bool valid_width(int tx, int prec, int pf) {
     switch (tx) {
-    case 64: case 128: case 132: case 256: case 260: case 512: return true;
+    case 64: case 128: case 132: case 256: case 260: case 452: case 512: return true;
     case 516: return !(prec == LB_FP64 && pf != 0);
     case 1024: return prec != LB_FP64 && pf == 0;
     }
@@ -468,7 +469,7 @@ double time_candidate(int prec, int kind, int tx, int pf, const LatDesc* d, cons
 std::vector<Sched> candidates(int prec, int nx, int ny, int kind) {
     std::vector<Sched> out;
     for (int pf : {PF_HOLD, PF_PREFETCH})
-        for (int tx : {64, 128, 132, 256, 260, 512, 516, 1024}) {
+        for (int tx : {64, 128, 132, 256, 260, 452, 512, 516, 1024}) {
             if (pf != PF_HOLD && kind != KIND_COUPLED_CASCADED) continue;
             if (!valid_width(tx, prec, pf)) continue;
             if (tx > 64 && nx <= strip_w(tx / 2)) continue;

@@ -45,6 +45,12 @@ static hipError_t launch_tx(int tx, const LatDesc* d, const WorkItem* items, int
         else
             return hipErrorInvalidValue;
         break;
+    case 452:
+        if constexpr (MODE == MODE_STEP)
+            launch_one<ST, 452, MODE, PF, KIND>(dim3(grid), d, items, n_items, parity, s);
+        else
+            return hipErrorInvalidValue;
+        break;
     case 516:  // 9 waves: FP64 prefetching would spill at the 3 waves per SIMD this needs
         if constexpr (MODE == MODE_STEP && !(sizeof(typename ST::R) == 8 && PF == PF_PREFETCH))
             launch_one<ST, 516, MODE, PF, KIND>(dim3(grid), d, items, n_items, parity, s);
@@ -119,6 +125,7 @@ static int occ_st(int kind, int tx, int pf) {
     case 512: return occ_kind<ST, 512>(kind, pf);
     case 132: return occ_kind<ST, 132>(kind, pf);
     case 260: return occ_kind<ST, 260>(kind, pf);
+    case 452: return occ_kind<ST, 452>(kind, pf);
     case 516:
         if constexpr (sizeof(typename ST::R) == 8) {
             if (pf == PF_PREFETCH) return 0;

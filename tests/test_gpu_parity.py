@@ -103,8 +103,8 @@ def test_coupling_fields_match_oracle():
 
 
 # (workgroup width, rows per item[, 1 = the variant that prefetches the next rows])
-TILES = [(64, 8), (64, 16), (128, 32), (132, 16), (256, 64), (260, 40), (512, 24), (516, 24),
-         (64, 16, 1), (256, 64, 1), (260, 40, 1), (512, 24, 1)]
+TILES = [(64, 8), (64, 16), (128, 32), (132, 16), (256, 64), (260, 40), (452, 16), (512, 24), (516, 24),
+         (64, 16, 1), (256, 64, 1), (260, 40, 1), (452, 16, 1), (512, 24, 1)]
 
 
 @pytest.mark.parametrize("tile", TILES)
@@ -289,7 +289,8 @@ def test_workgroup_widths_bit_identical(prec):
     case.update(gy=-2e-5, rho_A=10.0)
     _print_case(f"workgroup widths {prec}", case)
     runs = []
-    tiles = [(64, 16), (132, 16), (260, 40), (512, 24), (516, 24)] + ([(1024, 24)] if prec != "fp64" else [])
+    tiles = [(64, 16), (132, 16), (260, 40), (452, 24), (512, 24), (516, 24)] + (
+        [(1024, 24)] if prec != "fp64" else [])
     for tile in tiles:
         g = lb.Lattice(case, phi0, prec, tile=tile)
         assert g.tile[0] == tile[0]
