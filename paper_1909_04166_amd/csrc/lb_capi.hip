@@ -263,7 +263,7 @@ struct Sched {
     int grid = 0, n_items = 0, rows = 0;
 };
 
-bool build_schedule(const std::vector<LatShape>& lats, int prec, int kind, Sched& sc, int max_items,
+bool build_schedule(const std::vector<LatShape>& lats, int prec, int kind, bool walls, Sched& sc, int max_items,
                     std::vector<WorkItem>& items) {
     items.clear();
     if (sc.mode == 0) {
@@ -273,7 +273,7 @@ bool build_schedule(const std::vector<LatShape>& lats, int prec, int kind, Sched
         sc.rows = sc.th;
         xcd_permute(items, sc.grid);
     } else {
-        int G = sc.mult * std::max(1, step_occupancy(prec, kind, sc.tx, sc.pf)) * cu_count();
+        int G = sc.mult * std::max(1, step_occupancy(prec, kind, walls, sc.tx, sc.pf)) * cu_count();
         G = std::min(G, kMaxGrid);
         int nb = 0;
         if (!build_segments(lats, sc.tx, G, max_items, items, &nb)) return false;
@@ -320,6 +320,7 @@ std::map<TuneKey, Sched> g_tune;
 struct lb_handle {
     lb_config cfg;
     int kind = KIND_COUPLED_CASCADED;
+    bool walls = true;  // the lattice has a wall on some side (else the wall-free kernels run)
     hipStream_t s = nullptr;
     char* ws = nullptr;
     uint64_t ws_bytes = 0;
@@ -384,7 +385,7 @@ Layout layout_of(const lb_config* c) {
 
 lb_status set_sched(lb_handle* h, Sched sc) {
     std::vector<WorkItem> items;
-    if (!build_schedule({{0, h->cfg.nx, h->cfg.ny}}, h->cfg.precision, h->kind, sc, h->max_items, items))
+    if (!build_schedule({{0, h->cfg.nx, h->cfg.ny}}, h->cfg.precision, h->kind, h->walls, sc, h->max_items, items))
         return LB_E_INVALID_ARG;
     HIPC(hipMemcpyAsync(h->d_items, items.data(), items.size() * sizeof(WorkItem),
                         hipMemcpyHostToDevice, h->s));
@@ -398,7 +399,7 @@ lb_status set_sched(lb_handle* h, Sched sc) {
 
 lb_status launch_steps_eager(lb_handle* h, int64_t n) {
     for (int64_t i = 0; i < n; ++i) {
-        HIPC(launch_step(h->cfg.precision, h->kind, h->sc.tx, h->sc.pf, h->d_desc, h->d_items, h->n_items,
+        HIPC(launch_step(h->cfg.precision, h->kind, h->walls, h->sc.tx, h->sc.pf, h->d_desc, h->d_items, h->n_items,
                          h->sc.grid, h->parity, h->s));
         h->parity ^= 1;
         h->step += 1;
@@ -415,7 +416,7 @@ lb_status graph_for(lb_handle* h, int parity, hipGraphExec_t* out) {
         hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         int p = parity;
         for (int i = 0; i < h->glen && e == hipSuccess; ++i) {
-            e = launch_step(h->cfg.precision, h->kind, h->sc.tx, h->sc.pf, h->d_desc, h->d_items, h->n_items,
+            e = launch_step(h->cfg.precision, h->kind, h->walls, h->sc.tx, h->sc.pf, h->d_desc, h->d_items, h->n_items,
                             h->sc.grid, p, cs);
             p ^= 1;
         }
@@ -446,16 +447,16 @@ lb_status enqueue_diag(lb_handle* h) {
 
 // Times `reps` launches of one candidate without advancing the state (every
 // launch reads the current buffer and overwrites the other one).
-double time_candidate(int prec, int kind, int tx, int pf, const LatDesc* d, const WorkItem* items, int n,
+double time_candidate(int prec, int kind, bool walls, int tx, int pf, const LatDesc* d, const WorkItem* items, int n,
                       int grid, int parity, hipStream_t s, int reps) {
     hipEvent_t a, b;
     if (hipEventCreate(&a) != hipSuccess) return 1e30;
     if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return 1e30; }
     double ms_out = 1e30;
-    bool ok = launch_step(prec, kind, tx, pf, d, items, n, grid, parity, s) == hipSuccess;
+    bool ok = launch_step(prec, kind, walls, tx, pf, d, items, n, grid, parity, s) == hipSuccess;
     ok = ok && hipEventRecord(a, s) == hipSuccess;
     for (int i = 0; i < reps && ok; ++i)
-        ok = launch_step(prec, kind, tx, pf, d, items, n, grid, parity, s) == hipSuccess;
+        ok = launch_step(prec, kind, walls, tx, pf, d, items, n, grid, parity, s) == hipSuccess;
     ok = ok && hipEventRecord(b, s) == hipSuccess && hipEventSynchronize(b) == hipSuccess;
     float ms = 0;
     if (ok && hipEventElapsedTime(&ms, a, b) == hipSuccess) ms_out = ms / reps;
@@ -501,11 +502,11 @@ lb_status autotune_single(lb_handle* h) {
     auto timed = [&](Sched& sc, int r, double* ms) -> lb_status {
         std::vector<WorkItem> items;
         *ms = 1e30;
-        if (!build_schedule({{0, h->cfg.nx, h->cfg.ny}}, h->cfg.precision, h->kind, sc, h->max_items, items))
+        if (!build_schedule({{0, h->cfg.nx, h->cfg.ny}}, h->cfg.precision, h->kind, h->walls, sc, h->max_items, items))
             return LB_OK;
         HIPC(hipMemcpyAsync(h->d_items, items.data(), items.size() * sizeof(WorkItem),
                             hipMemcpyHostToDevice, h->s));
-        *ms = time_candidate(h->cfg.precision, h->kind, sc.tx, sc.pf, h->d_desc, h->d_items, sc.n_items,
+        *ms = time_candidate(h->cfg.precision, h->kind, h->walls, sc.tx, sc.pf, h->d_desc, h->d_items, sc.n_items,
                              sc.grid, h->parity, h->s, r);
         return LB_OK;
     };
@@ -588,6 +589,7 @@ lb_status lb_create(const lb_config* cfg, void* dev_ws, uint64_t ws_bytes, void*
     h->glen = 32;
     h->kind = kind_of(cfg);
     fill_desc(cfg, h->hdesc, h->buf[0], h->buf[1], h->plane, h->d_fields);
+    h->walls = h->hdesc.wall_y != WALL_NONE || h->hdesc.wall_x != WALL_NONE;
     h->hdesc.vel = cfg->flow == LB_FLOW_IMPOSED ? (void*)(h->ws + L.vel) : nullptr;
     h->hdesc.ktab = (double*)(h->ws + L.ktab);
     auto fail = [&](lb_status s) { lb_destroy(h); return s; };
@@ -906,6 +908,7 @@ struct lb_batch {
     Sched sc;
     bool fixed_tile = false;
     bool dirty = true;
+    bool walls = true;  // some occupied slot has walls (set when the work list is rebuilt)
     int64_t tuned_nodes = 0;  // nodes in use when the schedule was last autotuned
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     int glen = 16;
@@ -992,7 +995,7 @@ std::vector<LatShape> batch_shapes(lb_batch* b) {
 
 lb_status batch_set_sched(lb_batch* b, Sched sc) {
     std::vector<WorkItem> items;
-    if (!build_schedule(batch_shapes(b), b->prec, std::max(b->kind, 0), sc, b->max_items, items))
+    if (!build_schedule(batch_shapes(b), b->prec, std::max(b->kind, 0), b->walls, sc, b->max_items, items))
         return LB_E_WORKSPACE;
     if (!items.empty())
         HIPC(hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(WorkItem),
@@ -1017,10 +1020,10 @@ lb_status batch_autotune(lb_batch* b) {
     auto timed = [&](Sched& sc, int reps, double* ms) -> lb_status {
         std::vector<WorkItem> items;
         *ms = 1e30;
-        if (!build_schedule(lats, b->prec, b->kind, sc, b->max_items, items)) return LB_OK;
+        if (!build_schedule(lats, b->prec, b->kind, b->walls, sc, b->max_items, items)) return LB_OK;
         HIPC(hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(WorkItem),
                             hipMemcpyHostToDevice, b->s));
-        *ms = time_candidate(b->prec, b->kind, sc.tx, sc.pf, b->d_descs, b->d_items, sc.n_items, sc.grid,
+        *ms = time_candidate(b->prec, b->kind, b->walls, sc.tx, sc.pf, b->d_descs, b->d_items, sc.n_items, sc.grid,
                              b->parity, b->s, reps);
         return LB_OK;
     };
@@ -1053,7 +1056,7 @@ lb_status batch_graph(lb_batch* b, int parity, hipGraphExec_t* out) {
         hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         int p = parity;
         for (int i = 0; i < b->glen && e == hipSuccess; ++i) {
-            e = launch_step(b->prec, b->kind, b->sc.tx, b->sc.pf, b->d_descs, b->d_items, b->n_items, b->sc.grid,
+            e = launch_step(b->prec, b->kind, b->walls, b->sc.tx, b->sc.pf, b->d_descs, b->d_items, b->n_items, b->sc.grid,
                             p, cs);
             p ^= 1;
         }
@@ -1214,6 +1217,11 @@ lb_status lb_batch_step(lb_batch* b, int64_t n, int32_t use_graph) {
         int32_t used;
         int64_t nodes;
         lb_batch_usage(b, &used, &nodes);
+        // the kernels without wall logic serve batches of periodic lattices only
+        b->walls = false;
+        for (int i = 0; i < b->nslots; ++i)
+            if (b->slot[i].used && (b->slot[i].cfg.bc_x != LB_PERIODIC || b->slot[i].cfg.bc_y != LB_PERIODIC))
+                b->walls = true;
         // autotune when the load changed by more than 2x since the last tuning,
         // otherwise rebuild the work list with the current schedule
         const bool retune = !b->fixed_tile && nodes > 0 &&
@@ -1237,7 +1245,7 @@ lb_status lb_batch_step(lb_batch* b, int64_t n, int32_t use_graph) {
             left -= reps * b->glen;  // glen is even: parity unchanged
         }
         for (int64_t i = 0; i < left; ++i) {
-            HIPC(launch_step(b->prec, b->kind, b->sc.tx, b->sc.pf, b->d_descs, b->d_items, b->n_items, b->sc.grid,
+            HIPC(launch_step(b->prec, b->kind, b->walls, b->sc.tx, b->sc.pf, b->d_descs, b->d_items, b->n_items, b->sc.grid,
                              b->parity, b->s));
             b->parity ^= 1;
         }

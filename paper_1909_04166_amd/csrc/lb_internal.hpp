@@ -8,9 +8,10 @@
 
 namespace cmlb {
 
-// kind: KIND_*; pf != 0 selects the variant that prefetches the next rows during
-// the collision (coupled cascaded kind only).
-hipError_t launch_step(int prec, int kind, int tx, int pf, const LatDesc* d, const WorkItem* items,
+// kind: KIND_*; walls false: no lattice of the launch has walls (the kernels
+// without wall logic run); pf != 0 selects the variant that prefetches the next
+// rows (coupled cascaded kind only).
+hipError_t launch_step(int prec, int kind, bool walls, int tx, int pf, const LatDesc* d, const WorkItem* items,
                        int n_items, int grid, int parity, hipStream_t s);
 hipError_t launch_extract(int prec, int kind, int mode, const LatDesc* d, const WorkItem* items64,
                           int n_items, int parity, hipStream_t s);
@@ -25,6 +26,6 @@ hipError_t launch_diag(const LatDesc* d, const double* fields, double* part, dou
                        double step, double u_max, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, uint64_t n, hipStream_t s);
 // Resident workgroups per CU of a step kernel (from the HIP occupancy API).
-int step_occupancy(int prec, int kind, int tx, int pf);
+int step_occupancy(int prec, int kind, bool walls, int tx, int pf);
 
 }  // namespace cmlb

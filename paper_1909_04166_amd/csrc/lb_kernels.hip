@@ -7,59 +7,60 @@ namespace cmlb {
 
 // The kernel behind a step: the coupled pair (lb_fused) or the phase field alone
 // (lb_ace), with the cascaded or the SRT collisions.  The variant that prefetches
-// rows (PF_PREFETCH) exists for the coupled cascaded kernel only.
-template <class ST, int TX, int MODE, int PF, int KIND>
+// rows (PF_PREFETCH) exists for the coupled cascaded kernel only.  W false: the
+// launch's lattices have no walls (the kernels' wall logic is compiled out).
+template <class ST, int TX, int MODE, int PF, int KIND, bool W>
 static void launch_one(dim3 grid, const LatDesc* d, const WorkItem* items, int n_items, int parity,
                        hipStream_t s) {
     if constexpr (KIND == KIND_COUPLED_CASCADED)
-        hipLaunchKernelGGL((lb_fused<ST, TX, MODE, PF, COLL_CASCADED>), grid, dim3(TX), 0, s, d, items, n_items, parity);
+        hipLaunchKernelGGL((lb_fused<ST, TX, MODE, PF, COLL_CASCADED, W>), grid, dim3(TX), 0, s, d, items, n_items, parity);
     else if constexpr (KIND == KIND_COUPLED_SRT)
-        hipLaunchKernelGGL((lb_fused<ST, TX, MODE, PF_HOLD, COLL_SRT>), grid, dim3(TX), 0, s, d, items, n_items, parity);
+        hipLaunchKernelGGL((lb_fused<ST, TX, MODE, PF_HOLD, COLL_SRT, W>), grid, dim3(TX), 0, s, d, items, n_items, parity);
     else if constexpr (KIND == KIND_ACE_CASCADED)
-        hipLaunchKernelGGL((lb_ace<ST, TX, MODE, COLL_CASCADED>), grid, dim3(TX), 0, s, d, items, n_items, parity);
+        hipLaunchKernelGGL((lb_ace<ST, TX, MODE, COLL_CASCADED, W>), grid, dim3(TX), 0, s, d, items, n_items, parity);
     else
-        hipLaunchKernelGGL((lb_ace<ST, TX, MODE, COLL_SRT>), grid, dim3(TX), 0, s, d, items, n_items, parity);
+        hipLaunchKernelGGL((lb_ace<ST, TX, MODE, COLL_SRT, W>), grid, dim3(TX), 0, s, d, items, n_items, parity);
 }
 
-template <class ST, int MODE, int PF, int KIND>
+template <class ST, int MODE, int PF, int KIND, bool W = true>
 static hipError_t launch_tx(int tx, const LatDesc* d, const WorkItem* items, int n_items, int grid,
                             int parity, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
     if (grid <= 0 || grid > n_items) grid = n_items;
     switch (tx) {
-    case 64: launch_one<ST, 64, MODE, PF, KIND>(dim3(grid), d, items, n_items, parity, s); break;
-    case 128: launch_one<ST, 128, MODE, PF, KIND>(dim3(grid), d, items, n_items, parity, s); break;
-    case 256: launch_one<ST, 256, MODE, PF, KIND>(dim3(grid), d, items, n_items, parity, s); break;
-    case 512: launch_one<ST, 512, MODE, PF, KIND>(dim3(grid), d, items, n_items, parity, s); break;
+    case 64: launch_one<ST, 64, MODE, PF, KIND, W>(dim3(grid), d, items, n_items, parity, s); break;
+    case 128: launch_one<ST, 128, MODE, PF, KIND, W>(dim3(grid), d, items, n_items, parity, s); break;
+    case 256: launch_one<ST, 256, MODE, PF, KIND, W>(dim3(grid), d, items, n_items, parity, s); break;
+    case 512: launch_one<ST, 512, MODE, PF, KIND, W>(dim3(grid), d, items, n_items, parity, s); break;
     // 64k + 4 lanes: strips of 64k columns, so every wave but the last works on
     // whole cache lines (see lane_slot); step kernels only
     case 132:
         if constexpr (MODE == MODE_STEP)
-            launch_one<ST, 132, MODE, PF, KIND>(dim3(grid), d, items, n_items, parity, s);
+            launch_one<ST, 132, MODE, PF, KIND, W>(dim3(grid), d, items, n_items, parity, s);
         else
             return hipErrorInvalidValue;
         break;
     case 260:
         if constexpr (MODE == MODE_STEP)
-            launch_one<ST, 260, MODE, PF, KIND>(dim3(grid), d, items, n_items, parity, s);
+            launch_one<ST, 260, MODE, PF, KIND, W>(dim3(grid), d, items, n_items, parity, s);
         else
             return hipErrorInvalidValue;
         break;
     case 452:
         if constexpr (MODE == MODE_STEP)
-            launch_one<ST, 452, MODE, PF, KIND>(dim3(grid), d, items, n_items, parity, s);
+            launch_one<ST, 452, MODE, PF, KIND, W>(dim3(grid), d, items, n_items, parity, s);
         else
             return hipErrorInvalidValue;
         break;
     case 516:  // 9 waves: FP64 prefetching would spill at the 3 waves per SIMD this needs
         if constexpr (MODE == MODE_STEP && !(sizeof(typename ST::R) == 8 && PF == PF_PREFETCH))
-            launch_one<ST, 516, MODE, PF, KIND>(dim3(grid), d, items, n_items, parity, s);
+            launch_one<ST, 516, MODE, PF, KIND, W>(dim3(grid), d, items, n_items, parity, s);
         else
             return hipErrorInvalidValue;
         break;
     case 1024:  // 16 waves: FP32 compute without prefetching only (4 waves per SIMD)
         if constexpr (sizeof(typename ST::R) == 4 && PF == PF_HOLD && MODE == MODE_STEP)
-            launch_one<ST, 1024, MODE, PF, KIND>(dim3(grid), d, items, n_items, parity, s);
+            launch_one<ST, 1024, MODE, PF, KIND, W>(dim3(grid), d, items, n_items, parity, s);
         else
             return hipErrorInvalidValue;
         break;
@@ -68,31 +69,38 @@ static hipError_t launch_tx(int tx, const LatDesc* d, const WorkItem* items, int
     return hipGetLastError();
 }
 
-template <class ST>
-static hipError_t launch_step_st(int kind, int tx, int pf, const LatDesc* d, const WorkItem* items,
+template <class ST, bool W>
+static hipError_t launch_step_kind(int kind, int tx, int pf, const LatDesc* d, const WorkItem* items,
                                  int n_items, int grid, int parity, hipStream_t s) {
     switch (kind) {
     case KIND_COUPLED_CASCADED:
         if (pf == PF_PREFETCH)
-            return launch_tx<ST, MODE_STEP, PF_PREFETCH, KIND_COUPLED_CASCADED>(tx, d, items, n_items, grid, parity, s);
-        return launch_tx<ST, MODE_STEP, PF_HOLD, KIND_COUPLED_CASCADED>(tx, d, items, n_items, grid, parity, s);
+            return launch_tx<ST, MODE_STEP, PF_PREFETCH, KIND_COUPLED_CASCADED, W>(tx, d, items, n_items, grid, parity, s);
+        return launch_tx<ST, MODE_STEP, PF_HOLD, KIND_COUPLED_CASCADED, W>(tx, d, items, n_items, grid, parity, s);
     case KIND_COUPLED_SRT:
-        return launch_tx<ST, MODE_STEP, PF_HOLD, KIND_COUPLED_SRT>(tx, d, items, n_items, grid, parity, s);
+        return launch_tx<ST, MODE_STEP, PF_HOLD, KIND_COUPLED_SRT, W>(tx, d, items, n_items, grid, parity, s);
     case KIND_ACE_CASCADED:
-        return launch_tx<ST, MODE_STEP, PF_HOLD, KIND_ACE_CASCADED>(tx, d, items, n_items, grid, parity, s);
+        return launch_tx<ST, MODE_STEP, PF_HOLD, KIND_ACE_CASCADED, W>(tx, d, items, n_items, grid, parity, s);
     case KIND_ACE_SRT:
-        return launch_tx<ST, MODE_STEP, PF_HOLD, KIND_ACE_SRT>(tx, d, items, n_items, grid, parity, s);
+        return launch_tx<ST, MODE_STEP, PF_HOLD, KIND_ACE_SRT, W>(tx, d, items, n_items, grid, parity, s);
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_step(int prec, int kind, int tx, int pf, const LatDesc* d, const WorkItem* items,
+template <class ST>
+static hipError_t launch_step_st(int kind, bool walls, int tx, int pf, const LatDesc* d, const WorkItem* items,
+                                 int n_items, int grid, int parity, hipStream_t s) {
+    return walls ? launch_step_kind<ST, true>(kind, tx, pf, d, items, n_items, grid, parity, s)
+                 : launch_step_kind<ST, false>(kind, tx, pf, d, items, n_items, grid, parity, s);
+}
+
+hipError_t launch_step(int prec, int kind, bool walls, int tx, int pf, const LatDesc* d, const WorkItem* items,
                        int n_items, int grid, int parity, hipStream_t s) {
     switch (prec) {
-    case LB_FP64: return launch_step_st<StF64>(kind, tx, pf, d, items, n_items, grid, parity, s);
-    case LB_FP32: return launch_step_st<StF32>(kind, tx, pf, d, items, n_items, grid, parity, s);
-    case LB_FP32_F16: return launch_step_st<StF16>(kind, tx, pf, d, items, n_items, grid, parity, s);
-    case LB_FP32_BF16: return launch_step_st<StBF16>(kind, tx, pf, d, items, n_items, grid, parity, s);
+    case LB_FP64: return launch_step_st<StF64>(kind, walls, tx, pf, d, items, n_items, grid, parity, s);
+    case LB_FP32: return launch_step_st<StF32>(kind, walls, tx, pf, d, items, n_items, grid, parity, s);
+    case LB_FP32_F16: return launch_step_st<StF16>(kind, walls, tx, pf, d, items, n_items, grid, parity, s);
+    case LB_FP32_BF16: return launch_step_st<StBF16>(kind, walls, tx, pf, d, items, n_items, grid, parity, s);
     }
     return hipErrorInvalidValue;
 }
@@ -103,50 +111,50 @@ static int occ_of(F kern, int tx) {
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, tx, 0) == hipSuccess ? nb : 1;
 }
 
-template <class ST, int TX>
+template <class ST, int TX, bool W>
 static int occ_kind(int kind, int pf) {
     switch (kind) {
     case KIND_COUPLED_CASCADED:
-        if (pf == PF_PREFETCH) return occ_of(lb_fused<ST, TX, MODE_STEP, PF_PREFETCH, COLL_CASCADED>, TX);
-        return occ_of(lb_fused<ST, TX, MODE_STEP, PF_HOLD, COLL_CASCADED>, TX);
-    case KIND_COUPLED_SRT: return occ_of(lb_fused<ST, TX, MODE_STEP, PF_HOLD, COLL_SRT>, TX);
-    case KIND_ACE_CASCADED: return occ_of(lb_ace<ST, TX, MODE_STEP, COLL_CASCADED>, TX);
-    case KIND_ACE_SRT: return occ_of(lb_ace<ST, TX, MODE_STEP, COLL_SRT>, TX);
+        if (pf == PF_PREFETCH) return occ_of(lb_fused<ST, TX, MODE_STEP, PF_PREFETCH, COLL_CASCADED, W>, TX);
+        return occ_of(lb_fused<ST, TX, MODE_STEP, PF_HOLD, COLL_CASCADED, W>, TX);
+    case KIND_COUPLED_SRT: return occ_of(lb_fused<ST, TX, MODE_STEP, PF_HOLD, COLL_SRT, W>, TX);
+    case KIND_ACE_CASCADED: return occ_of(lb_ace<ST, TX, MODE_STEP, COLL_CASCADED, W>, TX);
+    case KIND_ACE_SRT: return occ_of(lb_ace<ST, TX, MODE_STEP, COLL_SRT, W>, TX);
     }
     return 1;
 }
 
-template <class ST>
+template <class ST, bool W>
 static int occ_st(int kind, int tx, int pf) {
     switch (tx) {
-    case 64: return occ_kind<ST, 64>(kind, pf);
-    case 128: return occ_kind<ST, 128>(kind, pf);
-    case 256: return occ_kind<ST, 256>(kind, pf);
-    case 512: return occ_kind<ST, 512>(kind, pf);
-    case 132: return occ_kind<ST, 132>(kind, pf);
-    case 260: return occ_kind<ST, 260>(kind, pf);
-    case 452: return occ_kind<ST, 452>(kind, pf);
+    case 64: return occ_kind<ST, 64, W>(kind, pf);
+    case 128: return occ_kind<ST, 128, W>(kind, pf);
+    case 256: return occ_kind<ST, 256, W>(kind, pf);
+    case 512: return occ_kind<ST, 512, W>(kind, pf);
+    case 132: return occ_kind<ST, 132, W>(kind, pf);
+    case 260: return occ_kind<ST, 260, W>(kind, pf);
+    case 452: return occ_kind<ST, 452, W>(kind, pf);
     case 516:
         if constexpr (sizeof(typename ST::R) == 8) {
             if (pf == PF_PREFETCH) return 0;
             switch (kind) {
-            case KIND_COUPLED_CASCADED: return occ_of(lb_fused<ST, 516, MODE_STEP, PF_HOLD, COLL_CASCADED>, 516);
-            case KIND_COUPLED_SRT: return occ_of(lb_fused<ST, 516, MODE_STEP, PF_HOLD, COLL_SRT>, 516);
-            case KIND_ACE_CASCADED: return occ_of(lb_ace<ST, 516, MODE_STEP, COLL_CASCADED>, 516);
-            case KIND_ACE_SRT: return occ_of(lb_ace<ST, 516, MODE_STEP, COLL_SRT>, 516);
+            case KIND_COUPLED_CASCADED: return occ_of(lb_fused<ST, 516, MODE_STEP, PF_HOLD, COLL_CASCADED, W>, 516);
+            case KIND_COUPLED_SRT: return occ_of(lb_fused<ST, 516, MODE_STEP, PF_HOLD, COLL_SRT, W>, 516);
+            case KIND_ACE_CASCADED: return occ_of(lb_ace<ST, 516, MODE_STEP, COLL_CASCADED, W>, 516);
+            case KIND_ACE_SRT: return occ_of(lb_ace<ST, 516, MODE_STEP, COLL_SRT, W>, 516);
             }
             return 0;
         } else {
-            return occ_kind<ST, 516>(kind, pf);
+            return occ_kind<ST, 516, W>(kind, pf);
         }
     case 1024:
         if constexpr (sizeof(typename ST::R) == 4) {
             if (pf != PF_HOLD) return 0;
             switch (kind) {
-            case KIND_COUPLED_CASCADED: return occ_of(lb_fused<ST, 1024, MODE_STEP, PF_HOLD, COLL_CASCADED>, 1024);
-            case KIND_COUPLED_SRT: return occ_of(lb_fused<ST, 1024, MODE_STEP, PF_HOLD, COLL_SRT>, 1024);
-            case KIND_ACE_CASCADED: return occ_of(lb_ace<ST, 1024, MODE_STEP, COLL_CASCADED>, 1024);
-            case KIND_ACE_SRT: return occ_of(lb_ace<ST, 1024, MODE_STEP, COLL_SRT>, 1024);
+            case KIND_COUPLED_CASCADED: return occ_of(lb_fused<ST, 1024, MODE_STEP, PF_HOLD, COLL_CASCADED, W>, 1024);
+            case KIND_COUPLED_SRT: return occ_of(lb_fused<ST, 1024, MODE_STEP, PF_HOLD, COLL_SRT, W>, 1024);
+            case KIND_ACE_CASCADED: return occ_of(lb_ace<ST, 1024, MODE_STEP, COLL_CASCADED, W>, 1024);
+            case KIND_ACE_SRT: return occ_of(lb_ace<ST, 1024, MODE_STEP, COLL_SRT, W>, 1024);
             }
         }
         return 0;
@@ -154,14 +162,19 @@ static int occ_st(int kind, int tx, int pf) {
     return 1;
 }
 
-int step_occupancy(int prec, int kind, int tx, int pf) {
+template <bool W>
+static int step_occupancy_w(int prec, int kind, int tx, int pf) {
     switch (prec) {
-    case LB_FP64: return occ_st<StF64>(kind, tx, pf);
-    case LB_FP32: return occ_st<StF32>(kind, tx, pf);
-    case LB_FP32_F16: return occ_st<StF16>(kind, tx, pf);
-    case LB_FP32_BF16: return occ_st<StBF16>(kind, tx, pf);
+    case LB_FP64: return occ_st<StF64, W>(kind, tx, pf);
+    case LB_FP32: return occ_st<StF32, W>(kind, tx, pf);
+    case LB_FP32_F16: return occ_st<StF16, W>(kind, tx, pf);
+    case LB_FP32_BF16: return occ_st<StBF16, W>(kind, tx, pf);
     }
     return 1;
+}
+
+int step_occupancy(int prec, int kind, bool walls, int tx, int pf) {
+    return walls ? step_occupancy_w<true>(prec, kind, tx, pf) : step_occupancy_w<false>(prec, kind, tx, pf);
 }
 
 // Fields / coupling extraction always runs with 64-wide strips.  The coupled

@@ -83,3 +83,30 @@ def test_batch_rejects_when_full():
     with pytest.raises(lb.LBError) as e:
         B.add(*W.droplet(16, 4.0))  # no free slot
     assert e.value.code == lb.LB_E_WORKSPACE
+
+
+@pytest.mark.parametrize("prec", ["fp16", "fp64"])
+def test_batch_wall_kernels_follow_membership(prec):
+    """A batch of periodic lattices runs the kernels without wall logic; adding
+    a walled lattice switches to the general ones and removing it switches
+    back. Every lattice still evolves bit for bit as it would alone."""
+    per0, per1 = W.droplet(96, 20.0, ratio=100.0), W.droplet(64, 12.0, ratio=10.0, ny=100)
+    walled = W.random_case(130, 66, seed=7, bc_y="wall", gy=-1e-5)
+    print(f"[case] periodic/walled batch membership, {prec}", flush=True)
+    B = lb.Batch(4, 60000, prec)
+    s0, s1 = B.add(*per0), B.add(*per1)
+    B.step(10)
+    sw = B.add(*walled)
+    B.step(11, use_graph=False)
+    got_w = B.fields(sw)
+    B.remove(sw)
+    B.step(12)
+    for (c, p), s, n in [(per0, s0, 33), (per1, s1, 33)]:
+        L = lb.Lattice(c, p, prec)
+        L.step(n)
+        for u, v in zip(B.fields(s), L.fields()):
+            assert np.array_equal(u, v, equal_nan=True)
+    L = lb.Lattice(*walled, prec)
+    L.step(11)
+    for u, v in zip(got_w, L.fields()):
+        assert np.array_equal(u, v, equal_nan=True)
