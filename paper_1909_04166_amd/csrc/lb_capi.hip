@@ -489,6 +489,19 @@ std::vector<Sched> candidates(int prec, int nx, int ny, int kind) {
     return out;
 }
 
+// The finalists' times that lie within 1% of the fastest are taken as equal
+// (repeated timings of one schedule spread about that much); among those the
+// schedule with the fewest work items wins, as it re-reads the fewest halo rows.
+// This keeps the choice the same from run to run when schedules tie.
+Sched pick_final(const std::vector<std::pair<double, Sched>>& fin, const Sched& fallback) {
+    double best = 1e30;
+    for (const auto& f : fin) best = std::min(best, f.first);
+    const Sched* pick = nullptr;
+    for (const auto& f : fin)
+        if (f.first <= 1.01 * best && (!pick || f.second.n_items < pick->n_items)) pick = &f.second;
+    return pick ? *pick : fallback;
+}
+
 lb_status autotune_single(lb_handle* h) {
     const TuneKey key{h->cfg.precision, h->cfg.nx, h->cfg.ny, h->hdesc.wall_y, h->hdesc.wall_x,
                       h->cfg.st_form, h->kind, h->cfg.surf};
@@ -521,14 +534,14 @@ lb_status autotune_single(lb_handle* h) {
     }
     std::sort(scored.begin(), scored.end(),
               [](const std::pair<double, Sched>& a, const std::pair<double, Sched>& b) { return a.first < b.first; });
-    Sched best_sc = h->sc;
-    double best = 1e30;
+    std::vector<std::pair<double, Sched>> fin;
     for (size_t i = 0; i < scored.size() && i < 3; ++i) {
         double ms;
         const lb_status st = timed(scored[i].second, 4 * reps, &ms);
         if (st != LB_OK) return st;
-        if (ms < best) { best = ms; best_sc = scored[i].second; }
+        if (ms < 1e30) fin.push_back({ms, scored[i].second});
     }
+    const Sched best_sc = pick_final(fin, h->sc);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune[key] = best_sc;
@@ -1037,15 +1050,14 @@ lb_status batch_autotune(lb_batch* b) {
     }
     std::sort(scored.begin(), scored.end(),
               [](const std::pair<double, Sched>& x, const std::pair<double, Sched>& y) { return x.first < y.first; });
-    Sched best_sc = b->sc;
-    double best = 1e30;
+    std::vector<std::pair<double, Sched>> fin;
     for (size_t i = 0; i < scored.size() && i < 3; ++i) {
         double ms;
         const lb_status st = timed(scored[i].second, 12, &ms);
         if (st != LB_OK) return st;
-        if (ms < best) { best = ms; best_sc = scored[i].second; }
+        if (ms < 1e30) fin.push_back({ms, scored[i].second});
     }
-    return batch_set_sched(b, best_sc);
+    return batch_set_sched(b, pick_final(fin, b->sc));
 }
 
 lb_status batch_graph(lb_batch* b, int parity, hipGraphExec_t* out) {
