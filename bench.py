@@ -36,7 +36,7 @@ METRIC = "MLUPS (f+g per node-step) & % HBM roofline; p50/p99 solve latency batc
 # otherwise the roofline's traffic is null.
 KERNEL_SOURCES = ["paper_1909_04166_amd/csrc/lb_device.hpp", "paper_1909_04166_amd/csrc/lb_kernels.hip",
                   "paper_1909_04166_amd/csrc/lb_capi.hip", "paper_1909_04166_amd/csrc/lb_internal.hpp",
-                  "paper_1909_04166_amd/build.py"]
+                  "paper_1909_04166_amd/csrc/lb_sched.hpp", "paper_1909_04166_amd/build.py"]
 TRAFFIC = {
     "fingerprint": "eb585e95ec48330f",
     "workload": "tiled8192",

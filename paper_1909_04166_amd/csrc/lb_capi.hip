@@ -159,83 +159,6 @@ void fill_desc(const lb_config* c, LatDesc& D, void* b0, void* b1, int64_t plane
     D.ps_G = c->psi_G;
 }
 
-// Strip width of a TX-lane workgroup: two halo lanes on each side.
-inline int strip_w(int tx) { return tx - 4; }
-
-// Work items of one lattice: strips of tx - 4 columns, runs of th rows;
-// strip-major so that consecutive items are vertically adjacent (they share
-// halo rows).
-void build_items(int inst, int nx, int ny, int tx, int th, std::vector<WorkItem>& out) {
-    for (int x0 = 0; x0 < nx; x0 += strip_w(tx))
-        for (int y0 = 0; y0 < ny; y0 += th) out.push_back({inst, x0, y0, std::min(ny, y0 + th)});
-}
-
-struct LatShape {
-    int inst, nx, ny;
-};
-
-// Balanced persistent schedule: the rows of every strip of every lattice, in
-// order, are cut into G contiguous segments of nearly equal length; block b
-// runs segment b as the items at positions b, b + G, b + 2G, ... (padding
-// items are empty).  Returns false if more than max_items slots are needed.
-bool build_segments(const std::vector<LatShape>& lats, int tx, int G, int max_items,
-                    std::vector<WorkItem>& out, int* nblocks) {
-    *nblocks = 0;
-    struct Strip { int inst, x0, ny; };
-    std::vector<Strip> strips;
-    int64_t total = 0;
-    for (const auto& l : lats)
-        for (int x0 = 0; x0 < l.nx; x0 += strip_w(tx)) {
-            strips.push_back({l.inst, x0, l.ny});
-            total += l.ny;
-        }
-    if (total == 0 || G <= 0) { out.clear(); return true; }
-    const int64_t per = std::max<int64_t>(8, (total + G - 1) / G);
-    const int nb = (int)std::min<int64_t>(G, (total + per - 1) / per);
-    std::vector<std::vector<WorkItem>> blocks(nb);
-    int b = 0;
-    int64_t used = 0;
-    for (const auto& st : strips) {
-        int y = 0;
-        while (y < st.ny) {
-            const int take = (int)std::min<int64_t>(st.ny - y, per - used);
-            blocks[b].push_back({st.inst, st.x0, y, y + take});
-            y += take;
-            used += take;
-            if (used == per && b + 1 < nb) { ++b; used = 0; }
-        }
-    }
-    size_t maxj = 0;
-    for (auto& bl : blocks) maxj = std::max(maxj, bl.size());
-    if ((int64_t)maxj * nb > max_items) return false;
-    out.assign(maxj * nb, WorkItem{0, 0, 0, 0});
-    for (int i = 0; i < nb; ++i)
-        for (size_t j = 0; j < blocks[i].size(); ++j) out[j * nb + i] = blocks[i][j];
-    *nblocks = nb;
-    return true;
-}
-
-// Blocks are dispatched round-robin over the 8 XCDs (block b -> XCD b % 8).
-// Reorder each group of `grid` consecutive items so that the items one XCD
-// receives are consecutive in the original order (they share halo rows in the
-// XCD's L2).
-void xcd_permute(std::vector<WorkItem>& items, int grid) {
-    if (grid < 16 || grid % 8) return;
-    std::vector<WorkItem> out(items.size());
-    const size_t n = items.size();
-    for (size_t g0 = 0; g0 < n; g0 += grid) {
-        const size_t len = std::min<size_t>(grid, n - g0);
-        if (len < (size_t)grid) {
-            for (size_t i = 0; i < len; ++i) out[g0 + i] = items[g0 + i];
-            continue;
-        }
-        const size_t per = grid / 8;
-        for (size_t b = 0; b < len; ++b) out[g0 + b] = items[g0 + (b % 8) * per + b / 8];
-    }
-    items.swap(out);
-}
-
-constexpr int kMaxGrid = 16384;
 int max_items_for(int nx, int ny) {
     return ((nx + 59) / 60) * ((ny + kMinH - 1) / kMinH) + 3 * kMaxGrid;
 }
@@ -253,37 +176,10 @@ int cu_count() {
     return n;
 }
 
-// How a step is spread over workgroups.
-//   mode 0: one work item of th rows per workgroup, grid = number of items,
-//           items ordered so that each XCD gets vertically adjacent ones;
-//   mode 1: persistent grid of mult * (resident workgroups per CU) * CUs, each
-//           workgroup one balanced segment of the concatenated strip rows.
-struct Sched {
-    int tx = 64, th = 64, mode = 0, mult = 1, pf = 0;
-    int grid = 0, n_items = 0, rows = 0;
-};
-
 bool build_schedule(const std::vector<LatShape>& lats, int prec, int kind, bool walls, Sched& sc, int max_items,
                     std::vector<WorkItem>& items) {
-    items.clear();
-    if (sc.mode == 0) {
-        for (const auto& l : lats) build_items(l.inst, l.nx, l.ny, sc.tx, sc.th, items);
-        if ((int64_t)items.size() > max_items) return false;
-        sc.grid = (int)items.size();
-        sc.rows = sc.th;
-        xcd_permute(items, sc.grid);
-    } else {
-        int G = sc.mult * std::max(1, step_occupancy(prec, kind, walls, sc.tx, sc.pf)) * cu_count();
-        G = std::min(G, kMaxGrid);
-        int nb = 0;
-        if (!build_segments(lats, sc.tx, G, max_items, items, &nb)) return false;
-        sc.grid = nb;
-        int64_t total = 0;
-        for (const auto& l : lats) total += (int64_t)((l.nx + strip_w(sc.tx) - 1) / strip_w(sc.tx)) * l.ny;
-        sc.rows = nb ? (int)((total + nb - 1) / nb) : 0;
-    }
-    sc.n_items = (int)items.size();
-    return true;
+    const int resident = sc.mode == 0 ? 1 : step_occupancy(prec, kind, walls, sc.tx, sc.pf);
+    return plan_schedule(lats, resident, cu_count(), sc, max_items, items);
 }
 
 Sched default_sched(int nx, int ny) {
@@ -480,11 +376,12 @@ std::vector<Sched> candidates(int prec, int nx, int ny, int kind) {
                 sc.tx = tx; sc.th = th; sc.mode = 0; sc.pf = pf;
                 out.push_back(sc);
             }
-            for (int m : {1, 2}) {
-                Sched sc;
-                sc.tx = tx; sc.mode = 1; sc.mult = m; sc.pf = pf;
-                out.push_back(sc);
-            }
+            for (int mode : {1, 2})
+                for (int m : {1, 2}) {
+                    Sched sc;
+                    sc.tx = tx; sc.mode = mode; sc.mult = m; sc.pf = pf;
+                    out.push_back(sc);
+                }
         }
     return out;
 }
@@ -864,7 +761,7 @@ lb_status lb_get_schedule(lb_handle* h, int32_t* tile_x, int32_t* rows, int32_t*
     if (!h || !tile_x || !rows || !grid || !prefetch) return LB_E_INVALID_ARG;
     *tile_x = h->sc.tx;
     *rows = h->sc.rows;
-    *grid = h->sc.mode == 1 ? h->sc.grid : 0;
+    *grid = h->sc.mode != 0 ? h->sc.grid : 0;
     *prefetch = h->sc.pf;
     return LB_OK;
 }
@@ -1008,8 +905,15 @@ std::vector<LatShape> batch_shapes(lb_batch* b) {
 
 lb_status batch_set_sched(lb_batch* b, Sched sc) {
     std::vector<WorkItem> items;
-    if (!build_schedule(batch_shapes(b), b->prec, std::max(b->kind, 0), b->walls, sc, b->max_items, items))
-        return LB_E_WORKSPACE;
+    const std::vector<LatShape> lats = batch_shapes(b);
+    if (!build_schedule(lats, b->prec, std::max(b->kind, 0), b->walls, sc, b->max_items, items)) {
+        // the strip-aligned cut needs lattices of one height: once others have
+        // joined, the same grid is cut the general way
+        if (sc.mode != 2) return LB_E_WORKSPACE;
+        sc.mode = 1;
+        if (!build_schedule(lats, b->prec, std::max(b->kind, 0), b->walls, sc, b->max_items, items))
+            return LB_E_WORKSPACE;
+    }
     if (!items.empty())
         HIPC(hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(WorkItem),
                             hipMemcpyHostToDevice, b->s));
@@ -1350,7 +1254,7 @@ lb_status lb_batch_get_schedule(lb_batch* b, int32_t* tile_x, int32_t* rows, int
     if (!b || !tile_x || !rows || !grid || !prefetch) return LB_E_INVALID_ARG;
     *tile_x = b->sc.tx;
     *rows = b->sc.rows;
-    *grid = b->sc.mode == 1 ? b->sc.grid : 0;
+    *grid = b->sc.mode != 0 ? b->sc.grid : 0;
     *prefetch = b->sc.pf;
     return LB_OK;
 }

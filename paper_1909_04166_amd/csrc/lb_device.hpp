@@ -26,6 +26,8 @@
 
 #include <type_traits>
 
+#include "lb_sched.hpp"
+
 namespace cmlb {
 
 // ------------------------------------------------------------------ storage
@@ -99,12 +101,6 @@ struct alignas(16) LatDesc {
     double kt0, lbeta, ps_a, ps_G;  // Langmuir: kappa~ = kt0 (1 + lbeta ln(1 - psi)), psi = ps_a + ps_G y
 };
 
-struct WorkItem {
-    int32_t inst;  // index into the descriptor array
-    int32_t x0;    // first column of the strip
-    int32_t y0;    // first row collided
-    int32_t y1;    // one past the last row collided
-};
 
 enum { MODE_STEP = 0, MODE_FIELDS = 1, MODE_COUPLING = 2 };
 // Collision models of the coupled step: the cascaded pair, or the SRT pair of the
