@@ -388,14 +388,17 @@ std::vector<Sched> candidates(int prec, int nx, int ny, int kind) {
 
 // The finalists' times that lie within 1% of the fastest are taken as equal
 // (repeated timings of one schedule spread about that much); among those the
-// schedule with the fewest work items wins, as it re-reads the fewest halo rows.
-// This keeps the choice the same from run to run when schedules tie.
+// schedule with the fewest work items wins, as it re-reads the fewest halo rows,
+// then the one without prefetching, then the narrower workgroup, then the lower
+// mode and multiplier.  This keeps the choice the same from run to run when
+// schedules tie.
 Sched pick_final(const std::vector<std::pair<double, Sched>>& fin, const Sched& fallback) {
     double best = 1e30;
     for (const auto& f : fin) best = std::min(best, f.first);
+    auto key = [](const Sched& c) { return std::make_tuple(c.n_items, c.pf, c.tx, c.mode, c.mult, c.th); };
     const Sched* pick = nullptr;
     for (const auto& f : fin)
-        if (f.first <= 1.01 * best && (!pick || f.second.n_items < pick->n_items)) pick = &f.second;
+        if (f.first <= 1.01 * best && (!pick || key(f.second) < key(*pick))) pick = &f.second;
     return pick ? *pick : fallback;
 }
 
