@@ -146,6 +146,61 @@ __device__ __forceinline__ void sto(typename ST::T* plane, uint32_t e, typename 
     *(gmem_t<T>*)(p + e * (uint32_t)sizeof(T)) = ST::st(v);
 }
 
+// The step kernels move 16- and 32-bit stored values through buffer resources: a
+// descriptor in scalar registers holds the 64-bit base of one lattice row's block
+// of values, the lane adds a 32-bit byte offset (its column) and the instruction a
+// 32-bit uniform byte offset (the value's plane within the block, the same on
+// every row).  No address then takes 64-bit arithmetic per access, which matters
+// where the kernel is bound by instruction issue.  FP64 keeps global accesses
+// (a 64-bit scalar row base per access and a 32-bit lane offset): it waits on
+// memory, and with buffer accesses it ran 8% slower.
+template <class ST>
+constexpr bool kBufIO = sizeof(typename ST::T) < 8;
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+typedef uint32_t u32x2 __attribute__((__vector_size__(8)));
+__device__ __forceinline__ rsrc_t row_rsrc(const void* p) {
+    // raw buffer (stride 0), every 32-bit offset in range, 32-bit data format
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, -1, 0x00020000);
+}
+template <class ST, bool RAW = false>
+__device__ __forceinline__ std::conditional_t<RAW, typename ST::T, typename ST::R> ldb(rsrc_t r, uint32_t voff,
+                                                                                        uint32_t soff) {
+    using T = typename ST::T;
+    T v;
+    if constexpr (sizeof(T) == 2)
+        v = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0));
+    else if constexpr (sizeof(T) == 4)
+        v = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+    else
+        v = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+    if constexpr (RAW) return v; else return ST::ld(v);
+}
+template <class ST>
+__device__ __forceinline__ void stb(rsrc_t r, uint32_t voff, uint32_t soff, typename ST::R v) {
+    using T = typename ST::T;
+    const T s = ST::st(v);
+    if constexpr (sizeof(T) == 2)
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, s), r, (int)voff, (int)soff, 0);
+    else if constexpr (sizeof(T) == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, s), r, (int)voff, (int)soff, 0);
+    else
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, s), r, (int)voff, (int)soff, 0);
+}
+// Stores values first..first+n-1 of row block `row` at column col.
+template <class ST, int N>
+__device__ __forceinline__ void store_row(typename ST::T* row, int nx, int first, int col, const typename ST::R* v) {
+    using T = typename ST::T;
+    if constexpr (kBufIO<ST>) {
+        const rsrc_t R = row_rsrc(row);
+        const uint32_t P = (uint32_t)nx * (uint32_t)sizeof(T), b = (uint32_t)col * (uint32_t)sizeof(T);
+#pragma unroll
+        for (int a = 0; a < N; ++a) stb<ST>(R, b, (uint32_t)(first + a) * P, v[a]);
+    } else {
+#pragma unroll
+        for (int a = 0; a < N; ++a) sto<ST>(row + (first + a) * nx, (uint32_t)col, v[a]);
+    }
+}
+
 // Buffer layout: the 18 stored values of a lattice are row-interleaved, value q
 // (0..8 f, 9..17 gbar) of node (x, y) at element (18 y + q) nx + x.  The nine f
 // (or gbar) rows of one lattice row form one contiguous block, so a workgroup
@@ -176,19 +231,27 @@ __device__ __forceinline__ void pull9(const typename ST::T* __restrict__ base, i
     // that the nine loads issue together without branches.
     const T* sb = bot ? ro : rbp;
     const T* st = top ? ro : rtp;
-    const int p2 = bot ? 4 : 2, p5 = bot ? (slip ? 8 : 7) : 5, p6 = bot ? (slip ? 7 : 8) : 6;
-    const int p4 = top ? 2 : 4, p7 = top ? (slip ? 6 : 5) : 7, p8 = top ? (slip ? 5 : 6) : 8;
+    const uint32_t P = (uint32_t)nx * (uint32_t)sizeof(T);  // bytes between value planes
+    // value `plane` of row block `row` at column `col`
+    auto ld = [&](const T* row, uint32_t plane, int col) {
+        if constexpr (kBufIO<ST>)
+            return ldb<ST, RAW>(row_rsrc(row), (uint32_t)col * (uint32_t)sizeof(T), plane * P);
+        else
+            return ldo<ST, RAW>(row + (int)plane * nx, (uint32_t)col);
+    };
+    const uint32_t p2 = bot ? 4 : 2, p5 = bot ? (slip ? 8 : 7) : 5, p6 = bot ? (slip ? 7 : 8) : 6;
+    const uint32_t p4 = top ? 2 : 4, p7 = top ? (slip ? 6 : 5) : 7, p8 = top ? (slip ? 5 : 6) : 8;
     const int x5 = (bot && !slip) ? x : xm, x6 = (bot && !slip) ? x : xp;
     const int x7 = (top && !slip) ? x : xp, x8 = (top && !slip) ? x : xm;
-    out[0] = ldo<ST, RAW>(ro, x);
-    out[1] = ldo<ST, RAW>(ro + nx, xm);
-    out[3] = ldo<ST, RAW>(ro + 3 * nx, xp);
-    out[2] = ldo<ST, RAW>(sb + p2 * nx, x);
-    out[5] = ldo<ST, RAW>(sb + p5 * nx, x5);
-    out[6] = ldo<ST, RAW>(sb + p6 * nx, x6);
-    out[4] = ldo<ST, RAW>(st + p4 * nx, x);
-    out[7] = ldo<ST, RAW>(st + p7 * nx, x7);
-    out[8] = ldo<ST, RAW>(st + p8 * nx, x8);
+    out[0] = ld(ro, 0, x);
+    out[1] = ld(ro, 1, xm);
+    out[3] = ld(ro, 3, xp);
+    out[2] = ld(sb, p2, x);
+    out[5] = ld(sb, p5, x5);
+    out[6] = ld(sb, p6, x6);
+    out[4] = ld(st, p4, x);
+    out[7] = ld(st, p7, x7);
+    out[8] = ld(st, p8, x8);
     if (wallx) {
         // Lanes on the first or last column replace what arrived from beyond an x
         // wall: bounce-back (opposite direction, same node), or specular reflection
@@ -196,16 +259,25 @@ __device__ __forceinline__ void pull9(const typename ST::T* __restrict__ base, i
         // beyond an x and a y wall at once, bounce-back.
         const bool sx = wallx == WALL_SLIP;
         if (x == 0) {
-            out[1] = ldo<ST, RAW>(ro + 3 * nx, x);
-            out[5] = (sx && !bot) ? ldo<ST, RAW>(rbp + 6 * nx, x) : ldo<ST, RAW>(ro + 7 * nx, x);
-            out[8] = (sx && !top) ? ldo<ST, RAW>(rtp + 7 * nx, x) : ldo<ST, RAW>(ro + 6 * nx, x);
+            out[1] = ld(ro, 3, x);
+            out[5] = (sx && !bot) ? ld(rbp, 6, x) : ld(ro, 7, x);
+            out[8] = (sx && !top) ? ld(rtp, 7, x) : ld(ro, 6, x);
         }
         if (x == nx - 1) {
-            out[3] = ldo<ST, RAW>(ro + 1 * nx, x);
-            out[6] = (sx && !bot) ? ldo<ST, RAW>(rbp + 5 * nx, x) : ldo<ST, RAW>(ro + 8 * nx, x);
-            out[7] = (sx && !top) ? ldo<ST, RAW>(rtp + 8 * nx, x) : ldo<ST, RAW>(ro + 5 * nx, x);
+            out[3] = ld(ro, 1, x);
+            out[6] = (sx && !bot) ? ld(rbp, 5, x) : ld(ro, 8, x);
+            out[7] = (sx && !top) ? ld(rtp, 8, x) : ld(ro, 5, x);
         }
     }
+}
+
+// Marks the lane's column indices as redefined inside the row loop (an empty asm
+// statement: no instruction).  Otherwise the compiler hoists their widened byte
+// offsets out of the loop as 64-bit values and forms every address with a 64-bit
+// vector add; redefined in the loop, each access becomes a global load or store
+// with the 64-bit row base in scalar registers and a 32-bit lane offset.
+__device__ __forceinline__ void lane_columns_in_loop(int& xc, int& xm, int& xp) {
+    asm volatile("" : "+v"(xc), "+v"(xm), "+v"(xp));
 }
 
 // Column slot of a lane in a TX-lane workgroup: slots 0, 1 and TX-2, TX-1 hold the
@@ -584,9 +656,9 @@ lb_fused(const LatDesc* __restrict__ descs, const WorkItem* __restrict__ items, 
         const bool inF = t >= 2 && t < w + 2;    // collided cells
         // this lane's column: halo lanes wrap, or mirror across x walls (ghost
         // values); lanes past the strip are idle and park on column 0
-        const int xc = inA ? map_row(it.x0 - 2 + t, nx, wallx) : 0;
-        const int xm = xc == 0 ? nx - 1 : xc - 1;
-        const int xp = xc == nx - 1 ? 0 : xc + 1;
+        int xc = inA ? map_row(it.x0 - 2 + t, nx, wallx) : 0;
+        int xm = xc == 0 ? nx - 1 : xc - 1;
+        int xp = xc == nx - 1 ? 0 : xc + 1;
 
         R f0[9], f1[9], f2[9], g0[9], g1[9];
         T nf[9], ng[9];  // next rows' pulls in flight (PF_PREFETCH)
@@ -602,6 +674,7 @@ lb_fused(const LatDesc* __restrict__ descs, const WorkItem* __restrict__ items, 
         for (int k = 0; k < H + 4; ++k) {
             const int L = it.y0 - 2 + k;
             constexpr bool ahead = PF == PF_PREFETCH && MODE == MODE_STEP;
+            if constexpr (!kBufIO<ST>) lane_columns_in_loop(xc, xm, xp);
             if (ahead && k + 1 < H + 4) {  // the next iteration's pulls
                 if (inA) pull9<ST, true>(src, nx, ny, wall, wallx, xc, xm, xp, map_row(L + 1, ny, wall), nf);
                 if (k >= 2 && inB) pull9<ST, true>(srcg, nx, ny, wall, wallx, xc, xm, xp, map_row(L, ny, wall), ng);
@@ -679,18 +752,14 @@ lb_fused(const LatDesc* __restrict__ descs, const WorkItem* __restrict__ items, 
                         else
                             ace_collide<R, ST::shifted>(f2, in.phi, o.ux, o.uy, Mth * in.nx, Mth * in.ny, K.omphi,
                                                         K.shf);
-                        T* drow = dst + C * RS;
-#pragma unroll
-                        for (int a = 0; a < 9; ++a) sto<ST>(drow + a * nx, (uint32_t)xc, f2[a]);
+                        store_row<ST, 9>(dst + C * RS, nx, 0, xc, f2);
                     }
                     if (inF) {
                         if constexpr (COLL == COLL_SRT)
                             hydro_srt<R, ST::shifted>(g1, o, K.shg);
                         else
                             hydro_collide<R, ST::shifted>(g1, o, K.shg);
-                        T* drow = dst + C * RS + 9 * nx;
-#pragma unroll
-                        for (int a = 0; a < 9; ++a) sto<ST>(drow + a * nx, (uint32_t)xc, g1[a]);
+                        store_row<ST, 9>(dst + C * RS, nx, 9, xc, g1);
                     }
                 } else if constexpr (MODE == MODE_FIELDS) {
                     if (inF) {
@@ -766,9 +835,9 @@ __global__ void __launch_bounds__(TX) lb_ace(const LatDesc* __restrict__ descs,
         const int w = min(TX - 4, nx - it.x0);
         const bool inA = t < w + 4;
         const bool inF = t >= 2 && t < w + 2;
-        const int xc = inA ? map_row(it.x0 - 2 + t, nx, wallx) : 0;
-        const int xm = xc == 0 ? nx - 1 : xc - 1;
-        const int xp = xc == nx - 1 ? 0 : xc + 1;
+        int xc = inA ? map_row(it.x0 - 2 + t, nx, wallx) : 0;
+        int xm = xc == 0 ? nx - 1 : xc - 1;
+        int xp = xc == nx - 1 ? 0 : xc + 1;
 
         R f0[9], f1[9];
 #pragma unroll
@@ -776,6 +845,7 @@ __global__ void __launch_bounds__(TX) lb_ace(const LatDesc* __restrict__ descs,
         const int H = it.y1 - it.y0;
         for (int k = 0; k < H + 2; ++k) {
             const int L = it.y0 - 1 + k;
+            if constexpr (!kBufIO<ST>) lane_columns_in_loop(xc, xm, xp);
             if (inA) {
                 pull9<ST>(src, nx, ny, wall, wallx, xc, xm, xp, map_row(L, ny, wall), f0);
                 R ph = sum9(f0);
@@ -798,9 +868,7 @@ __global__ void __launch_bounds__(TX) lb_ace(const LatDesc* __restrict__ descs,
                         ace_srt<R, ST::shifted>(f1, phi, ux, uy, Mth * ix, Mth * iy, omphi, shf);
                     else
                         ace_collide<R, ST::shifted>(f1, phi, ux, uy, Mth * ix, Mth * iy, omphi, shf);
-                    T* drow = dst + C * RS;
-#pragma unroll
-                    for (int a = 0; a < 9; ++a) sto<ST>(drow + a * nx, (uint32_t)xc, f1[a]);
+                    store_row<ST, 9>(dst + C * RS, nx, 0, xc, f1);
                 } else {
                     double* F = D.fields;
                     const int64_t N = (int64_t)nx * ny;
