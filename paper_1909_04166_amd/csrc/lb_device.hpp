@@ -207,6 +207,12 @@ __device__ __forceinline__ void store_row(typename ST::T* row, int nx, int first
 // streams three blocks per row instead of eighteen scattered planes.  Row bases
 // are formed in 64-bit uniform arithmetic, lane offsets within a block in 32 bits.
 __device__ __forceinline__ int64_t row_stride(int nx) { return 18 * (int64_t)nx; }
+// Row block r (0 <= r < ny) of a buffer, with the element offset formed by one
+// 32 x 32 -> 64-bit multiply (18 nx fits 32 bits) instead of a 64 x 64 one.
+template <class T>
+__device__ __forceinline__ T* row_at(T* base, int r, int nx) {
+    return base + (uint64_t)(uint32_t)r * (uint32_t)row_stride(nx);
+}
 
 // Pull the nine stored values arriving at (x, r): f_a(x, r) = f~_a(x - e_a).  A source
 // beyond a halfway wall is replaced by the opposite direction at the same node
@@ -223,10 +229,9 @@ __device__ __forceinline__ void pull9(const typename ST::T* __restrict__ base, i
     const bool slip = wall == WALL_SLIP;
     const int rb = r == 0 ? ny - 1 : r - 1;
     const int rt = r == ny - 1 ? 0 : r + 1;
-    const int64_t RS = row_stride(nx);
-    const T* ro = base + r * RS;
-    const T* rbp = base + rb * RS;  // row below (periodic image)
-    const T* rtp = base + rt * RS;  // row above
+    const T* ro = row_at(base, r, nx);
+    const T* rbp = row_at(base, rb, nx);  // row below (periodic image)
+    const T* rtp = row_at(base, rt, nx);  // row above
     // Every source is selected (uniform value block and row, per-lane column) so
     // that the nine loads issue together without branches.
     const T* sb = bot ? ro : rbp;
@@ -649,7 +654,6 @@ lb_fused(const LatDesc* __restrict__ descs, const WorkItem* __restrict__ items, 
         const T* __restrict__ src = reinterpret_cast<const T*>(D.buf[parity]);
         T* __restrict__ dst = reinterpret_cast<T*>(D.buf[parity ^ 1]);
         const T* __restrict__ srcg = src + 9 * nx;  // gbar values of row 0
-        const int64_t RS = row_stride(nx);
         const int w = min(TX - 4, nx - it.x0);  // interior columns of this strip
         const bool inA = t < w + 4;              // phi cells
         const bool inB = t >= 1 && t < w + 3;    // pbar and normal cells
@@ -752,14 +756,14 @@ lb_fused(const LatDesc* __restrict__ descs, const WorkItem* __restrict__ items, 
                         else
                             ace_collide<R, ST::shifted>(f2, in.phi, o.ux, o.uy, Mth * in.nx, Mth * in.ny, K.omphi,
                                                         K.shf);
-                        store_row<ST, 9>(dst + C * RS, nx, 0, xc, f2);
+                        store_row<ST, 9>(row_at(dst, C, nx), nx, 0, xc, f2);
                     }
                     if (inF) {
                         if constexpr (COLL == COLL_SRT)
                             hydro_srt<R, ST::shifted>(g1, o, K.shg);
                         else
                             hydro_collide<R, ST::shifted>(g1, o, K.shg);
-                        store_row<ST, 9>(dst + C * RS, nx, 9, xc, g1);
+                        store_row<ST, 9>(row_at(dst, C, nx), nx, 9, xc, g1);
                     }
                 } else if constexpr (MODE == MODE_FIELDS) {
                     if (inF) {
@@ -827,7 +831,6 @@ __global__ void __launch_bounds__(TX) lb_ace(const LatDesc* __restrict__ descs,
         const int nx = D.nx, ny = D.ny;
         const int wall = WALLS ? D.wall_y : WALL_NONE, wallx = WALLS ? D.wall_x : WALL_NONE;
         const int64_t P = D.plane;  // stride of the two velocity planes
-        const int64_t RS = row_stride(nx);
         const R shf = R(D.shift_f), four_W = R(D.four_W), Mm = R(D.M), omphi = R(D.omphi);
         const T* __restrict__ src = reinterpret_cast<const T*>(D.buf[parity]);
         T* __restrict__ dst = reinterpret_cast<T*>(D.buf[parity ^ 1]);
@@ -868,7 +871,7 @@ __global__ void __launch_bounds__(TX) lb_ace(const LatDesc* __restrict__ descs,
                         ace_srt<R, ST::shifted>(f1, phi, ux, uy, Mth * ix, Mth * iy, omphi, shf);
                     else
                         ace_collide<R, ST::shifted>(f1, phi, ux, uy, Mth * ix, Mth * iy, omphi, shf);
-                    store_row<ST, 9>(dst + C * RS, nx, 0, xc, f1);
+                    store_row<ST, 9>(row_at(dst, C, nx), nx, 0, xc, f1);
                 } else {
                     double* F = D.fields;
                     const int64_t N = (int64_t)nx * ny;
