@@ -151,11 +151,15 @@ __device__ __forceinline__ void sto(typename ST::T* plane, uint32_t e, typename 
 // of values, the lane adds a 32-bit byte offset (its column) and the instruction a
 // 32-bit uniform byte offset (the value's plane within the block, the same on
 // every row).  No address then takes 64-bit arithmetic per access, which matters
-// where the kernel is bound by instruction issue.  FP64 keeps global accesses
-// (a 64-bit scalar row base per access and a 32-bit lane offset): it waits on
-// memory, and with buffer accesses it ran 8% slower.
+// where the kernel is bound by instruction issue.  Kernels that wait on memory
+// keep global accesses (a 64-bit scalar row base per access and a 32-bit lane
+// offset): with buffer accesses the FP64 pair ran 8% slower and the FP32 phase
+// field alone 4% slower.  kBufIO: the coupled pair in 16- and 32-bit storage;
+// kBufIOAce: the phase field alone in 16-bit storage.
 template <class ST>
 constexpr bool kBufIO = sizeof(typename ST::T) < 8;
+template <class ST>
+constexpr bool kBufIOAce = sizeof(typename ST::T) < 4;
 using rsrc_t = __amdgpu_buffer_rsrc_t;
 typedef uint32_t u32x2 __attribute__((__vector_size__(8)));
 __device__ __forceinline__ rsrc_t row_rsrc(const void* p) {
@@ -187,10 +191,10 @@ __device__ __forceinline__ void stb(rsrc_t r, uint32_t voff, uint32_t soff, type
         __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, s), r, (int)voff, (int)soff, 0);
 }
 // Stores values first..first+n-1 of row block `row` at column col.
-template <class ST, int N>
+template <class ST, int N, bool BUF>
 __device__ __forceinline__ void store_row(typename ST::T* row, int nx, int first, int col, const typename ST::R* v) {
     using T = typename ST::T;
-    if constexpr (kBufIO<ST>) {
+    if constexpr (BUF) {
         const rsrc_t R = row_rsrc(row);
         const uint32_t P = (uint32_t)nx * (uint32_t)sizeof(T), b = (uint32_t)col * (uint32_t)sizeof(T);
 #pragma unroll
@@ -218,8 +222,8 @@ __device__ __forceinline__ T* row_at(T* base, int r, int nx) {
 // beyond a halfway wall is replaced by the opposite direction at the same node
 // (bounce-back), or by the y-mirrored direction at the node the particle left,
 // x - e_ax (specular reflection).  base points at value 0 of row 0 of the group
-// (f or gbar); xm, xp are the periodic neighbours of x.
-template <class ST, bool RAW = false>
+// (f or gbar); xm, xp are the periodic neighbours of x.  BUF: buffer accesses.
+template <class ST, bool BUF, bool RAW = false>
 __device__ __forceinline__ void pull9(const typename ST::T* __restrict__ base, int nx, int ny,
                                       int wall, int wallx, int x, int xm, int xp, int r,
                                       std::conditional_t<RAW, typename ST::T, typename ST::R> out[9]) {
@@ -239,7 +243,7 @@ __device__ __forceinline__ void pull9(const typename ST::T* __restrict__ base, i
     const uint32_t P = (uint32_t)nx * (uint32_t)sizeof(T);  // bytes between value planes
     // value `plane` of row block `row` at column `col`
     auto ld = [&](const T* row, uint32_t plane, int col) {
-        if constexpr (kBufIO<ST>)
+        if constexpr (BUF)
             return ldb<ST, RAW>(row_rsrc(row), (uint32_t)col * (uint32_t)sizeof(T), plane * P);
         else
             return ldo<ST, RAW>(row + (int)plane * nx, (uint32_t)col);
@@ -680,12 +684,12 @@ lb_fused(const LatDesc* __restrict__ descs, const WorkItem* __restrict__ items, 
             constexpr bool ahead = PF == PF_PREFETCH && MODE == MODE_STEP;
             if constexpr (!kBufIO<ST>) lane_columns_in_loop(xc, xm, xp);
             if (ahead && k + 1 < H + 4) {  // the next iteration's pulls
-                if (inA) pull9<ST, true>(src, nx, ny, wall, wallx, xc, xm, xp, map_row(L + 1, ny, wall), nf);
-                if (k >= 2 && inB) pull9<ST, true>(srcg, nx, ny, wall, wallx, xc, xm, xp, map_row(L, ny, wall), ng);
+                if (inA) pull9<ST, kBufIO<ST>, true>(src, nx, ny, wall, wallx, xc, xm, xp, map_row(L + 1, ny, wall), nf);
+                if (k >= 2 && inB) pull9<ST, kBufIO<ST>, true>(srcg, nx, ny, wall, wallx, xc, xm, xp, map_row(L, ny, wall), ng);
             }
             // ---- A: phi at the leading row
             if (inA) {
-                if (!ahead || k == 0) pull9<ST>(src, nx, ny, wall, wallx, xc, xm, xp, map_row(L, ny, wall), f0);
+                if (!ahead || k == 0) pull9<ST, kBufIO<ST>>(src, nx, ny, wall, wallx, xc, xm, xp, map_row(L, ny, wall), f0);
                 R ph = sum9(f0);
                 if constexpr (ST::shifted) ph += K.shf;
                 s_phi[L & 3][t] = ph;
@@ -693,7 +697,7 @@ lb_fused(const LatDesc* __restrict__ descs, const WorkItem* __restrict__ items, 
             // ---- B: pbar one row behind
             if (k >= 2 && inB) {
                 const int Lg = L - 1;
-                if (!ahead || k == 2) pull9<ST>(srcg, nx, ny, wall, wallx, xc, xm, xp, map_row(Lg, ny, wall), g0);
+                if (!ahead || k == 2) pull9<ST, kBufIO<ST>>(srcg, nx, ny, wall, wallx, xc, xm, xp, map_row(Lg, ny, wall), g0);
                 R pb = sum9(g0);
                 if constexpr (ST::shifted) pb += K.shg;
                 s_pb[Lg & 3][t] = pb;
@@ -756,14 +760,14 @@ lb_fused(const LatDesc* __restrict__ descs, const WorkItem* __restrict__ items, 
                         else
                             ace_collide<R, ST::shifted>(f2, in.phi, o.ux, o.uy, Mth * in.nx, Mth * in.ny, K.omphi,
                                                         K.shf);
-                        store_row<ST, 9>(row_at(dst, C, nx), nx, 0, xc, f2);
+                        store_row<ST, 9, kBufIO<ST>>(row_at(dst, C, nx), nx, 0, xc, f2);
                     }
                     if (inF) {
                         if constexpr (COLL == COLL_SRT)
                             hydro_srt<R, ST::shifted>(g1, o, K.shg);
                         else
                             hydro_collide<R, ST::shifted>(g1, o, K.shg);
-                        store_row<ST, 9>(row_at(dst, C, nx), nx, 9, xc, g1);
+                        store_row<ST, 9, kBufIO<ST>>(row_at(dst, C, nx), nx, 9, xc, g1);
                     }
                 } else if constexpr (MODE == MODE_FIELDS) {
                     if (inF) {
@@ -848,9 +852,9 @@ __global__ void __launch_bounds__(TX) lb_ace(const LatDesc* __restrict__ descs,
         const int H = it.y1 - it.y0;
         for (int k = 0; k < H + 2; ++k) {
             const int L = it.y0 - 1 + k;
-            if constexpr (!kBufIO<ST>) lane_columns_in_loop(xc, xm, xp);
+            if constexpr (!kBufIOAce<ST>) lane_columns_in_loop(xc, xm, xp);
             if (inA) {
-                pull9<ST>(src, nx, ny, wall, wallx, xc, xm, xp, map_row(L, ny, wall), f0);
+                pull9<ST, kBufIOAce<ST>>(src, nx, ny, wall, wallx, xc, xm, xp, map_row(L, ny, wall), f0);
                 R ph = sum9(f0);
                 if constexpr (ST::shifted) ph += shf;
                 s_phi[L & 3][t] = ph;
@@ -871,7 +875,7 @@ __global__ void __launch_bounds__(TX) lb_ace(const LatDesc* __restrict__ descs,
                         ace_srt<R, ST::shifted>(f1, phi, ux, uy, Mth * ix, Mth * iy, omphi, shf);
                     else
                         ace_collide<R, ST::shifted>(f1, phi, ux, uy, Mth * ix, Mth * iy, omphi, shf);
-                    store_row<ST, 9>(row_at(dst, C, nx), nx, 0, xc, f1);
+                    store_row<ST, 9, kBufIOAce<ST>>(row_at(dst, C, nx), nx, 0, xc, f1);
                 } else {
                     double* F = D.fields;
                     const int64_t N = (int64_t)nx * ny;
