@@ -636,15 +636,23 @@ constexpr int fused_waves() {
 // The wall kinds are then compile-time zero and the source selection of every
 // pull reduces to the periodic rows; this removes about 45% of the loop's scalar
 // and 5-15% of its vector instructions, which the 16-bit kernels feel (+12%).
+template <int N>
+using IC = std::integral_constant<int, N>;
+
 template <class ST, int TX, int MODE, int PF, int COLL = COLL_CASCADED, bool WALLS = true>
 __global__ void __launch_bounds__(TX) __attribute__((amdgpu_waves_per_eu(fused_waves<ST, PF, COLL>())))
 lb_fused(const LatDesc* __restrict__ descs, const WorkItem* __restrict__ items, int n_items, int parity) {
     using R = typename ST::R;
     using T = typename ST::T;
-    __shared__ R s_phi[4][TX];
-    __shared__ R s_pb[4][TX];
-    __shared__ R s_na[4][TX];  // n_x (geometric) or mu_phi (chemical potential)
-    __shared__ R s_nb[4][TX];  // n_y (geometric)
+    // Role-based register pipeline (see below): the coupled cascaded step with 16-
+    // or 32-bit storage, without prefetching.  Elsewhere (FP64, which waits on
+    // memory; the prefetching and SRT kernels, which would spill) it is not used.
+    constexpr bool kRoles = MODE == MODE_STEP && PF == PF_HOLD && COLL == COLL_CASCADED && sizeof(T) < 8;
+    constexpr int RING = kRoles ? 6 : 4;  // rows held in each LDS ring
+    __shared__ R s_phi[RING][TX];
+    __shared__ R s_pb[RING][TX];
+    __shared__ R s_na[RING][TX];  // n_x (geometric) or mu_phi (chemical potential)
+    __shared__ R s_nb[RING][TX];  // n_y (geometric)
     const int t = lane_slot<TX>(threadIdx.x);  // column slot of this lane
 
     for (int wi = blockIdx.x; wi < n_items; wi += gridDim.x) {
@@ -668,20 +676,39 @@ lb_fused(const LatDesc* __restrict__ descs, const WorkItem* __restrict__ items, 
         int xm = xc == 0 ? nx - 1 : xc - 1;
         int xp = xc == nx - 1 ? 0 : xc + 1;
 
-        R f0[9], f1[9], f2[9], g0[9], g1[9];
+        // Register pipeline: the f pulled at the leading row is collided two
+        // iterations later, the gbar one iteration later, and the gradient and
+        // normal found for row L - 1 serve its collision in the next iteration.
+        // By copies: F[0], G[0] and entry 0 take the new values, and each
+        // iteration ends by shifting F[0] -> F[1] -> F[2], G[0] -> G[1] and entry
+        // 0 -> 1.  By roles (kRoles): the values stay where they were written,
+        // in F[k % 3], G[k % 2] and entry k % 2, the rings hold the row leading in
+        // iteration k in slot k % 6, and the loop is unrolled six times so that
+        // every role and slot is a constant: nothing is moved between iterations.
+        R F[3][9], G[2][9];
         T nf[9], ng[9];  // next rows' pulls in flight (PF_PREFETCH)
-        R cdx = 0, cdy = 0, cm2 = 0, cnx = 0, cny = 0;  // grad / normal at row L-1
-        R pdx = 0, pdy = 0, pm2 = 0, pnx = 0, pny = 0;  // the same one row below
+        R Dx[2], Dy[2], Dm[2], Nx[2], Ny[2];  // grad phi, |grad phi|^2, normal
 #pragma unroll
         for (int a = 0; a < 9; ++a) {
-            f0[a] = f1[a] = f2[a] = g0[a] = g1[a] = R(0);
+            F[0][a] = F[1][a] = F[2][a] = G[0][a] = G[1][a] = R(0);
             nf[a] = ng[a] = T(0);
         }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) Dx[j] = Dy[j] = Dm[j] = Nx[j] = Ny[j] = R(0);
 
         const int H = it.y1 - it.y0;
-        for (int k = 0; k < H + 4; ++k) {
+        constexpr bool ahead = PF == PF_PREFETCH && MODE == MODE_STEP;
+        // One row iteration.  S0..S3: ring slots of rows L, L - 1, L - 2, L - 3;
+        // fo, ft: F entries of the f pulled now and two iterations ago; go, gt: G
+        // entries of the gbar pulled now and one iteration ago; dw, dr: entries of
+        // the gradient found now and one iteration ago.
+        auto row_step = [&](const int k, auto S0, auto S1, auto S2, auto S3, auto fo, auto ft, auto go, auto gt,
+                            auto dw, auto dr) __attribute__((always_inline)) {
+            R* const f0 = F[fo];
+            R* const f2 = F[ft];
+            R* const g0 = G[go];
+            R* const g1 = G[gt];
             const int L = it.y0 - 2 + k;
-            constexpr bool ahead = PF == PF_PREFETCH && MODE == MODE_STEP;
             if constexpr (!kBufIO<ST>) lane_columns_in_loop(xc, xm, xp);
             if (ahead && k + 1 < H + 4) {  // the next iteration's pulls
                 if (inA) pull9<ST, kBufIO<ST>, true>(src, nx, ny, wall, wallx, xc, xm, xp, map_row(L + 1, ny, wall), nf);
@@ -692,7 +719,7 @@ lb_fused(const LatDesc* __restrict__ descs, const WorkItem* __restrict__ items, 
                 if (!ahead || k == 0) pull9<ST, kBufIO<ST>>(src, nx, ny, wall, wallx, xc, xm, xp, map_row(L, ny, wall), f0);
                 R ph = sum9(f0);
                 if constexpr (ST::shifted) ph += K.shf;
-                s_phi[L & 3][t] = ph;
+                s_phi[S0][t] = ph;
             }
             // ---- B: pbar one row behind
             if (k >= 2 && inB) {
@@ -700,15 +727,15 @@ lb_fused(const LatDesc* __restrict__ descs, const WorkItem* __restrict__ items, 
                 if (!ahead || k == 2) pull9<ST, kBufIO<ST>>(srcg, nx, ny, wall, wallx, xc, xm, xp, map_row(Lg, ny, wall), g0);
                 R pb = sum9(g0);
                 if constexpr (ST::shifted) pb += K.shg;
-                s_pb[Lg & 3][t] = pb;
+                s_pb[S1][t] = pb;
             }
             __syncthreads();
             // ---- D: gradient, normal or chemical potential at row L-1
             if (k >= 2 && inB) {
                 const int Ln = L - 1;
-                const R* rs = s_phi[(Ln - 1) & 3];
-                const R* rm = s_phi[Ln & 3];
-                const R* rn = s_phi[(Ln + 1) & 3];
+                const R* rs = s_phi[S2];
+                const R* rm = s_phi[S1];
+                const R* rn = s_phi[S0];
                 R gx, gy;
                 grad3x3(rs, rm, rn, t, gx, gy);
                 const R m2 = gx * gx + gy * gy;
@@ -719,13 +746,13 @@ lb_fused(const LatDesc* __restrict__ descs, const WorkItem* __restrict__ items, 
                     const R ph = rm[t];
                     const R beta = K.be_a + K.be_b * yrow;
                     const R kap = K.ka_a + K.ka_b * yrow;
-                    s_na[Ln & 3][t] = R(4) * beta * (ph - R(1)) * ph * (ph - R(0.5)) -
+                    s_na[S1][t] = R(4) * beta * (ph - R(1)) * ph * (ph - R(0.5)) -
                                       kap * lap3x3(rs, rm, rn, t);
                 } else {
-                    s_na[Ln & 3][t] = ix;
-                    s_nb[Ln & 3][t] = iy;
+                    s_na[S1][t] = ix;
+                    s_nb[S1][t] = iy;
                 }
-                cdx = gx; cdy = gy; cm2 = m2; cnx = ix; cny = iy;
+                Dx[dw] = gx; Dy[dw] = gy; Dm[dw] = m2; Nx[dw] = ix; Ny[dw] = iy;
             }
             __syncthreads();
             // ---- F: collide row C = L - 2
@@ -735,18 +762,18 @@ lb_fused(const LatDesc* __restrict__ descs, const WorkItem* __restrict__ items, 
                 NodeOut<R> o;
                 uint32_t idx = 0;
                 if (inF) {
-                    in.phi = s_phi[C & 3][t];
-                    in.pbar = s_pb[C & 3][t];
-                    in.dphx = pdx; in.dphy = pdy; in.m2 = pm2; in.nx = pnx; in.ny = pny;
+                    in.phi = s_phi[S2][t];
+                    in.pbar = s_pb[S2][t];
+                    in.dphx = Dx[dr]; in.dphy = Dy[dr]; in.m2 = Dm[dr]; in.nx = Nx[dr]; in.ny = Ny[dr];
                     row_kappa(K, ktab, ny, C, in.kt, in.dkt);
                     in.divn = R(0); in.dmux = R(0); in.dmuy = R(0);
-                    grad3x3(s_pb[(C - 1) & 3], s_pb[C & 3], s_pb[(C + 1) & 3], t, in.dpx, in.dpy);
+                    grad3x3(s_pb[S3], s_pb[S2], s_pb[S1], t, in.dpx, in.dpy);
                     if (chem) {
-                        grad3x3(s_na[(C - 1) & 3], s_na[C & 3], s_na[(C + 1) & 3], t, in.dmux, in.dmuy);
+                        grad3x3(s_na[S3], s_na[S2], s_na[S1], t, in.dmux, in.dmuy);
                     } else {
                         R a1, a2, b1, b2;
-                        grad3x3(s_na[(C - 1) & 3], s_na[C & 3], s_na[(C + 1) & 3], t, a1, a2);
-                        grad3x3(s_nb[(C - 1) & 3], s_nb[C & 3], s_nb[(C + 1) & 3], t, b1, b2);
+                        grad3x3(s_na[S3], s_na[S2], s_na[S1], t, a1, a2);
+                        grad3x3(s_nb[S3], s_nb[S2], s_nb[S1], t, b1, b2);
                         in.divn = a1 + b2;
                     }
                     o = node_macro<R>(K, chem, in, g1);
@@ -794,18 +821,40 @@ lb_fused(const LatDesc* __restrict__ descs, const WorkItem* __restrict__ items, 
                     }
                 }
             }
-            // ---- rotate the register pipeline
-#pragma unroll
-            for (int a = 0; a < 9; ++a) {
-                f2[a] = f1[a];
-                f1[a] = f0[a];
-                g1[a] = g0[a];
-                if constexpr (ahead) {
-                    f0[a] = ST::ld(nf[a]);
-                    g0[a] = ST::ld(ng[a]);
-                }
+        };
+        if constexpr (kRoles) {
+            // slots and roles of iteration k = k0 + PH
+            auto phase = [&](auto Pc, const int k) __attribute__((always_inline)) {
+                constexpr int PH = decltype(Pc)::value;
+                row_step(k, IC<PH>{}, IC<(PH + 5) % 6>{}, IC<(PH + 4) % 6>{}, IC<(PH + 3) % 6>{}, IC<PH % 3>{},
+                         IC<(PH + 1) % 3>{}, IC<PH % 2>{}, IC<(PH + 1) % 2>{}, IC<PH % 2>{}, IC<(PH + 1) % 2>{});
+            };
+            for (int k0 = 0; k0 < H + 4; k0 += 6) {
+                phase(IC<0>{}, k0);
+                if (k0 + 1 < H + 4) phase(IC<1>{}, k0 + 1);
+                if (k0 + 2 < H + 4) phase(IC<2>{}, k0 + 2);
+                if (k0 + 3 < H + 4) phase(IC<3>{}, k0 + 3);
+                if (k0 + 4 < H + 4) phase(IC<4>{}, k0 + 4);
+                if (k0 + 5 < H + 4) phase(IC<5>{}, k0 + 5);
             }
-            pdx = cdx; pdy = cdy; pm2 = cm2; pnx = cnx; pny = cny;
+        } else {
+            for (int k = 0; k < H + 4; ++k) {
+                const int L = it.y0 - 2 + k;
+                row_step(k, L & 3, (L - 1) & 3, (L - 2) & 3, (L - 3) & 3, IC<0>{}, IC<2>{}, IC<0>{}, IC<1>{}, IC<0>{},
+                         IC<1>{});
+                // ---- shift the register pipeline
+#pragma unroll
+                for (int a = 0; a < 9; ++a) {
+                    F[2][a] = F[1][a];
+                    F[1][a] = F[0][a];
+                    G[1][a] = G[0][a];
+                    if constexpr (ahead) {
+                        F[0][a] = ST::ld(nf[a]);
+                        G[0][a] = ST::ld(ng[a]);
+                    }
+                }
+                Dx[1] = Dx[0]; Dy[1] = Dy[0]; Dm[1] = Dm[0]; Nx[1] = Nx[0]; Ny[1] = Ny[0];
+            }
         }
         __syncthreads();  // the rings are reused by the next work item
     }
