@@ -252,6 +252,16 @@ lb_status lb_timing_read(lb_handle* h, double* ms_per_step, int64_t* steps);
 lb_status lb_batch_timing_enable(lb_batch* b, int32_t on);
 lb_status lb_batch_timing_read(lb_batch* b, double* ms_per_step, int64_t* steps);
 
+/* Pins the handle's schedule; later steps skip the autotuner.  tile_x as in
+ * lb_config; mode 0: work items of `param` rows (>= 8), one per workgroup;
+ * mode 1: persistent grid of param (1..4) x resident workgroups per CU x CUs,
+ * each workgroup one balanced run of the concatenated strip rows; mode 2: as 1,
+ * the grid cut down to strips x bands (bands a multiple of 8) so that every
+ * strip is cut at the same rows and the same rows of neighbouring strips run on
+ * one XCD.  prefetch as lb_config.tile_pf.  The step results do not depend on the
+ * schedule (bit for bit).  Returns LB_E_INVALID_ARG for an invalid value or a
+ * cut that does not apply to the lattice (too few rows for the bands). */
+lb_status lb_set_schedule(lb_handle* h, int32_t tile_x, int32_t mode, int32_t param, int32_t prefetch);
 /* Schedule chosen for the handle (after autotuning when tile_x/tile_h were 0):
  * workgroup width tile_x (lanes; the strip is tile_x - 4 columns), rows per work
  * item (or per persistent segment), the persistent grid size (0 when every work

@@ -759,6 +759,22 @@ lb_status lb_timing_read(lb_handle* h, double* ms_per_step, int64_t* steps) {
     return LB_OK;
 }
 
+lb_status lb_set_schedule(lb_handle* h, int32_t tile_x, int32_t mode, int32_t param, int32_t prefetch) {
+    if (!h || mode < 0 || mode > 2 || prefetch < 0 || prefetch > 1) return LB_E_INVALID_ARG;
+    if (!valid_width(tile_x, h->cfg.precision, prefetch)) return LB_E_INVALID_ARG;
+    if (prefetch && h->kind != KIND_COUPLED_CASCADED) return LB_E_INVALID_ARG;
+    if (mode == 0 ? param < kMinH : (param < 1 || param > 4)) return LB_E_INVALID_ARG;
+    Sched sc;
+    sc.tx = tile_x;
+    sc.mode = mode;
+    sc.pf = prefetch;
+    if (mode == 0) sc.th = param; else sc.mult = param;
+    HIPC(hipStreamSynchronize(h->s));
+    const lb_status st = set_sched(h, sc);  // LB_E_INVALID_ARG if the cut does not apply
+    if (st == LB_OK) h->tuned = true;
+    return st;
+}
+
 lb_status lb_get_schedule(lb_handle* h, int32_t* tile_x, int32_t* rows, int32_t* grid,
                           int32_t* prefetch) {
     if (!h || !tile_x || !rows || !grid || !prefetch) return LB_E_INVALID_ARG;

@@ -106,6 +106,7 @@ _SIGS = {
     "lb_batch_timing_enable": ([_vp, ctypes.c_int32], ctypes.c_int32),
     "lb_batch_timing_read": ([_vp, _dp, _i64p], ctypes.c_int32),
     "lb_get_schedule": ([_vp, _i32p, _i32p, _i32p, _i32p], ctypes.c_int32),
+    "lb_set_schedule": ([_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32], ctypes.c_int32),
     "lb_batch_get_schedule": ([_vp, _i32p, _i32p, _i32p, _i32p], ctypes.c_int32),
     "lb_struct_sizes": ([_u64p, _u64p], ctypes.c_int32),
     "lb_copy_kernel": ([_vp, _vp, ctypes.c_uint64, _vp], ctypes.c_int32),
@@ -283,6 +284,13 @@ def lb_get_schedule(h: int) -> tuple[int, int, int, int]:
     return int(a.value), int(b.value), int(c.value), int(d.value)
 
 
+def lb_set_schedule(h: int, tile_x: int, mode: int, param: int, prefetch: int = 0) -> None:
+    """Pin the schedule: mode 0 items of `param` rows; modes 1 and 2 persistent
+    grids of `param` x resident workgroups per CU x CUs (balanced runs of strip
+    rows; strip-aligned bands)."""
+    _check("lb_set_schedule", lib().lb_set_schedule(_vp(h), int(tile_x), int(mode), int(param), int(prefetch)))
+
+
 def lb_batch_get_schedule(b: int) -> tuple[int, int, int, int]:
     """(workgroup width, rows per segment, persistent grid or 0, prefetch) of a batch."""
     a, r, g, p = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
@@ -447,6 +455,9 @@ class Lattice:
     @property
     def tile(self):
         return lb_get_schedule(self.h)
+
+    def set_schedule(self, tile_x: int, mode: int, param: int, prefetch: int = 0) -> None:
+        lb_set_schedule(self.h, tile_x, mode, param, prefetch)
 
 
 class Batch:

@@ -170,3 +170,4 @@ def test_max_items_enforced(planner):
     lats = [(0, 8192, 8192)]
     assert not planner(0, 64, lats, th=8, max_items=1000)["ok"]
     assert planner(0, 64, lats, th=8)["ok"]
+
