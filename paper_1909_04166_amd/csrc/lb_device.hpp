@@ -236,8 +236,8 @@ __device__ __forceinline__ void pull9(const typename ST::T* __restrict__ base, i
     const T* ro = row_at(base, r, nx);
     const T* rbp = row_at(base, rb, nx);  // row below (periodic image)
     const T* rtp = row_at(base, rt, nx);  // row above
-    // Every source is selected (uniform value block and row, per-lane column) so
-    // that the nine loads issue together without branches.
+    // On the rows next to a y wall every source is selected (uniform value block
+    // and row, per-lane column), so that the nine loads issue together.
     const T* sb = bot ? ro : rbp;
     const T* st = top ? ro : rtp;
     const uint32_t P = (uint32_t)nx * (uint32_t)sizeof(T);  // bytes between value planes
@@ -248,19 +248,29 @@ __device__ __forceinline__ void pull9(const typename ST::T* __restrict__ base, i
         else
             return ldo<ST, RAW>(row + (int)plane * nx, (uint32_t)col);
     };
-    const uint32_t p2 = bot ? 4 : 2, p5 = bot ? (slip ? 8 : 7) : 5, p6 = bot ? (slip ? 7 : 8) : 6;
-    const uint32_t p4 = top ? 2 : 4, p7 = top ? (slip ? 6 : 5) : 7, p8 = top ? (slip ? 5 : 6) : 8;
-    const int x5 = (bot && !slip) ? x : xm, x6 = (bot && !slip) ? x : xp;
-    const int x7 = (top && !slip) ? x : xp, x8 = (top && !slip) ? x : xm;
     out[0] = ld(ro, 0, x);
     out[1] = ld(ro, 1, xm);
     out[3] = ld(ro, 3, xp);
-    out[2] = ld(sb, p2, x);
-    out[5] = ld(sb, p5, x5);
-    out[6] = ld(sb, p6, x6);
-    out[4] = ld(st, p4, x);
-    out[7] = ld(st, p7, x7);
-    out[8] = ld(st, p8, x8);
+    if (!bot && !top) {
+        // every row but the two next to a y wall (uniform branch): the plain pull
+        out[2] = ld(rbp, 2, x);
+        out[5] = ld(rbp, 5, xm);
+        out[6] = ld(rbp, 6, xp);
+        out[4] = ld(rtp, 4, x);
+        out[7] = ld(rtp, 7, xp);
+        out[8] = ld(rtp, 8, xm);
+    } else {
+        const uint32_t p2 = bot ? 4 : 2, p5 = bot ? (slip ? 8 : 7) : 5, p6 = bot ? (slip ? 7 : 8) : 6;
+        const uint32_t p4 = top ? 2 : 4, p7 = top ? (slip ? 6 : 5) : 7, p8 = top ? (slip ? 5 : 6) : 8;
+        const int x5 = (bot && !slip) ? x : xm, x6 = (bot && !slip) ? x : xp;
+        const int x7 = (top && !slip) ? x : xp, x8 = (top && !slip) ? x : xm;
+        out[2] = ld(sb, p2, x);
+        out[5] = ld(sb, p5, x5);
+        out[6] = ld(sb, p6, x6);
+        out[4] = ld(st, p4, x);
+        out[7] = ld(st, p7, x7);
+        out[8] = ld(st, p8, x8);
+    }
     if (wallx) {
         // Lanes on the first or last column replace what arrived from beyond an x
         // wall: bounce-back (opposite direction, same node), or specular reflection
