@@ -309,13 +309,13 @@ def test_workgroup_widths_bit_identical(prec):
         assert err <= 1e-4
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 2e-5)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 2e-5), ("fp16", 5e-3)])
 def test_bench_grid_tiles_equal_and_match_oracle(precision, tol):
     """The benchmark's own workload and launch configuration (the 8192^2 grid of
     64 x 64 periodic tiles of the 128^2 droplet, autotuned schedule): nothing in
     the step depends on absolute position here, so every tile stays bit-identical
     to every other, and the first tile matches the oracle's 128^2 run (FP64 within
-    1e-10; FP32 phi within 2e-5)."""
+    1e-10; FP32 phi within 2e-5; fp16 storage within its 5e-3 bound)."""
     case, phi0 = W.droplet(128, 25.0, W=5.0)
     big, bphi = W.tiled(case, phi0, 64, 64)
     _print_case("bench grid", big, precision=precision)
