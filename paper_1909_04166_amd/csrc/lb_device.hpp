@@ -656,9 +656,10 @@ lb_fused(const LatDesc* __restrict__ descs, const WorkItem* __restrict__ items, 
     using T = typename ST::T;
     // Role-based register pipeline (see below): the coupled cascaded step with 16-
     // or 32-bit storage, without prefetching or walls.  Elsewhere it is not used:
-    // FP64 waits on memory, the prefetching and SRT kernels would spill, and the
-    // wall logic unrolled six times (about 6000 instructions) outgrows the
-    // instruction cache (a batch with walled lattices ran 14% slower with it).
+    // FP64 waits on memory, the FP32 prefetching and the SRT kernels would spill,
+    // the 16-bit prefetching one gained nothing, and the wall logic unrolled six
+    // times (about 6000 instructions) outgrows the instruction cache (a batch with
+    // walled lattices ran 14% slower with it).
     constexpr bool kRoles =
         MODE == MODE_STEP && PF == PF_HOLD && COLL == COLL_CASCADED && sizeof(T) < 8 && !WALLS;
     constexpr int RING = kRoles ? 6 : 4;  // rows held in each LDS ring
