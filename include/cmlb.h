@@ -97,7 +97,8 @@ typedef struct lb_config {
     double T0, dTdy, y_ref;  /* imposed linear temperature T(y) */
     double W, M;             /* interface width (> 0) and mobility (> 0) */
     double gx, gy;           /* body-force acceleration */
-    double shift_f, shift_g; /* 16-bit storage stores f_a - w_a shift_f and g_a - w_a shift_g */
+    double shift_f, shift_g; /* 16-bit storage stores f_a - w_a shift_f and g_a - w_a shift_g
+                                (9/16 and 0 recommended: w_a 9/16 is exact in fp16 and bf16) */
     double u_max;            /* stability limit for diagnostics (0: 0.3) */
     int32_t tile_x;          /* workgroup width in lanes: 64, 128, 132, 256, 260, 452, 512,
                                 516 (not with FP64 prefetching), or 1024 (FP32-compute
