@@ -86,3 +86,21 @@ def test_set_schedule_rejects():
     L.step(3)
     assert L.t == 3
     L.close()
+
+
+def test_pinned_schedule_with_graph_replay_and_repin():
+    """A pinned persistent schedule replayed through captured graphs (76 steps:
+    two graphs of 32 steps and 12 eager ones), then re-pinned mid-run to another
+    mode, gives the same lattice as fixed items all along."""
+    case, phi0 = W.random_case(1030, 2600, seed=34)
+    print("[case] pinned schedule, graph replay and re-pin 1030x2600 fp32", flush=True)
+    ref, _ = _run(case, phi0, "fp32", SCHEDULES[0], 100)
+    L = lb.Lattice(case, phi0, "fp32")
+    L.set_schedule(132, 2, 1, 0)
+    L.step(76)
+    L.set_schedule(260, 1, 2, 0)  # drops the captured graphs of the first schedule
+    L.step(24)
+    got = L.fields()
+    L.close()
+    for a, b in zip(got, ref):
+        assert np.array_equal(a, b, equal_nan=True)
