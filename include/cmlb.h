@@ -260,8 +260,10 @@ lb_status lb_batch_timing_read(lb_batch* b, double* ms_per_step, int64_t* steps)
  * the grid cut down to strips x bands (bands a multiple of 8) so that every
  * strip is cut at the same rows and the same rows of neighbouring strips run on
  * one XCD.  prefetch as lb_config.tile_pf.  The step results do not depend on the
- * schedule (bit for bit).  Returns LB_E_INVALID_ARG for an invalid value or a
- * cut that does not apply to the lattice (too few rows for the bands). */
+ * schedule (bit for bit).  Synchronizes the handle's stream (the work list is
+ * uploaded from the host) and drops captured step graphs.  Returns
+ * LB_E_INVALID_ARG for an invalid value or a cut that does not apply to the
+ * lattice (too few rows for the bands); the previous schedule then stays. */
 lb_status lb_set_schedule(lb_handle* h, int32_t tile_x, int32_t mode, int32_t param, int32_t prefetch);
 /* Schedule chosen for the handle (after autotuning when tile_x/tile_h were 0):
  * workgroup width tile_x (lanes; the strip is tile_x - 4 columns), rows per work
