@@ -436,58 +436,80 @@ __global__ void __launch_bounds__(256) k_diag_rows(const LatDesc* __restrict__ d
     }
 }
 
-__device__ double crossing_dev(const double* phi, int nx, int ny, int x, int dir) {
-    if (dir > 0) {
-        for (int j = 0; j + 1 < ny; ++j) {
-            const double a = phi[(int64_t)j * nx + x] - 0.5, b = phi[(int64_t)(j + 1) * nx + x] - 0.5;
-            if ((a < 0) != (b < 0)) return j + a / (a - b);
-        }
-    } else {
-        for (int j = ny - 2; j >= 0; --j) {
-            const double a = phi[(int64_t)j * nx + x] - 0.5, b = phi[(int64_t)(j + 1) * nx + x] - 0.5;
-            if ((a < 0) != (b < 0)) return j + a / (a - b);
-        }
-    }
-    return __longlong_as_double(0x7ff8000000000000LL);
+// Linear interpolation of the phi = 1/2 crossing between rows j and j + 1 of column x.
+__device__ double crossing_at(const double* phi, int nx, int x, int j) {
+    const double a = phi[(int64_t)j * nx + x] - 0.5, b = phi[(int64_t)(j + 1) * nx + x] - 0.5;
+    return j + a / (a - b);
+}
+__device__ bool crosses(const double* phi, int nx, int x, int j) {
+    const double a = phi[(int64_t)j * nx + x] - 0.5, b = phi[(int64_t)(j + 1) * nx + x] - 0.5;
+    return (a < 0) != (b < 0);
 }
 
-// Final pass: rows summed in order by one thread; tips scanned by two threads.
-__global__ void k_diag_final(const LatDesc* __restrict__ dp, const double* __restrict__ F,
-                             const double* __restrict__ part, double* __restrict__ out,
-                             double step, double u_max) {
+// Final pass, one workgroup of 256 threads.  Thread t sums the partials of rows
+// t, t + 256, ... in order and the 256 sums are then added in a fixed tree, so the
+// result is the same on every run.  The tips are the first phi = 1/2 crossing from
+// the bottom in column nx / 2 and the first from the top in column 0: each thread
+// checks its rows, and a min / max reduction picks the crossing row.
+__global__ void __launch_bounds__(256) k_diag_final(const LatDesc* __restrict__ dp, const double* __restrict__ F,
+                                                    const double* __restrict__ part, double* __restrict__ out,
+                                                    double step, double u_max) {
     const LatDesc& D = *dp;
     const int nx = D.nx, ny = D.ny;
     const int64_t N = (int64_t)nx * ny;
-    if (threadIdx.x == 0) {
-        double sp = 0, sr = 0, sy = 0, mx = 0, nn = 0;
-        for (int y = 0; y < ny; ++y) {
-            sp += part[4 * (int64_t)y];
-            sr += part[4 * (int64_t)y + 1];
-            sy += (double)y * part[4 * (int64_t)y];
-            const double o = part[4 * (int64_t)y + 2];
-            if (!(o <= mx)) mx = o;
-            nn += part[4 * (int64_t)y + 3];
+    const int t = threadIdx.x;
+    __shared__ double s_sp[256], s_sr[256], s_sy[256], s_mx[256], s_nn[256];
+    __shared__ int s_lo[256], s_hi[256];
+    double sp = 0, sr = 0, sy = 0, mx = 0, nn = 0;
+    int lo = INT_MAX, hi = -1;
+    for (int y = t; y < ny; y += 256) {
+        const double ph = part[4 * (int64_t)y];
+        sp += ph;
+        sr += part[4 * (int64_t)y + 1];
+        sy += (double)y * ph;
+        const double o = part[4 * (int64_t)y + 2];
+        if (!(o <= mx)) mx = o;
+        nn += part[4 * (int64_t)y + 3];
+    }
+    for (int j = t; j + 1 < ny; j += 256) {
+        if (lo == INT_MAX && crosses(F, nx, nx / 2, j)) lo = j;
+        if (crosses(F, nx, 0, j)) hi = j;
+    }
+    s_sp[t] = sp; s_sr[t] = sr; s_sy[t] = sy; s_mx[t] = mx; s_nn[t] = nn; s_lo[t] = lo; s_hi[t] = hi;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (t < st) {
+            s_sp[t] += s_sp[t + st];
+            s_sr[t] += s_sr[t + st];
+            s_sy[t] += s_sy[t + st];
+            const double o = s_mx[t + st];
+            if (!(o <= s_mx[t])) s_mx[t] = o;
+            s_nn[t] += s_nn[t + st];
+            s_lo[t] = min(s_lo[t], s_lo[t + st]);
+            s_hi[t] = max(s_hi[t], s_hi[t + st]);
         }
+        __syncthreads();
+    }
+    if (t == 0) {
+        const double nan = __longlong_as_double(0x7ff8000000000000LL);
         out[0] = step;
-        out[1] = sp;
-        out[2] = sr;
-        out[3] = mx;
+        out[1] = s_sp[0];
+        out[2] = s_sr[0];
+        out[3] = s_mx[0];
         out[4] = F[N + (int64_t)(ny / 2) * nx + nx / 2] - F[N];
-        out[5] = sqrt(sp / 3.14159265358979323846);
-        out[8] = sy / sp;
-        out[9] = nn > 0 ? 1.0 : 0.0;
-        out[10] = (nn > 0 || !(mx <= u_max)) ? 1.0 : 0.0;  // unstable flag
-    } else if (threadIdx.x == 1) {
-        out[6] = crossing_dev(F, nx, ny, nx / 2, +1);
-    } else if (threadIdx.x == 2) {
-        out[7] = crossing_dev(F, nx, ny, 0, -1);
+        out[5] = sqrt(s_sp[0] / 3.14159265358979323846);
+        out[6] = s_lo[0] == INT_MAX ? nan : crossing_at(F, nx, nx / 2, s_lo[0]);
+        out[7] = s_hi[0] < 0 ? nan : crossing_at(F, nx, 0, s_hi[0]);
+        out[8] = s_sy[0] / s_sp[0];
+        out[9] = s_nn[0] > 0 ? 1.0 : 0.0;
+        out[10] = (s_nn[0] > 0 || !(s_mx[0] <= u_max)) ? 1.0 : 0.0;  // unstable flag
     }
 }
 
 hipError_t launch_diag(const LatDesc* d, const double* fields, double* part, double* out, int ny,
                        double step, double u_max, hipStream_t s) {
     hipLaunchKernelGGL(k_diag_rows, dim3(ny), dim3(256), 0, s, d, fields, part);
-    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, s, d, fields, part, out, step, u_max);
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, s, d, fields, part, out, step, u_max);
     return hipGetLastError();
 }
 
