@@ -229,7 +229,9 @@ lb_status lb_batch_add(lb_batch* b, const lb_config* cfg, const double* phi0, in
 lb_status lb_batch_remove(lb_batch* b, int32_t slot);
 
 /* Advances every occupied slot by n steps: n launches of the persistent
- * kernel, replayed from a captured HIP graph when use_graph != 0. Asynchronous. */
+ * kernel, replayed from captured HIP graphs of 32 steps when use_graph != 0 and
+ * the batch's lattices have not changed (add / remove) in the last 128 steps;
+ * before that, and for the remainder, launched one by one.  Asynchronous. */
 lb_status lb_batch_step(lb_batch* b, int64_t n, int32_t use_graph);
 
 /* Fields / diagnostics / step of one slot, as for a single lattice. Synchronize. */

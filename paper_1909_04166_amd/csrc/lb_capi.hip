@@ -29,6 +29,9 @@ struct TraceRange {
 
 constexpr uint64_t kAlign = 256;
 constexpr int kMinH = 8;
+// A batch replays captured step graphs once its work list has been unchanged for
+// this many graph lengths (steps).
+constexpr int kGraphAfter = 4;
 
 uint64_t align_up(uint64_t v, uint64_t a = kAlign) { return (v + a - 1) / a * a; }
 
@@ -838,6 +841,7 @@ struct lb_batch {
     bool fixed_tile = false;
     bool dirty = true;
     bool walls = true;  // some occupied slot has walls (set when the work list is rebuilt)
+    int64_t stable = 0;  // steps taken since the work list last changed
     int64_t tuned_nodes = 0;  // nodes in use when the schedule was last autotuned
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     int glen = 16;
@@ -1165,11 +1169,14 @@ lb_status lb_batch_step(lb_batch* b, int64_t n, int32_t use_graph) {
         if (retune && st == LB_OK) b->tuned_nodes = nodes;
         if (st != LB_OK) return st;
         b->dirty = false;
+        b->stable = 0;
     }
     if (b->timing) HIPC(hipEventRecord(b->t0, b->s));
     int64_t left = n;
     if (b->n_items > 0) {
-        if (use_graph && left >= b->glen) {
+        // graphs only once the work list has held for a while: while lattices
+        // join and leave every few ticks, capturing costs more than it saves
+        if (use_graph && left >= b->glen && b->stable >= kGraphAfter * b->glen) {
             const int64_t reps = left / b->glen;
             for (int64_t r = 0; r < reps; ++r) {
                 hipGraphExec_t ex;
@@ -1188,6 +1195,7 @@ lb_status lb_batch_step(lb_batch* b, int64_t n, int32_t use_graph) {
         b->parity ^= 1;
     }
     b->gstep += n;
+    b->stable += n;
     if (b->timing) {
         HIPC(hipEventRecord(b->t1, b->s));
         b->last_steps = n;

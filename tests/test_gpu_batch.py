@@ -37,16 +37,19 @@ def test_batch_slots_equal_single_lattices(prec):
 
 
 def test_batch_graph_replay_equals_eager_and_mix_order():
+    """Graphs are replayed once the lattices have held for 128 steps; replays,
+    eager steps and reads interleaved give the eager result."""
     cases = _cases()
     A = lb.Batch(8, 80000, "fp32")
     G = lb.Batch(8, 80000, "fp32")
     sa = [A.add(c, p) for c, p in cases]
     sg = [G.add(c, p) for c, p in reversed(cases)][::-1]  # different slot order
-    A.step(50, use_graph=False)
-    for _ in range(3):  # replays interleaved with eager work and reads
-        G.step(16, use_graph=True)
+    A.step(300, use_graph=False)
+    G.step(128, use_graph=True)  # eager: the work list has just been built
+    for _ in range(3):  # one graph of 32 steps and 16 eager ones each time, then a read
+        G.step(48, use_graph=True)
         G.fields(sg[0])
-    G.step(2, use_graph=False)
+    G.step(28, use_graph=False)  # 128 + 3 x 48 + 28 = 300
     for x, y in zip(sa, sg):
         for u, v in zip(A.fields(x), G.fields(y)):
             assert np.array_equal(u, v, equal_nan=True)
