@@ -32,13 +32,14 @@ METRIC = "MLUPS (f+g per node-step) & % HBM roofline; p50/p99 solve latency batc
 # counter passes (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0 KiB, the factors read on the
 # library's copy kernel; see profiles/lb_fused_pmc_tiled8192.md), with the workgroup
 # schedule the autotuner chose in those runs (workgroup width, rows, grid, prefetch).
-# They hold only for that schedule and the kernel code with this fingerprint;
+# They hold only for that schedule and for the code with this fingerprint (the
+# step kernels, their launchers, the work-list builder and the build flags);
 # otherwise the roofline's traffic is null.
 KERNEL_SOURCES = ["paper_1909_04166_amd/csrc/lb_device.hpp", "paper_1909_04166_amd/csrc/lb_kernels.hip",
-                  "paper_1909_04166_amd/csrc/lb_capi.hip", "paper_1909_04166_amd/csrc/lb_internal.hpp",
-                  "paper_1909_04166_amd/csrc/lb_sched.hpp", "paper_1909_04166_amd/build.py"]
+                  "paper_1909_04166_amd/csrc/lb_internal.hpp", "paper_1909_04166_amd/csrc/lb_sched.hpp",
+                  "paper_1909_04166_amd/build.py"]
 TRAFFIC = {
-    "fingerprint": "08e6740e4a014ba6",
+    "fingerprint": "fe9021925e193b6c",
     "workload": "tiled8192",
     "fp64": {"read": 9779230272, "write": 9663676416, "tile": [516, 512, 256, 0]},
     "fp32": {"read": 4912959296, "write": 4831838208, "tile": [516, 512, 256, 1]},
@@ -100,13 +101,20 @@ def make_workload(name: str):
     if name == "droplet128":
         case, phi0 = W.config("droplet128")
         return case, phi0, "stationary droplet 128x128 periodic, ratio 1000, W 4, M 0.02"
+    if name == "droplet128_W5":
+        case, phi0 = W.droplet(128, 25.0, W=5.0)
+        return case, phi0, "stationary droplet 128x128 periodic, ratio 1000, W 5, M 0.02"
     if name == "thermo512":
         case, phi0 = W.config("thermo512")
         return case, phi0, "thermocapillary drop 512x256, walls in y, ratio 10"
     raise SystemExit(f"unknown workload {name}")
 
 
-def time_lattice(case, phi0, precision, steps, warmup, tile=(0, 0), vel=None):
+def time_lattice(case, phi0, precision, steps, warmup, tile=(0, 0), vel=None, keep_tile=0):
+    """Times `steps` steps after `warmup`; keep_tile > 0 also returns the fields
+    (phi, p, ux, uy) of the first keep_tile x keep_tile block after the run and
+    whether the last such block equals it bit for bit (read after the timed
+    region)."""
     import torch
     L = lb.Lattice(case, phi0, precision, tile=tile)
     if vel is not None:
@@ -123,37 +131,66 @@ def time_lattice(case, phi0, precision, steps, warmup, tile=(0, 0), vel=None):
     lb.lb_timing_enable(L.h, False)
     d = L.diagnostics()
     tile_used = L.tile
+    first = same = None
+    if keep_tile:
+        k = keep_tile
+        fl = L.fields()
+        first = tuple(np.array(f[:k, :k]) for f in fl)
+        same = all(np.array_equal(f[:k, :k], f[-k:, -k:]) for f in fl)
+        del fl
     L.close()
     del L
     torch.cuda.empty_cache()
-    return dict(wall_s=t1 - t0, ms_kernel=ms_kernel, rc=rc, diag=d, tile=tile_used)
+    return dict(wall_s=t1 - t0, ms_kernel=ms_kernel, rc=rc, diag=d, tile=tile_used, first_tile=first,
+                tiles_identical=same)
 
 
-def bench_batched(precision: str, steps: int, n: int = 256, seed: int = 20190909):
+# bf16 storage keeps 8 mantissa bits: phi is resolved to about 2e-3, which moves
+# rho(phi) by O(1) in the light phase at density ratios near 1000.  Its batch
+# draws the same lattices with the ratio capped at this value.
+BF16_RATIO_CAP = 10.0
+
+
+def bench_batched(precision: str, steps: int, n: int = 256, seed: int = 20190909, warmup: int = 160):
     """Uneven batch: n independent droplet / Rayleigh-Taylor lattices, sides in
-    [64, 512], density ratio log-uniform in [3, 1000]; one persistent launch per
-    step, graph replay."""
+    [64, 512], density ratio log-uniform in [3, 1000] (bf16: capped at 10), W 5;
+    one persistent launch per step.  The warm-up (autotuning, then 160 steps)
+    passes the batch's graph gate (the work list unchanged for 128 steps), so the
+    timed steps replay captured graphs.  MLUPS count every lattice; MLUPS_stable
+    only those that end stable (no NaN/Inf, max |u| below 0.3), with their count."""
     import torch
-    inst = W.batch_instances(n, seed)
+    inst = W.batch_instances(n, seed, ratio_hi=BF16_RATIO_CAP if precision == "bf16" else 1000.0)
     nodes = sum(c["nx"] * c["ny"] for _, c, _ in inst)
     B = lb.Batch(n, nodes + 64 * n, precision)
     for _, c, p in inst:
         B.add(c, p)
-    B.step(10)  # autotune + warm-up
+    B.step(warmup)  # autotune + warm-up
     torch.cuda.synchronize()
+    g0, e0 = B.launch_counts()
     lb.lb_batch_timing_enable(B.b, True)
     t0 = time.perf_counter()
     B.step(steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms, _ = lb.lb_batch_timing_read(B.b)
-    unstable = sum(1 for s in range(n) if B.diagnostics(s)["nan_flag"] != 0.0)
+    g1, e1 = B.launch_counts()
+    bad = []
+    for s in range(n):
+        d = B.diagnostics(s)
+        if d["nan_flag"] != 0.0 or not d["max_u"] < 0.3:
+            bad.append(s)
+    stable_nodes = nodes - sum(inst[s][1]["nx"] * inst[s][1]["ny"] for s in bad)
     sched = list(lb.lb_batch_get_schedule(B.b))
     B.close()
-    return {"MLUPS": round(nodes * steps / wall / 1e6, 1), "nodes": nodes, "instances": n,
-            "steps": steps, "kernel_ms": round(ms, 4), "schedule": sched,
+    return {"MLUPS": round(nodes * steps / wall / 1e6, 1),
+            "MLUPS_stable": round(stable_nodes * steps / wall / 1e6, 1),
+            "nodes": nodes, "instances": n, "unstable_instances": len(bad),
+            "unstable_kinds": sorted({inst[s][0] for s in bad}),
+            "steps": steps, "warmup": warmup, "graph_steps_timed": g1 - g0, "eager_steps_timed": e1 - e0,
+            "kernel_ms": round(ms, 4), "schedule": sched,
             "kernel_GBs": round(36 * STORE[precision] * nodes / (ms * 1e-3) / 1e9, 1),
-            "unstable_instances": unstable}
+            "frac": round(36 * STORE[precision] * nodes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "ratio_cap": BF16_RATIO_CAP if precision == "bf16" else None}
 
 
 def bench_served(precision: str, n_req: int, rate: float, budget_gb: float = 24.0, seed: int = 5):
@@ -231,14 +268,32 @@ def bench_batched_same(n_req: int, rate: float, precision: str = "fp16"):
 
 def bench_configs():
     """The paper's configurations that fit the MALL (accuracy runs; launch and
-    latency bound): MLUPS in FP64 and FP32."""
+    latency bound): MLUPS in FP64 and FP32, with whether the run stayed stable.
+    The droplet runs at W 5: at the specified W 4 the ratio-1000 droplet
+    diverges near step 450 (in the oracle as well)."""
     out = {}
-    for name, steps in (("droplet128", 1000), ("rt256", 2000)):
+    for name, steps in (("droplet128_W5", 1000), ("rt256", 2000)):
         c, p, _ = make_workload(name)
         for prec in ("fp64", "fp32"):
             rr = time_lattice(c, p, prec, steps, 50)
-            out[f"{name}_{prec}"] = round(c["nx"] * c["ny"] * steps / rr["wall_s"] / 1e6, 1)
+            out[f"{name}_{prec}"] = {"MLUPS": round(c["nx"] * c["ny"] * steps / rr["wall_s"] / 1e6, 1),
+                                     "steps": steps,
+                                     "stable": bool(rr["rc"] == 0 and rr["diag"]["nan_flag"] == 0.0
+                                                    and rr["diag"]["max_u"] < 0.3)}
     return out
+
+
+def bench_served_compact(n_req: int = 40, rate: float = 50.0):
+    """The served stream's first n_req arrivals (Poisson 50 req/s, elliptic drops
+    of sides 64-1024, 500-20000 steps, ratio 1000, W 5) two ways: continuous
+    batching in FP32 compute with fp16 storage, and the plain form (FP64, one
+    lattice at a time, first come first served).  p50 / p99 of completion minus
+    arrival and delivered MLUPS of each."""
+    bat = bench_batched_same(n_req, rate, "fp16")
+    plain = bench_plain_fifo(n_req, rate)
+    return {"requests": n_req, "rate_per_s": rate, "batched_fp16": bat, "plain_fp64_fifo": plain,
+            "p50_plain_over_batched": round(plain["p50_s"] / max(bat["p50_s"], 1e-9), 1),
+            "MLUPS_batched_over_plain": round(bat["MLUPS"] / max(plain["MLUPS"], 1e-9), 2)}
 
 
 def bench_variants(side: int, steps: int, warmup: int):
@@ -308,17 +363,37 @@ def bench_stability(steps: int = 20000):
     return out
 
 
-def cpu_baseline(target_s: float = 15.0):
-    """The FP64 oracle as it stands, on the host cores: a bounded sample (about
-    target_s seconds) of the workload's 128^2 droplet tile with OpenMP over rows on
-    all cores, then the same tile single-threaded for a shorter sample."""
+def _tile_error(gpu, orc, case):
+    """phi max-abs; p and u max-abs relative to the larger of the oracle field's
+    maximum and its physical scale (Laplace pressure sigma / R, capillary
+    velocity sigma / mu_A)."""
+    sig, R = case["sigma0"], 25.0
+    ps = max(float(np.abs(orc[1]).max()), sig / R)
+    us = max(float(np.abs(orc[2]).max()), float(np.abs(orc[3]).max()), sig / (case["rho_A"] * case["nu_A"]))
+    return {"phi_maxabs": float(np.abs(gpu[0] - orc[0]).max()),
+            "p_rel": float(np.abs(gpu[1] - orc[1]).max() / ps),
+            "u_rel": float(max(np.abs(gpu[2] - orc[2]).max(), np.abs(gpu[3] - orc[3]).max()) / us)}
+
+
+def cpu_baseline(target_s: float = 15.0, ref_steps: int = 0, gpu_tile=None):
+    """The FP64 oracle as it stands, on the host cores.
+
+    All cores (OpenMP over rows): an 8 x 8 block of the workload's tiles (the
+    1024^2 periodic lattice of 128^2 droplets, about 0.5 GB of oracle state,
+    beyond the host caches), first ref_steps steps, then more steps up to about
+    target_s seconds; MLUPS over both timed segments.  Because the timed grid is
+    periodic in its tiles, its first 128^2 tile after ref_steps steps is the
+    oracle's answer for every tile of the GPU run after the same number of steps:
+    when gpu_tile (phi, p, ux, uy of the GPU's first tile) is given, its error
+    against that answer is returned too (computed outside every timed region).
+    One core: the 128^2 tile for a shorter sample."""
     import ctypes
     import oracle
     case, phi0 = W.droplet(128, 25.0, W=5.0)
     n_nodes = case["nx"] * case["ny"]
+    gomp = ctypes.CDLL("libgomp.so.1")
 
     def timed(threads, budget_s):
-        gomp = ctypes.CDLL("libgomp.so.1")
         gomp.omp_set_num_threads(int(threads))
         o = oracle.Oracle(case, phi0)
         o.step(10)  # thread start-up
@@ -332,6 +407,25 @@ def cpu_baseline(target_s: float = 15.0):
         return steps, dt
 
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    gomp.omp_set_num_threads(cores)
+    bcase, bphi = W.tiled(case, phi0, 8, 8)
+    nb = bcase["nx"] * bcase["ny"]
+    o = oracle.Oracle(bcase, bphi)
+    del bphi
+    t0 = time.perf_counter()
+    o.step(max(ref_steps, 1))
+    dt1 = time.perf_counter() - t0
+    err = None
+    if gpu_tile is not None and ref_steps > 0:
+        ref = tuple(f[:128, :128] for f in o.fields())
+        err = _tile_error(gpu_tile, ref, case)
+    per_step = dt1 / max(ref_steps, 1)
+    more = int(max(0, min(100000, (target_s - dt1) / max(per_step, 1e-9))))
+    t0 = time.perf_counter()
+    o.step(more)
+    dt2 = time.perf_counter() - t0
+    big_steps, big_dt = max(ref_steps, 1) + more, dt1 + dt2
+    del o
     model = "unknown CPU"
     try:
         with open("/proc/cpuinfo") as fh:
@@ -341,10 +435,8 @@ def cpu_baseline(target_s: float = 15.0):
                     break
     except OSError:
         pass
-    steps, dt = timed(cores, target_s)
-    steps1, dt1 = timed(1, target_s / 3)
+    steps1, dt1s = timed(1, target_s / 3)
     # config 2 (Rayleigh-Taylor 256 x 1024), all cores, a short sample
-    gomp = ctypes.CDLL("libgomp.so.1")
     gomp.omp_set_num_threads(int(cores))
     rc, rp = W.config("rt256")
     o = oracle.Oracle(rc, rp)
@@ -352,13 +444,15 @@ def cpu_baseline(target_s: float = 15.0):
     t0 = time.perf_counter()
     o.step(40)
     rt_dt = time.perf_counter() - t0
-    return {"value": n_nodes * steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "sample": f"FP64 oracle, 128x128 droplet tile of the workload (R=25, ratio 1000, W 5), "
-                      f"{steps} steps in {dt:.1f} s, OpenMP over rows on {cores} threads",
-            "single_thread_MLUPS": round(n_nodes * steps1 / dt1 / 1e6, 2),
-            "single_thread_sample": f"{steps1} steps in {dt1:.1f} s, 1 thread",
-            "rt256x1024_MLUPS": round(rc["nx"] * rc["ny"] * 40 / rt_dt / 1e6, 2),
-            "host": f"{model}, {os.cpu_count()} logical CPUs visible"}
+    out = {"value": nb * big_steps / big_dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
+           "sample": f"FP64 oracle, 1024x1024 block (8x8 tiles) of the workload's 128^2 droplets "
+                     f"(R=25, ratio 1000, W 5), {big_steps} steps in {big_dt:.1f} s, OpenMP over rows "
+                     f"on {cores} threads",
+           "single_thread_MLUPS": round(n_nodes * steps1 / dt1s / 1e6, 2),
+           "single_thread_sample": f"128x128 tile, {steps1} steps in {dt1s:.1f} s, 1 thread",
+           "rt256x1024_MLUPS": round(rc["nx"] * rc["ny"] * 40 / rt_dt / 1e6, 2),
+           "host": f"{model}, {os.cpu_count()} logical CPUs visible"}
+    return out, err
 
 
 def main():
@@ -369,7 +463,10 @@ def main():
     ap.add_argument("--workload", default="tiled8192")
     ap.add_argument("--precision", default="fp64", choices=list(STORE))
     ap.add_argument("--tile", default="0,0")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the CPU oracle leg (and with it the oracle error of the headline run)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the default 256-lattice batch line")
+    ap.add_argument("--no-served", action="store_true", help="skip the default served-stream comparison")
     ap.add_argument("--extra", action="store_true", help="also time the other precisions and workloads")
     ap.add_argument("--batched", action="store_true", help="also time the uneven batch (256 lattices)")
     ap.add_argument("--served", action="store_true", help="also run the served Poisson stream")
@@ -415,7 +512,8 @@ def main():
     N = case["nx"] * case["ny"]
     print(f"[bench] {desc}: N={N} precision={args.precision} steps={args.steps} warmup={args.warmup}",
           file=sys.stderr, flush=True)
-    r = time_lattice(case, phi0, args.precision, args.steps, args.warmup, tile)
+    tiled = args.workload.startswith("tiled")
+    r = time_lattice(case, phi0, args.precision, args.steps, args.warmup, tile, keep_tile=128 if tiled else 0)
     del phi0
     mlups = N * args.steps / r["wall_s"] / 1e6
     s = STORE[args.precision]
@@ -449,6 +547,13 @@ def main():
         "stable": r["rc"] == 0 and r["diag"]["nan_flag"] == 0.0,
     }
     out["paper_configs"] = bench_configs()
+    if not args.no_batched:
+        out["batched"] = {"fp16": bench_batched("fp16", max(args.steps, 320))}
+        out["batched"]["fp16"]["vs_plain_fp64"] = round(out["batched"]["fp16"]["MLUPS"] / out["value"], 3)
+        out["batched"]["workload"] = ("256 uneven lattices (droplet or Rayleigh-Taylor by seed 20190909, sides "
+                                      "64-512, ratio log-uniform 3-1000, W 5), one persistent launch per step")
+    if not args.no_served:
+        out["served"] = bench_served_compact()
     if args.extra:
         extra = {}
         for prec in ("fp32", "fp16", "bf16"):
@@ -469,9 +574,10 @@ def main():
                     "tile": list(rr["tile"])}
         out["extra"] = extra
     if args.batched:
-        out["batched"] = {p: bench_batched(p, 5000) for p in ("fp16", "bf16", "fp32")}
-        for p, r in out["batched"].items():
-            r["vs_plain_fp64"] = round(r["MLUPS"] / out["value"], 3)
+        full = {p: bench_batched(p, 5000) for p in ("fp16", "bf16", "fp32")}
+        for p, rb in full.items():
+            rb["vs_plain_fp64"] = round(rb["MLUPS"] / out["value"], 3)
+        out.setdefault("batched", {})["5000_steps"] = full
     if args.served:
         sat = bench_served("fp16", 500, 50.0)
         cap_glups = max(sat["MLUPS"] / 1e3, 1e-3)
@@ -481,7 +587,7 @@ def main():
         # plain form of the same stream: 60 requests of the 0.7-load trace, FP64,
         # one lattice at a time, beside the same 60 through the batching server
         rate7 = 0.7 * cap_glups * 1e9 / mean_work
-        out["served"] = {"saturated": sat, "load_0.7": low,
+        out["served_full"] = {"saturated": sat, "load_0.7": low,
                          "vs_plain_fp64": round(sat["MLUPS"] / out["value"], 3),
                          "latency_batched_vs_plain": {"batched_fp16": bench_batched_same(60, rate7),
                                                       "plain_fp64_fifo": bench_plain_fifo(60, rate7)}}
@@ -491,7 +597,12 @@ def main():
     if args.stability:
         out["stability"] = bench_stability()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"], err = cpu_baseline(ref_steps=args.warmup + args.steps if tiled else 0,
+                                                gpu_tile=r["first_tile"])
+        if err is not None:
+            err.update(steps=args.warmup + args.steps, tiles_identical=r["tiles_identical"],
+                       reference="FP64 oracle, the cpu_baseline run's first 128^2 tile")
+            out["oracle_error"] = err
     print(json.dumps(out), flush=True)
 
 

@@ -229,10 +229,15 @@ lb_status lb_batch_add(lb_batch* b, const lb_config* cfg, const double* phi0, in
 lb_status lb_batch_remove(lb_batch* b, int32_t slot);
 
 /* Advances every occupied slot by n steps: n launches of the persistent
- * kernel, replayed from captured HIP graphs of 32 steps when use_graph != 0 and
- * the batch's lattices have not changed (add / remove) in the last 128 steps;
- * before that, and for the remainder, launched one by one.  Asynchronous. */
+ * kernel.  With use_graph != 0, once the batch's lattices have not changed
+ * (add / remove) for 128 steps, whole runs of 32 steps are replayed from
+ * captured HIP graphs; the steps of a call up to that point, and the remainder
+ * below 32, are launched one by one.  Asynchronous. */
 lb_status lb_batch_step(lb_batch* b, int64_t n, int32_t use_graph);
+
+/* Steps the batch has replayed from captured graphs and launched one by one
+ * since it was created. */
+lb_status lb_batch_launch_counts(lb_batch* b, int64_t* graph_steps, int64_t* eager_steps);
 
 /* Fields / diagnostics / step of one slot, as for a single lattice. Synchronize. */
 lb_status lb_batch_get_fields(lb_batch* b, int32_t slot, double* phi, double* p, double* ux,

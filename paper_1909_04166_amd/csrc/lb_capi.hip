@@ -844,7 +844,9 @@ struct lb_batch {
     int64_t stable = 0;  // steps taken since the work list last changed
     int64_t tuned_nodes = 0;  // nodes in use when the schedule was last autotuned
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
-    int glen = 16;
+    int glen = 32;
+    int64_t graph_steps = 0;  // steps replayed from captured graphs since creation
+    int64_t eager_steps = 0;  // steps launched one by one since creation
     bool timing = false;
     hipEvent_t t0 = nullptr, t1 = nullptr;
     int64_t last_steps = 0;
@@ -1174,23 +1176,37 @@ lb_status lb_batch_step(lb_batch* b, int64_t n, int32_t use_graph) {
     if (b->timing) HIPC(hipEventRecord(b->t0, b->s));
     int64_t left = n;
     if (b->n_items > 0) {
-        // graphs only once the work list has held for a while: while lattices
-        // join and leave every few ticks, capturing costs more than it saves
-        if (use_graph && left >= b->glen && b->stable >= kGraphAfter * b->glen) {
+        auto eager = [&](int64_t k) -> lb_status {
+            for (int64_t i = 0; i < k; ++i) {
+                HIPC(launch_step(b->prec, b->kind, b->walls, b->sc.tx, b->sc.pf, b->d_descs, b->d_items, b->n_items,
+                                 b->sc.grid, b->parity, b->s));
+                b->parity ^= 1;
+            }
+            b->eager_steps += k;
+            return LB_OK;
+        };
+        // graphs only once the work list has held for kGraphAfter graph lengths:
+        // while lattices join and leave every few ticks, capturing costs more
+        // than it saves.  Within one call, the steps up to that point run one by
+        // one and the rest replays graphs.
+        if (use_graph) {
+            const int64_t gate = (int64_t)kGraphAfter * b->glen;
+            const int64_t first = std::min<int64_t>(left, std::max<int64_t>(0, gate - b->stable));
+            lb_status st = eager(first);
+            if (st != LB_OK) return st;
+            left -= first;
             const int64_t reps = left / b->glen;
             for (int64_t r = 0; r < reps; ++r) {
                 hipGraphExec_t ex;
-                lb_status st = batch_graph(b, b->parity, &ex);
+                st = batch_graph(b, b->parity, &ex);
                 if (st != LB_OK) return st;
                 HIPC(hipGraphLaunch(ex, b->s));
             }
             left -= reps * b->glen;  // glen is even: parity unchanged
+            b->graph_steps += reps * b->glen;
         }
-        for (int64_t i = 0; i < left; ++i) {
-            HIPC(launch_step(b->prec, b->kind, b->walls, b->sc.tx, b->sc.pf, b->d_descs, b->d_items, b->n_items, b->sc.grid,
-                             b->parity, b->s));
-            b->parity ^= 1;
-        }
+        const lb_status st = eager(left);
+        if (st != LB_OK) return st;
     } else if (n & 1) {
         b->parity ^= 1;
     }
@@ -1276,6 +1292,13 @@ lb_status lb_batch_timing_read(lb_batch* b, double* ms_per_step, int64_t* steps)
     return LB_OK;
 }
 
+lb_status lb_batch_launch_counts(lb_batch* b, int64_t* graph_steps, int64_t* eager_steps) {
+    if (!b || !graph_steps || !eager_steps) return LB_E_INVALID_ARG;
+    *graph_steps = b->graph_steps;
+    *eager_steps = b->eager_steps;
+    return LB_OK;
+}
+
 lb_status lb_batch_get_schedule(lb_batch* b, int32_t* tile_x, int32_t* rows, int32_t* grid,
                                 int32_t* prefetch) {
     if (!b || !tile_x || !rows || !grid || !prefetch) return LB_E_INVALID_ARG;
@@ -1287,3 +1310,4 @@ lb_status lb_batch_get_schedule(lb_batch* b, int32_t* tile_x, int32_t* rows, int
 }
 
 }  // extern "C"
+

@@ -108,6 +108,7 @@ _SIGS = {
     "lb_get_schedule": ([_vp, _i32p, _i32p, _i32p, _i32p], ctypes.c_int32),
     "lb_set_schedule": ([_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32], ctypes.c_int32),
     "lb_batch_get_schedule": ([_vp, _i32p, _i32p, _i32p, _i32p], ctypes.c_int32),
+    "lb_batch_launch_counts": ([_vp, _i64p, _i64p], ctypes.c_int32),
     "lb_struct_sizes": ([_u64p, _u64p], ctypes.c_int32),
     "lb_copy_kernel": ([_vp, _vp, ctypes.c_uint64, _vp], ctypes.c_int32),
 }
@@ -305,6 +306,13 @@ def lb_batch_get_schedule(b: int) -> tuple[int, int, int, int]:
     _check("lb_batch_get_schedule", lib().lb_batch_get_schedule(_vp(b), ctypes.byref(a), ctypes.byref(r),
                                                                 ctypes.byref(g), ctypes.byref(p)))
     return int(a.value), int(r.value), int(g.value), int(p.value)
+
+
+def lb_batch_launch_counts(b: int) -> tuple[int, int]:
+    """(steps replayed from graphs, steps launched one by one) since creation."""
+    g, e = ctypes.c_int64(), ctypes.c_int64()
+    _check("lb_batch_launch_counts", lib().lb_batch_launch_counts(_vp(b), ctypes.byref(g), ctypes.byref(e)))
+    return int(g.value), int(e.value)
 
 
 def lb_copy_kernel(dst: int, src: int, n: int, stream: int) -> None:
@@ -526,3 +534,7 @@ class Batch:
 
     def usage(self) -> tuple[int, int]:
         return lb_batch_usage(self.b)
+
+    def launch_counts(self) -> tuple[int, int]:
+        """(steps replayed from captured graphs, steps launched one by one)."""
+        return lb_batch_launch_counts(self.b)

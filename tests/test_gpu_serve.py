@@ -4,6 +4,7 @@ lattice run alone (bit for bit)."""
 import numpy as np
 import pytest
 
+import oracle
 from paper_1909_04166_amd import lb, serve, workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -36,6 +37,20 @@ def test_served_results_equal_alone_runs():
         for u, v in zip(r.fields, L.fields()):
             assert np.array_equal(u, v, equal_nan=True)
         assert r.diag["step"] == r.steps
+        # and against the FP64 oracle: FP32 phi within 1e-4, p and u within 1e-3
+        # of their scale (Laplace pressure sigma / R_eq, capillary velocity sigma / mu_A)
+        o = oracle.Oracle(r.case, r.phi0)
+        o.step(r.steps)
+        fo = o.fields()
+        sig = r.case["sigma0"]
+        ps = max(np.abs(fo[1]).max(), sig / 12.0)
+        us = max(np.abs(fo[2]).max(), np.abs(fo[3]).max(), sig / (r.case["rho_A"] * r.case["nu_A"]))
+        e_phi = np.abs(r.fields[0] - fo[0]).max()
+        e_p = np.abs(r.fields[1] - fo[1]).max() / ps
+        e_u = max(np.abs(r.fields[2] - fo[2]).max(), np.abs(r.fields[3] - fo[3]).max()) / us
+        print(f"   request {r.rid} ({r.steps} steps) vs oracle: phi {e_phi:.2e} p {e_p:.2e} u {e_u:.2e}",
+              flush=True)
+        assert e_phi <= 1e-4 and e_p <= 1e-3 and e_u <= 1e-3
     S.close()
 
 
