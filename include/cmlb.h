@@ -53,7 +53,8 @@ enum {
     LB_E_HIP = -3,         /* a HIP runtime call failed */
     LB_E_UNSTABLE = -4,    /* a diagnostic found NaN/Inf or max|u| above the limit */
     LB_E_UNSUPPORTED = -5, /* a valid but unimplemented option */
-    LB_E_STATE = -6        /* buffer of the wrong size for save/load */
+    LB_E_STATE = -6,       /* buffer of the wrong size for save/load */
+    LB_E_TOO_LARGE = -7    /* lattice beyond the static scratch of lb_step_noalloc */
 };
 
 enum { LB_PERIODIC = 0, LB_HALFWAY_BB = 1, LB_FREE_SLIP = 2 };
@@ -283,6 +284,37 @@ lb_status lb_get_schedule(lb_handle* h, int32_t* tile_x, int32_t* rows, int32_t*
  * length; 0 until the batch has stepped with at least one occupied slot). */
 lb_status lb_batch_get_schedule(lb_batch* b, int32_t* tile_x, int32_t* rows, int32_t* grid,
                                 int32_t* prefetch);
+
+/* ------------------------------------------------------- no allocation ----
+ * For callers that cannot allocate memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Advances one lattice by n
+ * steps (the same step as lb_step) without a handle or a workspace and without
+ * allocating anything, host or device.
+ *
+ *   cfg            as for lb_create; LB_FLOW_COUPLED only and diag_every = 0
+ *                  (LB_E_UNSUPPORTED otherwise).  tile_x / tile_h / tile_pf are
+ *                  honoured; 0 takes a fixed default schedule (no autotuning).
+ *   state0, state1 caller-owned DEVICE buffers, 256-byte aligned, state_bytes each
+ *                  (at least the checkpoint size of lb_state_bytes minus its 16-byte
+ *                  header): the 18 stored planes in the storage precision, in the
+ *                  layout lb_save_state writes after that header.  The current
+ *                  state is read from state0; after the call it is in state0 if n
+ *                  is even and in state1 if n is odd.
+ *   stream         HIP stream (void*); every launch is enqueued there and the
+ *                  call returns without synchronizing.  It makes no copy, memset or
+ *                  synchronization, so it can be captured into a HIP graph once a
+ *                  first call on the device has looked up the scratch address.
+ *
+ * The descriptor, work list and per-row table live in a static 1 MiB device
+ * array that each GPU holds until the process ends; it must hold the work list
+ * (16 bytes per (strip, row block)) and, under the Langmuir law, 16 ny bytes:
+ * larger lattices (or tiles that cut them finer) return LB_E_TOO_LARGE before any
+ * device work.  Calls on one GPU share that array: calls that overlap on one
+ * device (other streams or threads) race and must be serialized by the caller.
+ * Errors: LB_E_INVALID_ARG, LB_E_UNSUPPORTED, LB_E_WORKSPACE (buffers too small
+ * or misaligned), LB_E_TOO_LARGE, LB_E_HIP. */
+lb_status lb_step_noalloc(const lb_config* cfg, void* state0, void* state1, uint64_t state_bytes,
+                          int64_t n, void* stream);
 
 /* sizeof(lb_config) and sizeof(lb_diag) as compiled, for binding checks. */
 lb_status lb_struct_sizes(uint64_t* config_bytes, uint64_t* diag_bytes);

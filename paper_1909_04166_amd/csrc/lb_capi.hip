@@ -465,6 +465,7 @@ const char* lb_status_string(lb_status s) {
     case LB_E_UNSTABLE: return "unstable: NaN/Inf or max|u| above the limit";
     case LB_E_UNSUPPORTED: return "unsupported option";
     case LB_E_STATE: return "state buffer of the wrong size";
+    case LB_E_TOO_LARGE: return "lattice too large for the 1 MiB static scratch of lb_step_noalloc";
     }
     return "unknown status";
 }
@@ -1311,3 +1312,113 @@ lb_status lb_batch_get_schedule(lb_batch* b, int32_t* tile_x, int32_t* rows, int
 
 }  // extern "C"
 
+// ================================================================ no allocation
+//
+// lb_step_noalloc advances a lattice whose two state buffers the caller owns,
+// with no handle and no workspace.  What the step kernels need beyond those
+// buffers -- the lattice descriptor, the work list and (Langmuir law only) the
+// per-row kappa~ table -- lives in `scratch`, a file-scope device array of fixed
+// size.  Each GPU holds its own copy until the process ends; its address on the
+// current device is looked up once (hipGetSymbolAddress) and kept per device.
+// Host code uses only that address, never the array's name.  Every call on one
+// device rewrites the descriptor, table and work list it uses before its step
+// kernels read them, so nothing has to start at zero; calls that overlap on one
+// device (different streams, or threads) race on the array.
+
+namespace {
+
+constexpr uint64_t kScratchBytes = (uint64_t)1 << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+lb_status scratch_on_current_device(char** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return LB_E_HIP;
+    if (dev < 0 || dev >= kMaxDevices) return LB_E_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return LB_E_HIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = (char*)g_scratch_ptr[dev];
+    return LB_OK;
+}
+
+// One thread stores the descriptor (passed by value) into device memory.
+__global__ void k_put_desc(LatDesc* __restrict__ dst, LatDesc d) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *dst = d;
+}
+
+// Work list of one lattice (instance 0), strip-major: item i is row block
+// i % nrb of strip i / nrb, th rows of strip_w columns (the host's build_items).
+__global__ void k_items_strips(WorkItem* __restrict__ out, int ny, int sw, int th, int nrb, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int st = i / nrb, r = i - st * nrb;
+    WorkItem w;
+    w.inst = 0;
+    w.x0 = st * sw;
+    w.y0 = r * th;
+    w.y1 = min(ny, r * th + th);
+    out[i] = w;
+}
+
+}  // namespace
+
+extern "C" {
+
+lb_status lb_step_noalloc(const lb_config* cfg, void* state0, void* state1, uint64_t state_bytes,
+                          int64_t n, void* stream) {
+    if (!cfg || !state0 || !state1 || n < 0 || state0 == state1) return LB_E_INVALID_ARG;
+    lb_status st = validate(cfg);
+    if (st != LB_OK) return st;
+    if (cfg->flow != LB_FLOW_COUPLED || cfg->diag_every != 0) return LB_E_UNSUPPORTED;
+    const int64_t P = plane_elems(cfg->nx, cfg->ny);
+    const uint64_t need = (uint64_t)18 * P * store_bytes(cfg->precision);
+    if (state_bytes < need || ((uintptr_t)state0 % kAlign) || ((uintptr_t)state1 % kAlign)) return LB_E_WORKSPACE;
+    // schedule: one work item per workgroup (the results do not depend on it)
+    Sched sc = default_sched(cfg->nx, cfg->ny);
+    if (cfg->tile_x) sc.tx = cfg->tile_x;
+    if (cfg->tile_h) sc.th = cfg->tile_h;
+    sc.pf = cfg->tile_pf;
+    const int sw = strip_w(sc.tx);
+    const int nrb = (cfg->ny + sc.th - 1) / sc.th;
+    const int64_t n_items = (int64_t)((cfg->nx + sw - 1) / sw) * nrb;
+    // scratch layout: descriptor | kappa~ table (Langmuir law) | work list
+    const uint64_t o_tab = align_up(sizeof(LatDesc));
+    const uint64_t tab = cfg->surf == LB_SIGMA_LANGMUIR ? align_up((uint64_t)2 * cfg->ny * sizeof(double)) : 0;
+    const uint64_t o_items = o_tab + tab;
+    if (o_items + (uint64_t)n_items * sizeof(WorkItem) > kScratchBytes) return LB_E_TOO_LARGE;
+    if (n == 0) return LB_OK;
+    char* scr = nullptr;
+    st = scratch_on_current_device(&scr);
+    if (st != LB_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    LatDesc D;
+    fill_desc(cfg, D, state0, state1, P, nullptr);
+    D.ktab = tab ? (double*)(scr + o_tab) : nullptr;
+    D.vel = nullptr;
+    const bool walls = D.wall_y != WALL_NONE || D.wall_x != WALL_NONE;
+    LatDesc* d_desc = (LatDesc*)scr;
+    WorkItem* d_items = (WorkItem*)(scr + o_items);
+    hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(64), 0, s, d_desc, D);
+    HIPC(hipGetLastError());
+    hipLaunchKernelGGL(k_items_strips, dim3((unsigned)((n_items + 255) / 256)), dim3(256), 0, s, d_items, cfg->ny,
+                       sw, sc.th, nrb, (int)n_items);
+    HIPC(hipGetLastError());
+    if (tab) HIPC(launch_kappa_table(d_desc, cfg->ny, s));
+    const int kind = kind_of(cfg);
+    int parity = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        HIPC(launch_step(cfg->precision, kind, walls, sc.tx, sc.pf, d_desc, d_items, (int)n_items, (int)n_items,
+                         parity, s));
+        parity ^= 1;
+    }
+    return LB_OK;
+}
+
+}  // extern "C"

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libcmlb.so")
 
 LB_OK, LB_E_INVALID_ARG, LB_E_WORKSPACE, LB_E_HIP, LB_E_UNSTABLE, LB_E_UNSUPPORTED, LB_E_STATE = (
     0, -1, -2, -3, -4, -5, -6)
+LB_E_TOO_LARGE = -7
 LB_PERIODIC, LB_HALFWAY_BB, LB_FREE_SLIP = 0, 1, 2
 LB_BC = {"periodic": LB_PERIODIC, "wall": LB_HALFWAY_BB, "slip": LB_FREE_SLIP}
 LB_COLLISION = {"cascaded": 0, "srt": 1}
@@ -111,6 +112,8 @@ _SIGS = {
     "lb_batch_launch_counts": ([_vp, _i64p, _i64p], ctypes.c_int32),
     "lb_struct_sizes": ([_u64p, _u64p], ctypes.c_int32),
     "lb_copy_kernel": ([_vp, _vp, ctypes.c_uint64, _vp], ctypes.c_int32),
+    "lb_step_noalloc": ([ctypes.POINTER(lb_config), _vp, _vp, ctypes.c_uint64, ctypes.c_int64, _vp],
+                        ctypes.c_int32),
 }
 
 
@@ -317,6 +320,13 @@ def lb_batch_launch_counts(b: int) -> tuple[int, int]:
 
 def lb_copy_kernel(dst: int, src: int, n: int, stream: int) -> None:
     _check("lb_copy_kernel", lib().lb_copy_kernel(_vp(dst), _vp(src), int(n), _vp(stream)))
+
+
+def lb_step_noalloc(cfg: lb_config, state0: int, state1: int, state_bytes: int, n: int, stream: int) -> None:
+    """n steps of a lattice held in two caller-owned device buffers (the checkpoint
+    payload layout); the state ends in state0 for even n, state1 for odd n."""
+    _check("lb_step_noalloc", lib().lb_step_noalloc(ctypes.byref(cfg), _vp(state0), _vp(state1),
+                                                     int(state_bytes), int(n), _vp(stream)))
 
 
 def lb_batch_workspace_bytes(slots: int, node_capacity: int, precision: str) -> int:

@@ -124,3 +124,32 @@ def test_option_validation():
     c = lb.config_from_case(case, "fp64")
     c.flow = lb.LB_FLOW["imposed"]
     assert lb.lb_workspace_bytes(c) >= base + 2 * 8 * case["nx"] * case["ny"]
+
+
+def test_noalloc_rejects_before_device_work():
+    """lb_step_noalloc checks its arguments and the static scratch limit on the
+    host, before any device work (fake, aligned pointers are never touched)."""
+    case, _ = W.droplet(128, 25.0)
+    cfg = lb.config_from_case(case, "fp64")
+    big = 1 << 40
+    a, b = 1 << 20, 1 << 21  # never dereferenced: every call below fails first
+
+    def code(c, n=1, nbytes=big, p0=a, p1=b):
+        try:
+            lb.lb_step_noalloc(c, p0, p1, nbytes, n, 0)
+            return lb.LB_OK
+        except lb.LBError as e:
+            return e.code
+
+    # 16384^2 cut into 64-lane strips of 8 rows: 274 x 2048 work items of 16 B
+    wide, _ = W.uniform_phase(16384, 16384)
+    assert code(lb.config_from_case(wide, "fp32", tile=(64, 8))) == lb.LB_E_TOO_LARGE
+    assert code(cfg, nbytes=18 * 8 * 128 * 128 - 8) == lb.LB_E_WORKSPACE
+    assert code(cfg, p0=a + 64) == lb.LB_E_WORKSPACE
+    assert code(cfg, p1=a) == lb.LB_E_INVALID_ARG
+    assert code(cfg, n=-1) == lb.LB_E_INVALID_ARG
+    c = lb.config_from_case(case, "fp64", diag_every=10)
+    assert code(c) == lb.LB_E_UNSUPPORTED
+    c = lb.config_from_case(dict(case, flow="imposed"), "fp64")
+    assert code(c) == lb.LB_E_UNSUPPORTED
+    assert "static scratch" in lb.lib().lb_status_string(lb.LB_E_TOO_LARGE).decode()
