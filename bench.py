@@ -551,7 +551,8 @@ def main():
         out["batched"] = {"fp16": bench_batched("fp16", max(args.steps, 320))}
         out["batched"]["fp16"]["vs_plain_fp64"] = round(out["batched"]["fp16"]["MLUPS"] / out["value"], 3)
         out["batched"]["workload"] = ("256 uneven lattices (droplet or Rayleigh-Taylor by seed 20190909, sides "
-                                      "64-512, ratio log-uniform 3-1000, W 5), one persistent launch per step")
+                                      "64-512, ratio log-uniform 3-1000, W 5, M 0.02), one persistent launch "
+                                      "per step")
     if not args.no_served:
         out["served"] = bench_served_compact()
     if args.extra:

@@ -229,7 +229,9 @@ def test_flat_interface_fp32():
     stationary case: FP32 storage and compute stay within 1e-4 of the FP64 oracle
     after 1000 steps, phi in max-abs, p and u relative to the interface's own
     scales (pressure sigma / W, capillary velocity sigma / mu_A), and the phi = 1/2
-    crossing within 1e-4 of the oracle's (63.5 by symmetry)."""
+    crossing (63.5 by symmetry in the oracle) within the distance that phi
+    tolerance allows: an error d in phi at the interface moves the crossing by
+    d / |dphi/dy| = d W (the tanh profile's slope there is 1 / W), so 1e-4 W."""
     case, phi0 = W.flat_interface(8, 128)
     _print_case("flat interface fp32", case)
     g = lb.Lattice(case, phi0, "fp32")
@@ -241,7 +243,7 @@ def test_flat_interface_fp32():
                 u_scale=sig / (case["rho_A"] * case["nu_A"]))
     cg, co = g.diagnostics()["spike_y"], o.diagnostics()["spike_y"]
     print(f"   crossing gpu {cg:.6f} oracle {co:.6f}", flush=True)
-    assert abs(co - 63.5) <= 1e-9 and abs(cg - co) <= 1e-4
+    assert abs(co - 63.5) <= 1e-9 and abs(cg - co) <= 1e-4 * case["W"]
 
 
 @pytest.mark.parametrize("prec,ratio,tol", [("fp16", 1000.0, 5e-3), ("bf16", 10.0, 5e-2)])
