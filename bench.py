@@ -33,17 +33,16 @@ METRIC = "MLUPS (f+g per node-step) & % HBM roofline; p50/p99 solve latency batc
 # library's copy kernel; see profiles/lb_fused_pmc_tiled8192.md), with the workgroup
 # schedule the autotuner chose in those runs (workgroup width, rows, grid, prefetch).
 # They hold only for that schedule and for the code with this fingerprint (the
-# step kernels, their launchers, the work-list builder and the build flags);
-# otherwise the roofline's traffic is null.
+# step kernels, their instantiations and launchers, the work-list builder and the
+# compiler flags); otherwise the roofline's traffic is null.
 KERNEL_SOURCES = ["paper_1909_04166_amd/csrc/lb_device.hpp", "paper_1909_04166_amd/csrc/lb_kernels.hip",
-                  "paper_1909_04166_amd/csrc/lb_internal.hpp", "paper_1909_04166_amd/csrc/lb_sched.hpp",
-                  "paper_1909_04166_amd/build.py"]
+                  "paper_1909_04166_amd/csrc/lb_sched.hpp"]
 TRAFFIC = {
-    "fingerprint": "fe9021925e193b6c",
+    "fingerprint": "6e28d17a276f7bc8",
     "workload": "tiled8192",
-    "fp64": {"read": 9779230272, "write": 9663676416, "tile": [516, 512, 256, 0]},
-    "fp32": {"read": 4912959296, "write": 4831838208, "tile": [516, 512, 256, 1]},
-    "fp16": {"read": 3045304000, "write": 2415919104, "tile": [452, 304, 512, 0]},
+    "fp64": {"read": 9807700992, "write": 9663676416, "tile": [516, 512, 256, 0]},
+    "fp32": {"read": 4910539264, "write": 4831838208, "tile": [516, 512, 256, 1]},
+    "fp16": {"read": 3045338112, "write": 2415919104, "tile": [452, 304, 512, 0]},
 }
 
 
@@ -61,12 +60,15 @@ def _code_only(text: str, hash_comments: bool) -> str:
 
 
 def kernel_fingerprint() -> str:
-    """Hash of the code that builds the step kernel (comments excluded)."""
+    """Hash of the code that builds the step kernel (comments excluded) and of
+    the compiler flags."""
     import hashlib
+    from paper_1909_04166_amd import build
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), encoding="utf-8") as fh:
             h.update(_code_only(fh.read(), f.endswith(".py")).encode())
+    h.update(" ".join(build.FLAGS).encode())
     return h.hexdigest()[:16]
 
 
@@ -110,13 +112,15 @@ def make_workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def time_lattice(case, phi0, precision, steps, warmup, tile=(0, 0), vel=None, keep_tile=0):
+def time_lattice(case, phi0, precision, steps, warmup, tile=(0, 0), vel=None, keep_tile=0, sched=None):
     """Times `steps` steps after `warmup`; keep_tile > 0 also returns the fields
     (phi, p, ux, uy) of the first keep_tile x keep_tile block after the run and
     whether the last such block equals it bit for bit (read after the timed
     region)."""
     import torch
     L = lb.Lattice(case, phi0, precision, tile=tile)
+    if sched is not None:  # pinned (width, mode, rows or multiplier, prefetch): no autotuning
+        L.set_schedule(*sched)
     if vel is not None:
         L.set_velocity(*vel)
     L.step(warmup)
@@ -330,14 +334,16 @@ def bench_variants(side: int, steps: int, warmup: int):
 def bench_stability(steps: int = 20000):
     """Sec. 7: smallest viscosity (nu_A = nu_B) with a stable run of the
     oscillating elliptic cylinder (200^2, a = 25, b = 15, kappa~ = 0.01) for the
-    cascaded and the SRT pair at density ratios 500-900.  Stable: no NaN/Inf and
+    cascaded pair (moment changes solved as stated, and their printed closed
+    forms) and the SRT pair at density ratios 500-900.  Stable: no NaN/Inf and
     max |u| < 0.1 after `steps` steps.  nu ladder 0.1 * 0.6^k, k = 0..19.  Each
     model runs as one batch of 80 lattices."""
     ratios = (500, 600, 800, 900)
     nus = [0.1 * 0.6 ** k for k in range(20)]
     stable = {}
     t0 = time.perf_counter()
-    for coll in ("cascaded", "srt"):
+    models = ("cascaded", "printed", "srt")
+    for coll in models:
         B = lb.Batch(len(ratios) * len(nus), 40000 * len(ratios) * len(nus) + 1000, "fp64")
         slots = {}
         for r in ratios:
@@ -352,12 +358,13 @@ def bench_stability(steps: int = 20000):
     out = {"steps": steps, "nu_ladder": [float(f"{v:.3e}") for v in nus], "wall_s": None}
     for r in ratios:
         row = {}
-        for coll in ("cascaded", "srt"):
+        for coll in models:
             ok = [nu for nu in nus if stable[(coll, r, nu)]]
             row[f"{coll}_nu_min"] = float(f"{min(ok):.3e}") if ok else None
             row[f"{coll}_unstable"] = [float(f"{nu:.3e}") for nu in nus if not stable[(coll, r, nu)]]
-        if row["cascaded_nu_min"] and row["srt_nu_min"]:
-            row["srt_over_cascaded"] = round(row["srt_nu_min"] / row["cascaded_nu_min"], 1)
+        for c in ("cascaded", "printed"):
+            if row[f"{c}_nu_min"] and row["srt_nu_min"]:
+                row[f"srt_over_{c}"] = round(row["srt_nu_min"] / row[f"{c}_nu_min"], 1)
         out[f"ratio_{r}"] = row
     out["wall_s"] = round(time.perf_counter() - t0, 1)
     return out
@@ -463,8 +470,11 @@ def main():
     ap.add_argument("--workload", default="tiled8192")
     ap.add_argument("--precision", default="fp64", choices=list(STORE))
     ap.add_argument("--tile", default="0,0")
+    ap.add_argument("--schedule", default="", metavar="TX,MODE,PARAM,PF",
+                    help="pin the headline lattice's schedule (lb_set_schedule) instead of autotuning")
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the CPU oracle leg (and with it the oracle error of the headline run)")
+    ap.add_argument("--no-configs", action="store_true", help="skip the paper's small configurations")
     ap.add_argument("--no-batched", action="store_true", help="skip the default 256-lattice batch line")
     ap.add_argument("--no-served", action="store_true", help="skip the default served-stream comparison")
     ap.add_argument("--extra", action="store_true", help="also time the other precisions and workloads")
@@ -477,6 +487,8 @@ def main():
     ap.add_argument("--copy-ref", type=int, default=0, metavar="MIB",
                     help="only run the library's device copy kernel over MIB MiB (bandwidth and "
                          "counter reference) and print its GB/s")
+    ap.add_argument("--copy-variants", default="0",
+                    help="with --copy-ref: comma-separated lb_bandwidth_probe variants (0 = lb_copy_kernel)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -491,21 +503,29 @@ def main():
     tile = tuple(int(v) for v in args.tile.split(","))
     if args.copy_ref:
         n = args.copy_ref << 20
-        a = torch.empty(n, dtype=torch.uint8, device="cuda")
+        a = torch.ones(n, dtype=torch.uint8, device="cuda")
         b = torch.empty(n, dtype=torch.uint8, device="cuda")
         stream = torch.cuda.current_stream().cuda_stream
-        for _ in range(3):
-            lb.lb_copy_kernel(b.data_ptr(), a.data_ptr(), n, stream)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        reps = 20
-        for _ in range(reps):
-            lb.lb_copy_kernel(b.data_ptr(), a.data_ptr(), n, stream)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
-        print(json.dumps({"copy_kernel_bytes_read": n, "bytes_written": n, "ms": ms,
-                          "GBs": 2 * n / (ms * 1e-3) / 1e9}), flush=True)
+        variants = [int(v) for v in args.copy_variants.split(",")]
+        # bytes each variant moves: copies read and write n, the read probe reads
+        # n (and writes 16 MiB), the write probe writes n
+        moved = {5: n + (16 << 20), 6: n}
+        out = {"bytes": n, "variants": {}}
+        for v in variants:
+            run = (lambda: lb.lb_copy_kernel(b.data_ptr(), a.data_ptr(), n, stream)) if v == 0 else \
+                  (lambda v=v: lb.lb_bandwidth_probe(b.data_ptr(), a.data_ptr(), n, v, stream))
+            for _ in range(3):
+                run()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            reps = 20
+            for _ in range(reps):
+                run()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            out["variants"][v] = {"ms": round(ms, 4), "GBs": round(moved.get(v, 2 * n) / (ms * 1e-3) / 1e9, 1)}
+        print(json.dumps(out), flush=True)
         return
 
     case, phi0, desc = make_workload(args.workload)
@@ -513,7 +533,9 @@ def main():
     print(f"[bench] {desc}: N={N} precision={args.precision} steps={args.steps} warmup={args.warmup}",
           file=sys.stderr, flush=True)
     tiled = args.workload.startswith("tiled")
-    r = time_lattice(case, phi0, args.precision, args.steps, args.warmup, tile, keep_tile=128 if tiled else 0)
+    sched = tuple(int(v) for v in args.schedule.split(",")) if args.schedule else None
+    r = time_lattice(case, phi0, args.precision, args.steps, args.warmup, tile, keep_tile=128 if tiled else 0,
+                     sched=sched)
     del phi0
     mlups = N * args.steps / r["wall_s"] / 1e6
     s = STORE[args.precision]
@@ -546,7 +568,8 @@ def main():
                      "alg_bytes_per_launch": bytes_per_launch},
         "stable": r["rc"] == 0 and r["diag"]["nan_flag"] == 0.0,
     }
-    out["paper_configs"] = bench_configs()
+    if not args.no_configs:
+        out["paper_configs"] = bench_configs()
     if not args.no_batched:
         out["batched"] = {"fp16": bench_batched("fp16", max(args.steps, 320))}
         out["batched"]["fp16"]["vs_plain_fp64"] = round(out["batched"]["fp16"]["MLUPS"] / out["value"], 3)

@@ -58,11 +58,20 @@ enum {
 };
 
 enum { LB_PERIODIC = 0, LB_HALFWAY_BB = 1, LB_FREE_SLIP = 2 };
-/* collision model of both schemes: cascaded central moments (Secs. 4, 5) or the
- * single-relaxation-time comparison pair (Sec. 7; BGK toward second-order Hermite
- * equilibria and sources with the same zeroth to second moments, one rate:
- * omega(nu(phi)) for gbar, omega^phi for f) */
-enum { LB_CASCADED = 0, LB_SRT = 1 };
+/* collision model of both schemes:
+ *   LB_CASCADED          cascaded central moments (Secs. 4, 5); the hydrodynamic
+ *                        moment changes h_3..h_8 solve the relaxation conditions
+ *                        of Sec. 4 as stated (the incoming gbar's own central
+ *                        moments, h_0..h_2 carried into the higher moments);
+ *   LB_SRT               the single-relaxation-time comparison pair (Sec. 7; BGK
+ *                        toward second-order Hermite equilibria and sources with
+ *                        the same zeroth to second moments, one rate:
+ *                        omega(nu(phi)) for gbar, omega^phi for f);
+ *   LB_CASCADED_PRINTED  as LB_CASCADED with the printed closed forms of h_3..h_8
+ *                        (Eq. cascadedcollisionoperator), which leave out both
+ *                        effects above and differ by O(F) in h_6, h_7.
+ * The phase-field cascade is the same in LB_CASCADED and LB_CASCADED_PRINTED. */
+enum { LB_CASCADED = 0, LB_SRT = 1, LB_CASCADED_PRINTED = 2 };
 /* LB_FLOW_IMPOSED: only the phase field f is advanced, under the velocity set by
  * lb_set_velocity (Sec. 6.1); gbar, the pressure and all forces are absent. */
 enum { LB_FLOW_COUPLED = 0, LB_FLOW_IMPOSED = 1 };
@@ -75,6 +84,21 @@ enum { LB_FREF_MEAN = 0, LB_FREF_LIGHT = 1, LB_FREF_HEAVY = 2, LB_FREF_NONE = 3 
 enum { LB_ST_GEOMETRIC = 0, LB_ST_CHEMPOT = 1 };
 /* storage precision of the 18 distribution planes; compute is FP64 for LB_FP64 and FP32 otherwise */
 enum { LB_FP64 = 0, LB_FP32 = 1, LB_FP32_F16 = 2, LB_FP32_BF16 = 3 };
+/* built-in initial phase field (lb_init_fields / lb_batch_add with phi0 = NULL): the
+ * equilibrium profile phi0 = 1/2 + 1/2 tanh(2 d / W) of the conservative Allen-Cahn
+ * equation (Sec. 2) of a signed distance d, positive in phase A:
+ *   LB_INIT_DROPLET   init_par = {xc, yc, R, s, px, py}: d = s (R - r), r the distance
+ *                     to (xc, yc); s = +1 a drop of phase A (Sec. 6.2), -1 a bubble of
+ *                     phase B (Sec. 6.5); px, py > 0 repeat it with that period
+ *                     (x and y taken modulo px, py first; 0: no repetition);
+ *   LB_INIT_ELLIPSE   init_par = {xc, yc, a, b, px, py}: semi-axes a (x), b (y) of phase
+ *                     A (Sec. 7); d = r (1/q - 1) with q = sqrt((X/a)^2 + (Y/b)^2), the
+ *                     radial scaling of the ellipse (d = max(a, b) at the centre);
+ *   LB_INIT_INTERFACE init_par = {y0, A, k}: phase A above y0 + A cos(2 pi k x / nx)
+ *                     (Sec. 6.3 with k = 1; a flat interface with A = 0):
+ *                     d = y - y0 - A cos(2 pi k x / nx).
+ * Node (i, j) sits at (x, y) = (i, j). */
+enum { LB_INIT_NONE = 0, LB_INIT_DROPLET = 1, LB_INIT_ELLIPSE = 2, LB_INIT_INTERFACE = 3 };
 
 /*
  * Problem description (Secs. 2, 4, 5).  Phase A is phi = 1, phase B is phi = 0.
@@ -114,13 +138,16 @@ typedef struct lb_config {
                                 collision (LB_CASCADED with LB_FLOW_COUPLED only);
                                 must be 0 otherwise */
     double beta, psi_a, psi_G; /* Langmuir law parameters */
+    int32_t init_kind;       /* LB_INIT_*: the built-in initial phase field */
+    int32_t init_pad_;
+    double init_par[8];      /* its parameters (see LB_INIT_*) */
 } lb_config;
 
 typedef struct lb_diag {
     double step;       /* time step of the state */
     double sum_phi;    /* sum over nodes of phi */
     double sum_rho;    /* sum over nodes of rho(phi) */
-    double max_u;      /* max |u| */
+    double max_u;      /* max |u| (NaN if any |u| is NaN) */
     double dp_laplace; /* p(nx/2, ny/2) - p(0, 0) (Laplace-Young probe, Sec. 6.2) */
     double r_eff;      /* sqrt(sum phi / pi) */
     double spike_y;    /* lowest phi = 1/2 crossing on column nx/2 (NaN if none) */
@@ -148,8 +175,12 @@ lb_status lb_workspace_bytes(const lb_config* cfg, uint64_t* bytes);
 lb_status lb_create(const lb_config* cfg, void* dev_ws, uint64_t ws_bytes, void* stream,
                     lb_handle** out);
 
-/* Initial state at t = 0 (Sec. 5 / readings): f_a = w_a phi0, gbar_a = 0 (p = 0, u = 0).
- * phi0: host, ny*nx FP64, caller-owned, read before return.  Synchronizes. */
+/* Initial state at t = 0: f_a = w_a phi0, gbar_a = 0, i.e. p = 0 and u = 0 (the
+ * paper states no initialization; this is the zero-velocity, zero-pressure
+ * equilibrium of both schemes without the sharpening term, Secs. 4 and 5).
+ * phi0: host, ny*nx FP64, caller-owned, read before return; or NULL for the
+ * built-in field of cfg.init_kind, computed on the device (LB_E_INVALID_ARG if
+ * init_kind is LB_INIT_NONE).  Synchronizes. */
 lb_status lb_init_fields(lb_handle* h, const double* phi0);
 
 /* Imposed velocity for LB_FLOW_IMPOSED (Sec. 6.1): host FP64 ux, uy of ny*nx each,
@@ -218,7 +249,8 @@ lb_status lb_batch_create(int32_t slots, int64_t node_capacity, int32_t precisio
                           int32_t tile_x, int32_t tile_h, void* dev_ws, uint64_t ws_bytes,
                           void* stream, lb_batch** out);
 
-/* Places a lattice in a free slot and initializes it like lb_init_fields.
+/* Places a lattice in a free slot and initializes it like lb_init_fields (phi0 NULL:
+ * the built-in field of cfg->init_kind).
  * Returns the slot index in *slot.  A slot holds at most min(node_capacity,
  * 2^24) nodes.  Errors: LB_E_INVALID_ARG (bad config, or a precision or collision
  * model other than the batch's), LB_E_UNSUPPORTED (LB_FLOW_IMPOSED),
@@ -322,6 +354,17 @@ lb_status lb_struct_sizes(uint64_t* config_bytes, uint64_t* diag_bytes);
 /* Device-to-device copy kernel over n bytes (attainable-bandwidth reference for
  * the roofline).  Enqueued on `stream`; src/dst are device pointers, 16-byte aligned. */
 lb_status lb_copy_kernel(void* dst, const void* src, uint64_t n, void* stream);
+
+/* Streams bounding the attainable HBM bandwidth, n bytes (>= 16 MiB, a multiple
+ * of 16), device pointers 16-byte aligned, enqueued on `stream`:
+ *   0 the copy of lb_copy_kernel (4 x 16 B per lane in flight);
+ *   1 copy, persistent grid (16 workgroups per CU), 8 x 16 B per lane in flight;
+ *   2 as 1 with nontemporal loads and stores;  3 as 1 with 4 in flight and
+ *     nontemporal stores;  4 copy, one contiguous chunk per workgroup;
+ *   5 read only: reads src, writes one 16-byte word per lane of the grid to dst
+ *     (16 MiB);  6 write only: fills dst.
+ * Errors: LB_E_INVALID_ARG. */
+lb_status lb_bandwidth_probe(void* dst, const void* src, uint64_t n, int32_t variant, void* stream);
 
 #ifdef __cplusplus
 }

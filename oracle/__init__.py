@@ -48,11 +48,16 @@ class OrcParams(ctypes.Structure):
         ("W", ctypes.c_double), ("M", ctypes.c_double),
         ("gx", ctypes.c_double), ("gy", ctypes.c_double),
         ("beta", ctypes.c_double), ("psi_a", ctypes.c_double), ("psi_G", ctypes.c_double),
+        ("q6_minus8", ctypes.c_int32), ("q8_printed", ctypes.c_int32), ("q11_lagged", ctypes.c_int32),
+        ("pad3_", ctypes.c_int32),
     ]
 
 
 _BC = {"periodic": 0, "wall": 1, "slip": 2}
-_COLL = {"cascaded": 0, "srt": 1}
+# "printed": the cascaded pair with the printed closed forms of the hydrodynamic
+# moment changes h_3..h_8 (the study switch q8_printed); "cascaded" solves the
+# relaxation conditions they come from
+_COLL = {"cascaded": 0, "srt": 1, "printed": 0}
 _FLOW = {"coupled": 0, "imposed": 1}
 _SURF = {"linear": 0, "langmuir": 1}
 _FREF = {"mean": 0, "light": 1, "heavy": 2, "none": 3}
@@ -81,6 +86,7 @@ def _load():
         lib.orc_step_count.argtypes = [vp]
         lib.orc_step_count.restype = ctypes.c_int64
         lib.orc_hydro_collide.argtypes = [dp] + [ctypes.c_double] * 9 + [dp, dp]
+        lib.orc_hydro_collide_study.argtypes = ([dp] + [ctypes.c_double] * 9 + [dp, ctypes.c_int, ctypes.c_int, dp])
         lib.orc_ace_collide.argtypes = [dp] + [ctypes.c_double] * 7 + [dp, dp]
         lib.orc_hydro_srt.argtypes = [dp] + [ctypes.c_double] * 9 + [dp]
         lib.orc_ace_srt.argtypes = [dp] + [ctypes.c_double] * 8 + [dp]
@@ -123,6 +129,10 @@ def params_from_case(case: dict) -> OrcParams:
     P.beta = float(case.get("beta", 0.0))
     P.psi_a = float(case.get("psi_a", 0.0))
     P.psi_G = float(case.get("psi_G", 0.0))
+    # study switches of the oracle only (other readings of Q6, Q8, Q11; off by default)
+    P.q6_minus8 = int(bool(case.get("oracle_q6_minus8", False)))
+    P.q8_printed = int(bool(case.get("oracle_q8_printed", False)) or case.get("collision") == "printed")
+    P.q11_lagged = int(bool(case.get("oracle_q11_lagged", False)))
     return P
 
 
@@ -208,6 +218,19 @@ def hydro_collide(gbar, p, rho, psi, ux, uy, Ftx, Fty, Fpx, Fpy, omega):
     om = np.ascontiguousarray(omega, dtype=np.float64)
     out = np.empty(Q)
     lib.orc_hydro_collide(_dp(g), p, rho, psi, ux, uy, Ftx, Fty, Fpx, Fpy, _dp(om), _dp(out))
+    return out
+
+
+def hydro_collide_study(gbar, p, rho, psi, ux, uy, Ftx, Fty, Fpx, Fpy, omega, q6_minus8=False,
+                        q8_printed=False):
+    """The hydrodynamic collision under the study switches (other readings of
+    m^s'_8's sigma'_00 coefficient and of h_3..h_8)."""
+    lib = _load()
+    g = np.ascontiguousarray(gbar, dtype=np.float64)
+    om = np.ascontiguousarray(omega, dtype=np.float64)
+    out = np.empty(Q)
+    lib.orc_hydro_collide_study(_dp(g), p, rho, psi, ux, uy, Ftx, Fty, Fpx, Fpy, _dp(om),
+                                int(bool(q6_minus8)), int(bool(q8_printed)), _dp(out))
     return out
 
 

@@ -22,7 +22,9 @@
  *   O8  pbar = sum gbar, grad pbar, F_p, p, psi              (Eqs. netgradientpressureforce, hydrodynamicfields)
  *   O9  raw source moments sigma'_mn                         (Sec. 4, after Eq. matchingmoments)
  *   O10 m^s'_j and delta g^s_a                               (Eq. cumulativesourcetermcomponents)
- *   O11 raw moments of gbar and h_0..h_8                     (Eq. cascadedcollisionoperator)
+ *   O11 central moments of gbar, h_0..h_2 and h_3..h_8 from the relaxation
+ *       conditions of the cascaded collision, solved as stated (Sec. 4,
+ *       Eq. cascadedcollisionoperator and the conditions that define it)
  *   O12 post-collision gbar                                  (Eq. postcollisioncascadedLBscheme)
  *   O13 raw moments of f, g_0..g_8 and post-collision f      (Sec. 5)
  *   O14 pull streaming, halfway bounce-back at walls         (Eqs. ACEstreamingLB and Sec. 4 streaming)
@@ -43,6 +45,15 @@
  *   - c_s^2 = c_sphi^2 = 1/3.
  *   - in m^s'_8 the coefficient of sigma'_00 is +4 (the projection on K_8),
  *     not the printed -8 (constant MS8_C00 below).
+ *   - h_3..h_8 solve the relaxation conditions of Sec. 4 with the incoming
+ *     gbar's own central moments (zeroth moment pbar, first sum gbar e) and with
+ *     h_0..h_2 carried into the higher central moments.  The printed closed forms
+ *     of h_3..h_8 are the solution of the same conditions with those two effects
+ *     left out; they differ by O(F) in h_6, h_7 and O(F u) elsewhere.  Solved as
+ *     stated, the pair is stable where the printed forms diverge (density ratio
+ *     1000 at W = 4, Sec. 6.2; the cylinder of Sec. 7 at nu = 0.1 and ratio 800),
+ *     and the Sec. 7 ratio of minimum viscosities at ratio 900 is about the
+ *     "over 55" the paper reports.  The printed forms remain as a switch.
  *   - in g_7 the term -(3/2) u_y g_3 is read as -(3/2) u_x g_3.
  *   - sigma'_21 = sigma'_12 = sigma'_22 = 0 (third and higher order dropped).
  *   - the gradient of p uses pbar = sum gbar at time t.
@@ -50,6 +61,17 @@
  *   - walls are halfway bounce-back; ghost scalars are mirrored across walls.
  *   - F_ext = (rho - rho_ref) g, rho_ref selectable (mean of the phases by default).
  *   - initial state f_a = w_a phi0, gbar_a = 0.
+ *
+ * Study switches (orc_params; all off by default, and every test of the GPU path
+ * runs with them off).  They implement the other readings of three passages
+ * so that their effect can be measured:
+ *   q6_minus8   the coefficient of sigma'_00 in m^s'_8 as printed (-8), not the
+ *               projection on K_8 (+4);
+ *   q8_printed  h_3..h_8 from their printed closed forms (Eq.
+ *               cascadedcollisionoperator) instead of the solve of the relaxation
+ *               conditions;
+ *   q11_lagged  the pressure gradient in F_p from p of the previous step
+ *               (p = pbar + F_p . u / 2 there) instead of pbar of this step.
  *
  * Parity status: the per-node collision functions are pinned by brute-force
  * central-moment solves and invariants, the stencils by exact polynomials, the
@@ -106,6 +128,8 @@ typedef struct {
     double W, M;              /* interface width, mobility */
     double gx, gy;            /* body-force acceleration vector */
     double beta, psi_a, psi_G; /* Langmuir: sigma = sigma0 (1 + beta ln(1 - psi)), psi = psi_a + psi_G y */
+    int32_t q6_minus8, q8_printed, q11_lagged; /* study switches (see the file header); 0 = off */
+    int32_t pad3_;
 } orc_params;
 
 typedef struct {
@@ -119,6 +143,8 @@ typedef struct {
     double *gx_, *gy_, *nnx, *nny, *mag2; /* on (ny+2) rows: one ghost row per side */
     double *divn, *mu_phi;                /* divn on ny rows, mu_phi on (ny+2) rows */
     double *ux, *uy, *p, *psi, *Ftx, *Fty, *Fpx, *Fpy;
+    double *p_prev;  /* p of the previous step (q11_lagged) */
+    int have_p_prev;
 } orc_state;
 
 /* ---------------------------------------------------------------- indexing */
@@ -182,9 +208,116 @@ double orc_lap9(const double q9[Q]) {
  * net gradient-pressure force F_p, relaxation rates om[9].
  * Output: post-collision gbar (Eq. postcollisioncascadedLBscheme).
  */
-void orc_hydro_collide(const double gbar[Q], double p, double rho, double psi,
-                       double ux, double uy, double Ftx, double Fty,
-                       double Fpx, double Fpy, const double om[Q], double out[Q]) {
+/* Solves the n x n system A x = b in place by Gaussian elimination with partial
+ * pivoting (A row-major); returns -1 if a pivot vanishes. */
+static int solve_dense(int n, double *A, double *b, double *x) {
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (fabs(A[r * n + c]) > fabs(A[piv * n + c])) piv = r;
+        if (A[piv * n + c] == 0.0) return -1;
+        if (piv != c) {
+            for (int k = 0; k < n; ++k) { const double t = A[c * n + k]; A[c * n + k] = A[piv * n + k]; A[piv * n + k] = t; }
+            const double t = b[c]; b[c] = b[piv]; b[piv] = t;
+        }
+        for (int r = c + 1; r < n; ++r) {
+            const double f = A[r * n + c] / A[c * n + c];
+            for (int k = c; k < n; ++k) A[r * n + k] -= f * A[c * n + k];
+            b[r] -= f * b[c];
+        }
+    }
+    for (int r = n - 1; r >= 0; --r) {
+        double v = b[r];
+        for (int k = r + 1; k < n; ++k) v -= A[r * n + k] * x[k];
+        x[r] = v / A[r * n + r];
+    }
+    return 0;
+}
+
+/* Orthogonal basis vectors K_0..K_8 of Sec. 4 at the nine velocities
+ * (K_j(a) = row j): 1, e_x, e_y, 3(e_x^2 + e_y^2) - 4, e_x^2 - e_y^2, e_x e_y,
+ * -3 e_x^2 e_y + 2 e_y, -3 e_x e_y^2 + 2 e_x, 9 e_x^2 e_y^2 - 6(e_x^2 + e_y^2) + 4. */
+static const double KB[Q][Q] = {
+    {1, 1, 1, 1, 1, 1, 1, 1, 1},
+    {0, 1, 0, -1, 0, 1, -1, -1, 1},
+    {0, 0, 1, 0, -1, 1, 1, -1, -1},
+    {-4, -1, -1, -1, -1, 2, 2, 2, 2},
+    {0, 1, -1, 1, -1, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0, 1, -1, 1, -1},
+    {0, 0, 2, 0, -2, -1, -1, 1, 1},
+    {0, 2, 0, -2, 0, -1, 1, 1, -1},
+    {4, -2, -2, -2, -2, 1, 1, 1, 1}};
+
+/* h_3..h_8 from the relaxation conditions of Sec. 4: the six central moments
+ * about u of order two and higher (second-order trace and difference, 11, 21,
+ * 12, 22) of the post-collision distribution gbar + K h, before the source,
+ * equal omega_j times (equilibrium - pre-collision) plus the pre-collision
+ * values, i.e. the central moments of the change K h equal omega (eq - eta).
+ * eta are the central moments of the incoming gbar itself (its zeroth moment is
+ * pbar, its first j), and the given h_0..h_2 enter the central moments of K h.
+ * Equilibrium central moments of g^eq = c^2 f^M(rho, u) + psi f^M(rho, 0) / rho
+ * about u: c^2 rho times those of the unit Gaussian at u, plus psi times those of
+ * the unit Gaussian at rest.  The 6 x 6 system is solved numerically. */
+static void hydro_h_solve(const double gbar[Q], double rho, double psi, double ux, double uy,
+                          const double om[Q], double h[Q]) {
+    const double c2 = CS2;
+    double Cm[Q][Q]; /* rows 00, 10, 01, 20, 02, 11, 21, 12, 22 of (e - u) powers */
+    for (int a = 0; a < Q; ++a) {
+        const double dx = EX[a] - ux, dy = EY[a] - uy;
+        Cm[0][a] = 1.0;
+        Cm[1][a] = dx;
+        Cm[2][a] = dy;
+        Cm[3][a] = dx * dx;
+        Cm[4][a] = dy * dy;
+        Cm[5][a] = dx * dy;
+        Cm[6][a] = dx * dx * dy;
+        Cm[7][a] = dx * dy * dy;
+        Cm[8][a] = dx * dx * dy * dy;
+    }
+    double eta[Q];
+    for (int r = 0; r < Q; ++r) {
+        double v = 0;
+        for (int a = 0; a < Q; ++a) v += Cm[r][a] * gbar[a];
+        eta[r] = v;
+    }
+    double eq[Q];
+    eq[3] = c2 * c2 * rho + psi * (c2 + ux * ux);
+    eq[4] = c2 * c2 * rho + psi * (c2 + uy * uy);
+    eq[5] = psi * ux * uy;
+    eq[6] = -psi * (c2 + ux * ux) * uy;
+    eq[7] = -psi * ux * (c2 + uy * uy);
+    eq[8] = c2 * c2 * c2 * rho + psi * (c2 + ux * ux) * (c2 + uy * uy);
+    double R6[6][Q];
+    for (int a = 0; a < Q; ++a) {
+        R6[0][a] = Cm[3][a] + Cm[4][a];
+        R6[1][a] = Cm[3][a] - Cm[4][a];
+        R6[2][a] = Cm[5][a];
+        R6[3][a] = Cm[6][a];
+        R6[4][a] = Cm[7][a];
+        R6[5][a] = Cm[8][a];
+    }
+    const double d_eq[6] = {eq[3] + eq[4], eq[3] - eq[4], eq[5], eq[6], eq[7], eq[8]};
+    const double d_eta[6] = {eta[3] + eta[4], eta[3] - eta[4], eta[5], eta[6], eta[7], eta[8]};
+    const double rate[6] = {om[3], om[4], om[5], om[6], om[7], om[8]};
+    double A[36], b[6], x[6];
+    for (int r = 0; r < 6; ++r) {
+        double low = 0; /* contribution of h_0..h_2 */
+        for (int a = 0; a < Q; ++a) low += R6[r][a] * (KB[0][a] * h[0] + KB[1][a] * h[1] + KB[2][a] * h[2]);
+        b[r] = rate[r] * (d_eq[r] - d_eta[r]) - low;
+        for (int j = 3; j < Q; ++j) {
+            double v = 0;
+            for (int a = 0; a < Q; ++a) v += R6[r][a] * KB[j][a];
+            A[r * 6 + (j - 3)] = v;
+        }
+    }
+    if (solve_dense(6, A, b, x) != 0) { for (int j = 3; j < Q; ++j) h[j] = NAN; return; }
+    for (int j = 3; j < Q; ++j) h[j] = x[j - 3];
+}
+
+static void hydro_collide_opt(const double gbar[Q], double p, double rho, double psi,
+                              double ux, double uy, double Ftx, double Fty,
+                              double Fpx, double Fpy, const double om[Q], double ms8_c00, int h_solve,
+                              double out[Q]) {
     const double c2 = CS2;
 
     /* O9: raw moments of the cumulative source (binomial transform of the matched
@@ -208,7 +341,7 @@ void orc_hydro_collide(const double gbar[Q], double p, double rho, double psi,
     ms[5] = (1.0 - 0.5 * om[5]) * s11;
     ms[6] = (1.0 - 0.5 * om[6]) * (-3.0 * s21 + 2.0 * s01);
     ms[7] = (1.0 - 0.5 * om[7]) * (-3.0 * s12 + 2.0 * s10);
-    ms[8] = (1.0 - 0.5 * om[8]) * (9.0 * s22 - 6.0 * (s20 + s02) + MS8_C00 * s00);
+    ms[8] = (1.0 - 0.5 * om[8]) * (9.0 * s22 - 6.0 * (s20 + s02) + ms8_c00 * s00);
 
     /* delta g^s = K^{-1} m^s' written out row by row. */
     double dgs[Q];
@@ -234,7 +367,9 @@ void orc_hydro_collide(const double gbar[Q], double p, double rho, double psi,
         e22 += g * ex * ex * ey * ey;
     }
 
-    /* Moment changes h_0..h_8 as printed (Eq. cascadedcollisionoperator). */
+    /* Moment changes h_0..h_8 as printed (Eq. cascadedcollisionoperator);
+     * h_0..h_2 are kept, h_3..h_8 replaced by the solve below unless the printed
+     * forms are asked for. */
     const double ux2 = ux * ux, uy2 = uy * uy;
     double h[Q];
     h[0] = 0.5 * om[0] * Gp / 9.0;
@@ -254,6 +389,8 @@ void orc_hydro_collide(const double gbar[Q], double p, double rho, double psi,
                           - 4.0 * ux * uy * e11 + 4.0 * c2 * rho * ux2 * uy2 - ux2 * uy2 * p)
            - 2.0 * h[3] - 0.5 * uy2 * (3.0 * h[3] + h[4]) - 0.5 * ux2 * (3.0 * h[3] - h[4])
            - 4.0 * ux * uy * h[5] - 2.0 * uy * h[6] - 2.0 * ux * h[7];
+    /* the printed closed forms above; solved as stated, h_3..h_8 are replaced */
+    if (h_solve) hydro_h_solve(gbar, rho, psi, ux, uy, om, h);
 
     /* O12: post-collision values, K . h expanded row by row, plus the source. */
     out[0] = gbar[0] + (h[0] - 4.0 * (h[3] - h[8])) + dgs[0];
@@ -265,6 +402,21 @@ void orc_hydro_collide(const double gbar[Q], double p, double rho, double psi,
     out[6] = gbar[6] + (h[0] - h[1] + h[2] + 2.0 * h[3] - h[5] - h[6] + h[7] + h[8]) + dgs[6];
     out[7] = gbar[7] + (h[0] - h[1] - h[2] + 2.0 * h[3] + h[5] + h[6] + h[7] + h[8]) + dgs[7];
     out[8] = gbar[8] + (h[0] + h[1] - h[2] + 2.0 * h[3] - h[5] + h[6] - h[7] + h[8]) + dgs[8];
+}
+
+void orc_hydro_collide(const double gbar[Q], double p, double rho, double psi,
+                       double ux, double uy, double Ftx, double Fty,
+                       double Fpx, double Fpy, const double om[Q], double out[Q]) {
+    hydro_collide_opt(gbar, p, rho, psi, ux, uy, Ftx, Fty, Fpx, Fpy, om, MS8_C00, 1, out);
+}
+
+/* The same collision under the study switches q6_minus8 / q8_printed. */
+void orc_hydro_collide_study(const double gbar[Q], double p, double rho, double psi,
+                             double ux, double uy, double Ftx, double Fty,
+                             double Fpx, double Fpy, const double om[Q], int q6_minus8, int q8_printed,
+                             double out[Q]) {
+    hydro_collide_opt(gbar, p, rho, psi, ux, uy, Ftx, Fty, Fpx, Fpy, om, q6_minus8 ? -8.0 : MS8_C00,
+                      !q8_printed, out);
 }
 
 /* ------------------------------------------------ phase-field collision (O13) */
@@ -419,7 +571,7 @@ void orc_destroy(orc_state *S) {
     if (!S) return;
     double **bufs[] = {&S->f, &S->g, &S->ft, &S->gt, &S->phi, &S->pbar, &S->rho,
                        &S->gx_, &S->gy_, &S->nnx, &S->nny, &S->mag2, &S->divn, &S->mu_phi,
-                       &S->ux, &S->uy, &S->p, &S->psi, &S->Ftx, &S->Fty, &S->Fpx, &S->Fpy};
+                       &S->ux, &S->uy, &S->p, &S->psi, &S->Ftx, &S->Fty, &S->Fpx, &S->Fpy, &S->p_prev};
     for (size_t i = 0; i < sizeof(bufs) / sizeof(bufs[0]); ++i) free(*bufs[i]);
     free(S);
 }
@@ -447,7 +599,7 @@ int orc_create(const orc_params *P, orc_state **out) {
     ALLOC(S->phi, N); ALLOC(S->pbar, N); ALLOC(S->rho, N);
     ALLOC(S->gx_, NG); ALLOC(S->gy_, NG); ALLOC(S->nnx, NG); ALLOC(S->nny, NG); ALLOC(S->mag2, NG);
     ALLOC(S->divn, N); ALLOC(S->mu_phi, NG);
-    ALLOC(S->ux, N); ALLOC(S->uy, N); ALLOC(S->p, N); ALLOC(S->psi, N);
+    ALLOC(S->ux, N); ALLOC(S->uy, N); ALLOC(S->p, N); ALLOC(S->psi, N); ALLOC(S->p_prev, N);
     ALLOC(S->Ftx, N); ALLOC(S->Fty, N); ALLOC(S->Fpx, N); ALLOC(S->Fpy, N);
 #undef ALLOC
     if (!ok) { orc_destroy(S); return -2; }
@@ -464,6 +616,7 @@ void orc_init(orc_state *S, const double *phi0) {
             S->g[a * N + k] = 0.0;
         }
     S->step = 0;
+    S->have_p_prev = 0;
 }
 
 /* Imposed velocity for ORC_IMPOSED (ny*nx each, row-major); kept until replaced. */
@@ -476,6 +629,7 @@ void orc_set_dist(orc_state *S, const double *f, const double *g, int64_t step) 
     memcpy(S->f, f, sizeof(double) * Q * S->N);
     memcpy(S->g, g, sizeof(double) * Q * S->N);
     S->step = step;
+    S->have_p_prev = 0;
 }
 
 void orc_get_dist(const orc_state *S, double *f, double *g) {
@@ -597,7 +751,10 @@ static void orc_fields_internal(orc_state *S) {
 
             /* O8: F_p = -grad pbar + c_s^2 grad rho ; p = pbar + (1/2) F_p . u. */
             double q9[Q], dpx, dpy;
-            for (int a = 0; a < Q; ++a) q9[a] = pbar_at(S, i + EX[a], j + EY[a]);
+            const int lag = P->q11_lagged && S->have_p_prev;
+            for (int a = 0; a < Q; ++a)
+                q9[a] = lag ? S->p_prev[(int64_t)row_of(P, j + EY[a]) * nx + col_of(P, i + EX[a])]
+                            : pbar_at(S, i + EX[a], j + EY[a]);
             orc_grad9(q9, &dpx, &dpy);
             const double Fpx = -dpx + CS2 * drhox;
             const double Fpy = -dpy + CS2 * drhoy;
@@ -640,8 +797,9 @@ void orc_step(orc_state *S, int64_t nsteps) {
                     orc_hydro_srt(gin, S->p[k], S->rho[k], S->ux[k], S->uy[k], S->Ftx[k],
                                   S->Fty[k], S->Fpx[k], S->Fpy[k], omv, gout);
                 } else {
-                    orc_hydro_collide(gin, S->p[k], S->rho[k], S->psi[k], S->ux[k], S->uy[k],
-                                      S->Ftx[k], S->Fty[k], S->Fpx[k], S->Fpy[k], om_h, gout);
+                    hydro_collide_opt(gin, S->p[k], S->rho[k], S->psi[k], S->ux[k], S->uy[k],
+                                      S->Ftx[k], S->Fty[k], S->Fpx[k], S->Fpy[k], om_h,
+                                      P->q6_minus8 ? -8.0 : MS8_C00, !P->q8_printed, gout);
                 }
                 const double om_f[Q] = {1, omphi, omphi, 1, 1, 1, 1, 1, 1};
                 const double theta = 4.0 * ph * (1.0 - ph) / P->W;
@@ -693,6 +851,10 @@ void orc_step(orc_state *S, int64_t nsteps) {
                     }
                 }
             }
+        if (P->q11_lagged) { /* p at time t serves the pressure gradient of step t + 1 */
+            memcpy(S->p_prev, S->p, sizeof(double) * (size_t)N);
+            S->have_p_prev = 1;
+        }
         S->step++;
     }
 }
@@ -749,7 +911,8 @@ static double crossing(const orc_state *S, int i, int dir) {
 
 /*
  * FP64 diagnostics at time t, out[10] =
- *  {step, sum phi, sum rho, max |u|, dp = p(centre) - p(corner), R_eff = sqrt(sum phi / pi),
+ *  {step, sum phi, sum rho, max |u| (NaN if any |u| is NaN), dp = p(centre) - p(corner),
+ *   R_eff = sqrt(sum phi / pi),
  *   spike y (lowest phi = 1/2 crossing on column nx/2), bubble y (highest crossing on column 0),
  *   centroid y = sum y phi / sum phi, nan flag}.
  * Sums run in row-major order.
@@ -767,7 +930,7 @@ void orc_diagnostics(orc_state *S, double *out) {
             srho += S->rho[k];
             sy += (double)j * ph;
             const double um = sqrt(S->ux[k] * S->ux[k] + S->uy[k] * S->uy[k]);
-            if (!(um <= umax)) umax = um; /* also propagates NaN */
+            if (!(um <= umax) && !isnan(umax)) umax = um; /* a NaN, once met, is kept */
             if (isnan(ph) || isnan(S->p[k]) || isnan(um) || isinf(ph) || isinf(S->p[k])) nan = 1;
         }
     out[0] = (double)S->step;

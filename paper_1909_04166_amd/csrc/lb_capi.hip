@@ -71,7 +71,8 @@ lb_status validate(const lb_config* c) {
         return LB_E_INVALID_ARG;
     if (c->bc_y != LB_PERIODIC && c->bc_y != LB_HALFWAY_BB && c->bc_y != LB_FREE_SLIP)
         return LB_E_INVALID_ARG;
-    if (c->collision != LB_CASCADED && c->collision != LB_SRT) return LB_E_INVALID_ARG;
+    if (c->collision != LB_CASCADED && c->collision != LB_SRT && c->collision != LB_CASCADED_PRINTED)
+        return LB_E_INVALID_ARG;
     if (c->flow != LB_FLOW_COUPLED && c->flow != LB_FLOW_IMPOSED) return LB_E_INVALID_ARG;
     if (c->surf != LB_SIGMA_LINEAR && c->surf != LB_SIGMA_LANGMUIR) return LB_E_INVALID_ARG;
     if (c->tile_pf < 0 || c->tile_pf > 1) return LB_E_INVALID_ARG;
@@ -102,6 +103,15 @@ lb_status validate(const lb_config* c) {
     if (c->tile_x != 0 && !valid_width(c->tile_x, c->precision, c->tile_pf)) return LB_E_INVALID_ARG;
     if (c->tile_h < 0 || (c->tile_h > 0 && c->tile_h < kMinH)) return LB_E_INVALID_ARG;
     if (c->diag_every < 0) return LB_E_INVALID_ARG;
+    if (c->init_kind < LB_INIT_NONE || c->init_kind > LB_INIT_INTERFACE) return LB_E_INVALID_ARG;
+    for (double v : c->init_par)
+        if (!std::isfinite(v)) return LB_E_INVALID_ARG;
+    if (c->init_kind == LB_INIT_DROPLET &&
+        (!(c->init_par[2] > 0) || std::fabs(c->init_par[3]) != 1.0 || c->init_par[4] < 0 || c->init_par[5] < 0))
+        return LB_E_INVALID_ARG;
+    if (c->init_kind == LB_INIT_ELLIPSE &&
+        (!(c->init_par[2] > 0) || !(c->init_par[3] > 0) || c->init_par[4] < 0 || c->init_par[5] < 0))
+        return LB_E_INVALID_ARG;
     return LB_OK;
 }
 
@@ -116,7 +126,8 @@ double rho_ref_of(const lb_config* c) {
 
 int kind_of(const lb_config* c) {
     const bool srt = c->collision == LB_SRT;
-    if (c->flow == LB_FLOW_IMPOSED) return srt ? KIND_ACE_SRT : KIND_ACE_CASCADED;
+    if (c->flow == LB_FLOW_IMPOSED) return srt ? KIND_ACE_SRT : KIND_ACE_CASCADED;  // one phase-field cascade
+    if (c->collision == LB_CASCADED_PRINTED) return KIND_COUPLED_PRINTED;
     return srt ? KIND_COUPLED_SRT : KIND_COUPLED_CASCADED;
 }
 
@@ -542,9 +553,12 @@ lb_status lb_create(const lb_config* cfg, void* dev_ws, uint64_t ws_bytes, void*
 }
 
 lb_status lb_init_fields(lb_handle* h, const double* phi0) {
-    if (!h || !phi0) return LB_E_INVALID_ARG;
+    if (!h || (!phi0 && h->cfg.init_kind == LB_INIT_NONE)) return LB_E_INVALID_ARG;
     const int64_t N = (int64_t)h->cfg.nx * h->cfg.ny;
-    HIPC(hipMemcpyAsync(h->d_fields, phi0, N * sizeof(double), hipMemcpyHostToDevice, h->s));
+    if (phi0)
+        HIPC(hipMemcpyAsync(h->d_fields, phi0, N * sizeof(double), hipMemcpyHostToDevice, h->s));
+    else
+        HIPC(launch_phi_builtin(h->d_fields, &h->cfg, h->s));
     HIPC(launch_state_op(h->cfg.precision, 0, h->d_desc, h->d_fields, 0, 0, h->parity, N, h->s));
     // the phase-field-only kernel never writes gbar: keep it zero in both buffers
     if (h->cfg.flow == LB_FLOW_IMPOSED)
@@ -799,6 +813,14 @@ lb_status lb_struct_sizes(uint64_t* config_bytes, uint64_t* diag_bytes) {
 lb_status lb_copy_kernel(void* dst, const void* src, uint64_t n, void* stream) {
     if (!dst || !src || ((uintptr_t)dst % 16) || ((uintptr_t)src % 16)) return LB_E_INVALID_ARG;
     HIPC(launch_copy(dst, src, n, (hipStream_t)stream));
+    return LB_OK;
+}
+
+lb_status lb_bandwidth_probe(void* dst, const void* src, uint64_t n, int32_t variant, void* stream) {
+    if (!dst || !src || ((uintptr_t)dst % 16) || ((uintptr_t)src % 16) || variant < 0 || variant > 6)
+        return LB_E_INVALID_ARG;
+    if (n < ((uint64_t)16 << 20)) return LB_E_INVALID_ARG;  // at least 16 MiB (the read probe's output fits)
+    HIPC(launch_bandwidth_probe(dst, src, n, variant, (hipStream_t)stream));
     return LB_OK;
 }
 
@@ -1088,7 +1110,7 @@ lb_status lb_batch_create(int32_t slots, int64_t node_capacity, int32_t precisio
 }
 
 lb_status lb_batch_add(lb_batch* b, const lb_config* cfg, const double* phi0, int32_t* slot) {
-    if (!b || !cfg || !phi0 || !slot) return LB_E_INVALID_ARG;
+    if (!b || !cfg || !slot || (!phi0 && cfg->init_kind == LB_INIT_NONE)) return LB_E_INVALID_ARG;
     lb_status st = validate(cfg);
     if (st != LB_OK) return st;
     if (cfg->precision != b->prec) return LB_E_INVALID_ARG;
@@ -1127,7 +1149,8 @@ lb_status lb_batch_add(lb_batch* b, const lb_config* cfg, const double* phi0, in
     if (cfg->surf == LB_SIGMA_LANGMUIR && launch_kappa_table(b->d_descs + free_slot, cfg->ny, b->s) != hipSuccess)
         return undo(LB_E_HIP);
     const int64_t N = (int64_t)cfg->nx * cfg->ny;
-    if (hipMemcpyAsync(b->d_fields, phi0, N * sizeof(double), hipMemcpyHostToDevice, b->s) != hipSuccess)
+    if (phi0 ? hipMemcpyAsync(b->d_fields, phi0, N * sizeof(double), hipMemcpyHostToDevice, b->s) != hipSuccess
+             : launch_phi_builtin(b->d_fields, cfg, b->s) != hipSuccess)
         return undo(LB_E_HIP);
     // the lattice starts in the buffer the batch's current parity reads
     if (launch_state_op(b->prec, 0, b->d_descs + free_slot, b->d_fields, 0, 0, b->parity, N, b->s) != hipSuccess)

@@ -105,11 +105,12 @@ struct alignas(16) LatDesc {
 enum { MODE_STEP = 0, MODE_FIELDS = 1, MODE_COUPLING = 2 };
 // Collision models of the coupled step: the cascaded pair, or the SRT pair of the
 // stability comparison.
-enum { COLL_CASCADED = 0, COLL_SRT = 1 };
+enum { COLL_CASCADED = 0, COLL_SRT = 1, COLL_PRINTED = 2 };
 enum { PF_HOLD = 0, PF_PREFETCH = 1 };
 enum { WALL_NONE = 0, WALL_BOUNCE = 1, WALL_SLIP = 2 };
 // Kernel behind a step: coupled pair or phase field alone, cascaded or SRT.
-enum { KIND_COUPLED_CASCADED = 0, KIND_COUPLED_SRT = 1, KIND_ACE_CASCADED = 2, KIND_ACE_SRT = 3 };
+enum { KIND_COUPLED_CASCADED = 0, KIND_COUPLED_SRT = 1, KIND_ACE_CASCADED = 2, KIND_ACE_SRT = 3,
+       KIND_COUPLED_PRINTED = 4 };
 
 // D2Q9 weights and velocities in the order 0 rest, 1 +x, 2 +y, 3 -x, 4 -y,
 // 5 (+,+), 6 (-,+), 7 (-,-), 8 (+,-).
@@ -447,10 +448,12 @@ __device__ __forceinline__ NodeOut<R> node_macro(const KConst<R>& K, int chem, c
 // instruction is spent on it.
 
 // Pressure-based cascaded collision with its cumulative source (Sec. 4), with
-// omega_0..3 = omega_6..8 = 1 and omega_4 = omega_5 = omv.
+// omega_0..3 = omega_6..8 = 1 and omega_4 = omega_5 = omv.  SOLVED (the
+// collision of the cascaded pair): h_3..h_8 solve the relaxation conditions as
+// stated; otherwise (the printed option) their printed closed forms are used.
 //
-// Written out, the cascade (moment changes h_0..h_8 of Eq.
-// cascadedcollisionoperator plus the source K^{-1}(I - Lambda/2) K S) leaves
+// Written out with the printed closed forms, the cascade (moment changes h_0..h_8
+// of Eq. cascadedcollisionoperator plus the source K^{-1}(I - Lambda/2) K S) leaves
 // post-collision raw moments that depend on the incoming values only through
 // pbar, j and the two shear non-equilibria
 //   N = (eta_20 - eta_02) - c^2 rho (ux^2 - uy^2),   X = eta_11 - c^2 rho ux uy,
@@ -470,7 +473,21 @@ __device__ __forceinline__ NodeOut<R> node_macro(const KConst<R>& K, int chem, c
 // operations instead of 150 and never forms the O(rho) terms of psi = p - c^2 rho
 // that cancel in the cascade.  Shifted storage subtracts the raw moments of w sh
 // (sh, 0, 0, sh/3, sh/3, 0, 0, 0, sh/9); N, X and j are shift-free.
-template <class R, bool SH = false>
+//
+// SOLVED: the relaxation conditions of the cascaded collision (Sec. 4) solved as
+// stated, with the central moments of the incoming gbar itself (zeroth moment
+// pbar, first j) and the source-driven h_0..h_2 carried into the higher central
+// moments, instead of the printed closed forms of h_3..h_8 (which leave those two
+// effects out).  The post-collision raw moments then differ from the ones above by
+//   T   - (2/3) G
+//   D   - (1 - omv)/6  [3 (ux^2 - uy^2) G - 2 (F_tx ux - F_ty uy)]
+//   m11 - (1 - omv)/6  [3 ux uy G - (F_tx uy + F_ty ux)]
+//   m21 - c^4 F_ty - (1 - omv)/36 [9 uy (5 ux^2 - uy^2) G - 18 F_tx ux uy - 12 F_ty ux^2 + 6 F_ty uy^2]
+//   m12 - c^4 F_tx + (1 - omv)/36 [9 ux (ux^2 - 5 uy^2) G - 6 F_tx ux^2 + 12 F_tx uy^2 + 18 F_ty ux uy]
+//   m22 - 2 c^4 G  + (1 - omv)/36 [9 (ux^4 - 10 ux^2 uy^2 + uy^4) G - 6 (F_tx ux^3 + F_ty uy^3)
+//                                  + 30 ux uy (F_tx uy + F_ty ux)]
+// (a symbolic identity with the numerical solve of the same conditions).
+template <class R, bool SH = false, bool SOLVED = false>
 __device__ __forceinline__ void hydro_collide(R g[9], const NodeOut<R>& o, R sh = R(0)) {
     const R ux = o.ux, uy = o.uy, ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy;
     const R third = R(1.0 / 3.0), ninth = R(1.0 / 9.0);
@@ -483,15 +500,31 @@ __device__ __forceinline__ void hydro_collide(R g[9], const NodeOut<R>& o, R sh 
     const R xx = om1 * (((g[5] - g[6]) + (g[7] - g[8])) - rc2 * uxy);
     const R m00 = o.p + R(0.5) * Gam - (SH ? sh : R(0));
     const R m10 = o.jx + third * o.Ftx, m01 = o.jy + third * o.Fty;
-    const R T = R(2.0 / 3.0) * o.p + rc2 * (ux2 + uy2) + R(4.0 / 3.0) * Gam +
+    R T = R(2.0 / 3.0) * o.p + rc2 * (ux2 + uy2) + R(4.0 / 3.0) * Gam +
                 third * (o.Ftx * ux + o.Fty * uy) - (SH ? R(2.0 / 3.0) * sh : R(0));
-    const R D = rc2 * (ux2 - uy2) + nn + hw * R(2.0 / 3.0) * (Sx * ux - Sy * uy);
-    const R m11 = rc2 * uxy + xx + hw * third * (Sx * uy + Sy * ux);
-    const R m21 = rc2 * uy * (third + ux2) + ninth * o.Fty + R(0.5) * uy * nn + R(2) * ux * xx;
-    const R m12 = rc2 * ux * (third + uy2) + ninth * o.Ftx - R(0.5) * ux * nn + R(2) * uy * xx;
-    const R m22 = ninth * o.p + o.rho * (ninth * (ux2 + uy2) + third * ux2 * uy2) +
-                  R(2.0 / 9.0) * Gam - R(0.5) * (ux2 - uy2) * nn + R(4) * uxy * xx -
-                  (SH ? ninth * sh : R(0));
+    R D = rc2 * (ux2 - uy2) + nn + hw * R(2.0 / 3.0) * (Sx * ux - Sy * uy);
+    R m11 = rc2 * uxy + xx + hw * third * (Sx * uy + Sy * ux);
+    R m21 = rc2 * uy * (third + ux2) + ninth * o.Fty + R(0.5) * uy * nn + R(2) * ux * xx;
+    R m12 = rc2 * ux * (third + uy2) + ninth * o.Ftx - R(0.5) * ux * nn + R(2) * uy * xx;
+    R m22 = ninth * o.p + o.rho * (ninth * (ux2 + uy2) + third * ux2 * uy2) +
+            R(2.0 / 9.0) * Gam - R(0.5) * (ux2 - uy2) * nn + R(4) * uxy * xx -
+            (SH ? ninth * sh : R(0));
+    if constexpr (SOLVED) {
+        const R fu = o.Ftx * ux - o.Fty * uy, fv = o.Ftx * uy + o.Fty * ux;
+        const R o6 = om1 * R(1.0 / 6.0), o36 = om1 * R(1.0 / 36.0);
+        T -= R(2.0 / 3.0) * Gam;
+        D -= o6 * (R(3) * (ux2 - uy2) * Gam - R(2) * fu);
+        m11 -= o6 * (R(3) * uxy * Gam - fv);
+        m21 -= ninth * o.Fty +
+               o36 * (R(9) * uy * (R(5) * ux2 - uy2) * Gam - R(18) * o.Ftx * uxy - R(12) * o.Fty * ux2 +
+                      R(6) * o.Fty * uy2);
+        m12 += o36 * (R(9) * ux * (ux2 - R(5) * uy2) * Gam - R(6) * o.Ftx * ux2 + R(12) * o.Ftx * uy2 +
+                      R(18) * o.Fty * uxy) -
+               ninth * o.Ftx;
+        m22 += o36 * (R(9) * (ux2 * ux2 - R(10) * ux2 * uy2 + uy2 * uy2) * Gam -
+                      R(6) * (o.Ftx * ux * ux2 + o.Fty * uy * uy2) + R(30) * uxy * fv) -
+               R(2.0 / 9.0) * Gam;
+    }
     // inverse of the moment map (m20 = (T + D)/2, m02 = (T - D)/2)
     const R a = R(0.5) * (T + D) - m22, b = m10 - m12;
     const R c = R(0.5) * (T - D) - m22, d = m01 - m21;
@@ -807,7 +840,7 @@ lb_fused(const LatDesc* __restrict__ descs, const WorkItem* __restrict__ items, 
                         if constexpr (COLL == COLL_SRT)
                             hydro_srt<R, ST::shifted>(g1, o, K.shg);
                         else
-                            hydro_collide<R, ST::shifted>(g1, o, K.shg);
+                            hydro_collide<R, ST::shifted, COLL != COLL_PRINTED>(g1, o, K.shg);
                         store_row<ST, 9, kBufIO<ST>>(row_at(dst, C, nx), nx, 9, xc, g1);
                     }
                 } else if constexpr (MODE == MODE_FIELDS) {

@@ -21,12 +21,13 @@ LB_OK, LB_E_INVALID_ARG, LB_E_WORKSPACE, LB_E_HIP, LB_E_UNSTABLE, LB_E_UNSUPPORT
 LB_E_TOO_LARGE = -7
 LB_PERIODIC, LB_HALFWAY_BB, LB_FREE_SLIP = 0, 1, 2
 LB_BC = {"periodic": LB_PERIODIC, "wall": LB_HALFWAY_BB, "slip": LB_FREE_SLIP}
-LB_COLLISION = {"cascaded": 0, "srt": 1}
+LB_COLLISION = {"cascaded": 0, "srt": 1, "printed": 2}
 LB_FLOW = {"coupled": 0, "imposed": 1}
 LB_SIGMA = {"linear": 0, "langmuir": 1}
 LB_FREF = {"mean": 0, "light": 1, "heavy": 2, "none": 3}
 LB_ST = {"geometric": 0, "chempot": 1}
 PRECISION = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
+LB_INIT = {"none": 0, "droplet": 1, "ellipse": 2, "interface": 3}
 STORE_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2}
 
 
@@ -48,6 +49,7 @@ class lb_config(ctypes.Structure):
         ("collision", ctypes.c_int32), ("flow", ctypes.c_int32),
         ("surf", ctypes.c_int32), ("tile_pf", ctypes.c_int32),
         ("beta", ctypes.c_double), ("psi_a", ctypes.c_double), ("psi_G", ctypes.c_double),
+        ("init_kind", ctypes.c_int32), ("init_pad_", ctypes.c_int32), ("init_par", ctypes.c_double * 8),
     ]
 
 
@@ -112,18 +114,29 @@ _SIGS = {
     "lb_batch_launch_counts": ([_vp, _i64p, _i64p], ctypes.c_int32),
     "lb_struct_sizes": ([_u64p, _u64p], ctypes.c_int32),
     "lb_copy_kernel": ([_vp, _vp, ctypes.c_uint64, _vp], ctypes.c_int32),
+    "lb_bandwidth_probe": ([_vp, _vp, ctypes.c_uint64, ctypes.c_int32, _vp], ctypes.c_int32),
     "lb_step_noalloc": ([ctypes.POINTER(lb_config), _vp, _vp, ctypes.c_uint64, ctypes.c_int64, _vp],
                         ctypes.c_int32),
 }
 
 
 def lib():
-    """Load libcmlb.so (raises if it has not been built)."""
+    """Load libcmlb.so (raises if it has not been built, or was built from other
+    sources than the ones in the tree)."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -m paper_1909_04166_amd.build` (no CPU fallback exists)")
+        from paper_1909_04166_amd import build as _build
+        try:
+            with open(LIB_PATH + _build.STAMP_SUFFIX) as fh:
+                stamp = fh.read().strip()
+        except OSError:
+            stamp = None
+        if stamp != _build.source_hash():
+            raise RuntimeError(f"{LIB_PATH} does not match the sources in the tree (stale or foreign "
+                               "build): rebuild it with `python -m paper_1909_04166_amd.build`")
         L = ctypes.CDLL(LIB_PATH)
         for name, (args, res) in _SIGS.items():
             fn = getattr(L, name)
@@ -184,6 +197,10 @@ def config_from_case(case: dict, precision: str = "fp64", diag_every: int = 0,
     c.surf = LB_SIGMA[case.get("surf", "linear")]
     c.beta = float(case.get("beta", 0.0))
     c.psi_a, c.psi_G = float(case.get("psi_a", 0.0)), float(case.get("psi_G", 0.0))
+    kind, par = case.get("init", ("none", ()))
+    c.init_kind = LB_INIT[kind]
+    for i, v in enumerate(par):
+        c.init_par[i] = float(v)
     return c
 
 
@@ -201,8 +218,9 @@ def lb_create(cfg: lb_config, ws_ptr: int, ws_bytes: int, stream: int) -> int:
     return h.value
 
 
-def lb_init_fields(h: int, phi0: np.ndarray) -> None:
-    a = np.ascontiguousarray(phi0, dtype=np.float64)
+def lb_init_fields(h: int, phi0: np.ndarray | None) -> None:
+    """phi0 None: the built-in initial field of the lattice's init_kind."""
+    a = None if phi0 is None else np.ascontiguousarray(phi0, dtype=np.float64)
     _check("lb_init_fields", lib().lb_init_fields(_vp(h), _dptr(a)))
 
 
@@ -311,6 +329,10 @@ def lb_batch_get_schedule(b: int) -> tuple[int, int, int, int]:
     return int(a.value), int(r.value), int(g.value), int(p.value)
 
 
+def lb_bandwidth_probe(dst: int, src: int, n: int, variant: int, stream: int) -> None:
+    _check("lb_bandwidth_probe", lib().lb_bandwidth_probe(_vp(dst), _vp(src), int(n), int(variant), _vp(stream)))
+
+
 def lb_batch_launch_counts(b: int) -> tuple[int, int]:
     """(steps replayed from graphs, steps launched one by one) since creation."""
     g, e = ctypes.c_int64(), ctypes.c_int64()
@@ -345,9 +367,10 @@ def lb_batch_create(slots: int, node_capacity: int, precision: str, tile: tuple[
     return h.value
 
 
-def lb_batch_add(b: int, cfg: lb_config, phi0: np.ndarray) -> int:
-    """Returns the slot index; raises LBError (code LB_E_WORKSPACE when full)."""
-    a = np.ascontiguousarray(phi0, dtype=np.float64)
+def lb_batch_add(b: int, cfg: lb_config, phi0: np.ndarray | None) -> int:
+    """Returns the slot index; raises LBError (code LB_E_WORKSPACE when full).
+    phi0 None: the built-in initial field of cfg.init_kind."""
+    a = None if phi0 is None else np.ascontiguousarray(phi0, dtype=np.float64)
     s = ctypes.c_int32()
     _check("lb_batch_add", lib().lb_batch_add(_vp(b), ctypes.byref(cfg), _dptr(a), ctypes.byref(s)))
     return int(s.value)
@@ -437,8 +460,9 @@ class Lattice:
         except Exception:
             pass
 
-    def init(self, phi0: np.ndarray) -> None:
-        lb_init_fields(self.h, np.asarray(phi0, dtype=np.float64).reshape(self.shape))
+    def init(self, phi0: np.ndarray | None) -> None:
+        """phi0 None: the built-in initial field described by the case's "init" entry."""
+        lb_init_fields(self.h, None if phi0 is None else np.asarray(phi0, dtype=np.float64).reshape(self.shape))
 
     def step(self, n: int = 1) -> int:
         return lb_step(self.h, n)
@@ -517,7 +541,7 @@ class Batch:
             shift_g: float = 0.0) -> int:
         cfg = config_from_case(case, self.precision, diag_every, (0, 0), shift_f, shift_g)
         shape = (int(case["ny"]), int(case["nx"]))
-        slot = lb_batch_add(self.b, cfg, np.asarray(phi0, dtype=np.float64).reshape(shape))
+        slot = lb_batch_add(self.b, cfg, None if phi0 is None else np.asarray(phi0, dtype=np.float64).reshape(shape))
         self.shapes[slot] = shape
         return slot
 

@@ -18,9 +18,15 @@ A case is a plain dictionary::
     force_ref         "mean" | "light" | "heavy" | "none" (rho_ref)
     st_form           "geometric" | "chempot" (surface-tension form)
     collision         "cascaded" (default) | "srt" (single-relaxation-time comparison model)
+                      | "printed" (the cascaded pair with the printed closed forms of
+                      the hydrodynamic moment changes h_3..h_8)
     flow              "coupled" (default) | "imposed" (phase field only, velocity given)
     surf              "linear" (sigma(T(y)), default) | "langmuir":
                       sigma = sigma0 (1 + beta ln(1 - psi)), psi = psi_a + psi_G y
+    init              optional (kind, parameters) of the same initial phase field as
+                      a shape the library can build itself: ("droplet", (xc, yc, R,
+                      sign, px, py)), ("ellipse", (xc, yc, a, b, px, py)) or
+                      ("interface", (y0, A, k)); the oracle ignores it
 
 Initial phase fields use the equilibrium tanh profile of the conservative
 Allen-Cahn equation (Sec. 2, Eq. hyperbolictangentprofile) with phi_A = 1,
@@ -63,7 +69,8 @@ def droplet(n: int = 128, R: float = 25.0, W: float = 4.0, ratio: float = 1000.0
     centred in a periodic box.  Light phase density 1, heavy = ratio."""
     nx, ny = int(n), int(ny or n)
     case = base_case(nx, ny, rho_A=float(ratio), rho_B=1.0, nu_A=nu, nu_B=nu,
-                     sigma0=sigma, W=W, M=M, st_form=st_form)
+                     sigma0=sigma, W=W, M=M, st_form=st_form,
+                     init=("droplet", (nx / 2, ny / 2, R, 1.0, 0.0, 0.0)))
     x, y = _grid(nx, ny)
     r = np.hypot(x - nx / 2, y - ny / 2)
     return case, tanh_profile(R - r, W)
@@ -77,7 +84,7 @@ def ellipse(n: int, aspect: float, ratio: float = 1000.0, W: float = 4.0, nu: fl
     R_eq = float(R_eq if R_eq is not None else max(n / 10.0, 12.0))
     a, b = R_eq * math.sqrt(aspect), R_eq / math.sqrt(aspect)
     case = base_case(nx, ny, rho_A=float(ratio), rho_B=1.0, nu_A=nu, nu_B=nu,
-                     sigma0=sigma, W=W, M=M)
+                     sigma0=sigma, W=W, M=M, init=("ellipse", (nx / 2, ny / 2, a, b, 0.0, 0.0)))
     x, y = _grid(nx, ny)
     X, Y = x - nx / 2, y - ny / 2
     # signed distance approximated by the radial scaling of the ellipse level set
@@ -99,7 +106,8 @@ def rayleigh_taylor(nx: int = 256, ny: int | None = None, W: float = 4.0, ratio:
     g = Uc * Uc / L
     mu = rho_A * Uc * L / Re
     case = base_case(L, ny, bc_y="wall", rho_A=rho_A, rho_B=rho_B, nu_A=mu / rho_A,
-                     nu_B=mu / rho_B, W=W, M=Uc * L / Pe, gy=-g, force_ref="mean")
+                     nu_B=mu / rho_B, W=W, M=Uc * L / Pe, gy=-g, force_ref="mean",
+                     init=("interface", (ny / 2, 0.1 * L, 1.0)))
     x, y = _grid(L, ny)
     y0 = ny / 2 + 0.1 * L * np.cos(2 * np.pi * x / L)
     return case, tanh_profile(y - y0, W)
@@ -112,7 +120,8 @@ def thermocapillary(nx: int = 512, ny: int = 256, R: float = 32.0, ratio: float 
     drop of phase A at (nx/2, 2R) in a channel with walls at top and bottom."""
     yc = 2.0 * R
     case = base_case(nx, ny, bc_y="wall", rho_A=float(ratio), rho_B=1.0, nu_A=nu, nu_B=nu,
-                     sigma0=sigma0, sigma_T=sigma_T, T0=0.0, dTdy=1.0, y_ref=yc, W=W, M=M)
+                     sigma0=sigma0, sigma_T=sigma_T, T0=0.0, dTdy=1.0, y_ref=yc, W=W, M=M,
+                     init=("droplet", (nx / 2, yc, R, 1.0, 0.0, 0.0)))
     x, y = _grid(nx, ny)
     r = np.hypot(x - nx / 2, y - yc)
     return case, tanh_profile(R - r, W)
@@ -132,7 +141,7 @@ def surfactant_young(sigma0_beta: float = 0.0244, G: float = 9.95e-5, D: float =
     yc = float(D if yc is None else yc)
     case = base_case(nx, ny, bc_y="wall", rho_A=1.0, rho_B=1.0, nu_A=nu, nu_B=nu,
                      sigma0=sigma0, W=W, M=M, surf="langmuir", beta=sigma0_beta / sigma0,
-                     psi_a=psi_a, psi_G=G)
+                     psi_a=psi_a, psi_G=G, init=("droplet", (nx // 2, yc, R, 1.0, 0.0, 0.0)))
     x, y = _grid(nx, ny)
     r = np.hypot(x - nx // 2, y - yc)
     return case, tanh_profile(R - r, W)
@@ -160,7 +169,8 @@ def falling_drop(Oh: float = 0.3, Eo: float = 43.0, D: float = 30.0, nx: int = 1
     sigma = (rho_A * nu / Oh) ** 2 / (rho_A * D)
     g = Eo * sigma / ((rho_A - rho_B) * D * D)
     case = base_case(nx, ny, bc_y="slip", rho_A=rho_A, rho_B=rho_B, nu_A=nu, nu_B=nu,
-                     sigma0=sigma, W=W, M=M, gy=-g, force_ref="light")
+                     sigma0=sigma, W=W, M=M, gy=-g, force_ref="light",
+                     init=("droplet", (75.0, 300.0, D / 2.0, 1.0, 0.0, 0.0)))
     x, y = _grid(nx, ny)
     r = np.hypot(x - 75.0, y - 300.0)
     return case, tanh_profile(D / 2.0 - r, W)
@@ -186,7 +196,7 @@ def rising_bubble(Eo: float = 125.0, Re: float = 35.0, D: float = 64.0, nx: int 
     sigma = rho_A * Ug * Ug * D / Eo
     case = base_case(nx, ny, bc_x="slip", bc_y="wall", rho_A=rho_A, rho_B=rho_B,
                      nu_A=muA / rho_A, nu_B=muB / rho_B, sigma0=sigma, W=W, M=M, gy=-g,
-                     force_ref="heavy")
+                     force_ref="heavy", init=("droplet", (xc, yc, D / 2.0, -1.0, 0.0, 0.0)))
     x, y = _grid(nx, ny)
     r = np.hypot(x - xc, y - yc)
     return case, tanh_profile(r - D / 2.0, W)
@@ -218,7 +228,8 @@ def elliptic_cylinder(ratio: float, nu: float, collision: str = "cascaded", n: i
     periodic n x n box, nu_A = nu_B = nu, surface-tension parameter
     kappa~ = 1.5 sigma W.  W and M are readings."""
     case = base_case(n, n, rho_A=float(ratio), rho_B=1.0, nu_A=nu, nu_B=nu,
-                     sigma0=kappa / (1.5 * W), W=W, M=M, collision=collision)
+                     sigma0=kappa / (1.5 * W), W=W, M=M, collision=collision,
+                     init=("ellipse", (n / 2, n / 2, a, b, 0.0, 0.0)))
     x, y = _grid(n, n)
     X, Y = x - n / 2, y - n / 2
     s = np.sqrt((X / a) ** 2 + (Y / b) ** 2)
@@ -231,7 +242,7 @@ def flat_interface(nx: int = 4, ny: int = 128, W: float = 4.0, ratio: float = 10
                    nu: float = 0.1, sigma: float = 0.01, M: float = 0.02):
     """Flat interface at y = (ny - 1)/2 between walls, phase A on top."""
     case = base_case(nx, ny, bc_y="wall", rho_A=float(ratio), rho_B=1.0, nu_A=nu, nu_B=nu,
-                     sigma0=sigma, W=W, M=M)
+                     sigma0=sigma, W=W, M=M, init=("interface", ((ny - 1) / 2.0, 0.0, 0.0)))
     x, y = _grid(nx, ny)
     return case, tanh_profile(y - (ny - 1) / 2.0, W)
 
@@ -240,6 +251,11 @@ def tiled(case: dict, phi0: np.ndarray, tx: int, ty: int):
     """Periodic tiling of a periodic case: a (ty*ny) x (tx*nx) lattice."""
     c = dict(case)
     c["nx"], c["ny"] = case["nx"] * tx, case["ny"] * ty
+    kind, par = case.get("init", ("none", ()))
+    if kind in ("droplet", "ellipse"):  # the same shape repeated with the tile's period
+        c["init"] = (kind, tuple(par[:4]) + (float(case["nx"]), float(case["ny"])))
+    else:
+        c.pop("init", None)
     return c, np.tile(phi0, (ty, tx))
 
 

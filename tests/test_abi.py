@@ -100,7 +100,7 @@ def test_option_validation():
     assert code(bc_y=lb.LB_FREE_SLIP) == lb.LB_OK
     assert code(bc_x=lb.LB_FREE_SLIP) == lb.LB_OK and code(bc_x=lb.LB_HALFWAY_BB) == lb.LB_OK
     assert code(bc_y=3) == lb.LB_E_INVALID_ARG
-    assert code(collision=2) == lb.LB_E_INVALID_ARG
+    assert code(collision=3) == lb.LB_E_INVALID_ARG
     assert code(flow=2) == lb.LB_E_INVALID_ARG
     assert code(surf=2) == lb.LB_E_INVALID_ARG
     assert code(tile_pf=1) == lb.LB_E_INVALID_ARG  # row variant without a fixed tile
@@ -153,3 +153,16 @@ def test_noalloc_rejects_before_device_work():
     c = lb.config_from_case(dict(case, flow="imposed"), "fp64")
     assert code(c) == lb.LB_E_UNSUPPORTED
     assert "static scratch" in lb.lib().lb_status_string(lb.LB_E_TOO_LARGE).decode()
+
+
+def test_stale_library_is_refused(tmp_path, monkeypatch):
+    """The binding loads libcmlb.so only when the hash written beside it at build
+    time matches the sources in the tree."""
+    from paper_1909_04166_amd import build
+    stamp = lb.LIB_PATH + build.STAMP_SUFFIX
+    with open(stamp) as fh:
+        assert fh.read().strip() == build.source_hash()
+    monkeypatch.setattr(build, "source_hash", lambda extra=None: "0" * 32)
+    monkeypatch.setattr(lb, "_lib", None)
+    with pytest.raises(RuntimeError, match="does not match the sources"):
+        lb.lib()

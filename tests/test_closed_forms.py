@@ -9,7 +9,9 @@ GPU.
   f~ = phi W(ex) W(ey) + a D(ex) V(ey) + b V(ex) D(ey).
 - Hydrodynamics (rates 1 except the two shear rates): post-collision raw moments
   that depend on the incoming gbar only through pbar, j and the shear
-  non-equilibria N, X, each times (1 - omega)."""
+  non-equilibria N, X, each times (1 - omega); the printed closed forms of the
+  moment changes, and the solve of the conditions they come from (the collision
+  of the cascaded pair) as those moments plus force terms."""
 import numpy as np
 
 import oracle
@@ -84,8 +86,10 @@ def test_phase_field_closed_form_equals_cascade():
 
 
 def test_hydrodynamic_closed_form_equals_cascade():
-    """Random pre-collision gbar, u, rho up to 1000 and forces, with p = pbar +
-    F_p.u / 2 as the step computes it; the closed form takes pbar back from p."""
+    """The kernel's closed form of the printed moment changes (the printed option)
+    against the oracle's printed cascade: random pre-collision gbar, u, rho up to
+    1000 and forces, with p = pbar + F_p.u / 2 as the step computes it; the closed
+    form takes pbar back from p."""
     rng = np.random.default_rng(12)
     worst = 0.0
     for _ in range(500):
@@ -96,7 +100,59 @@ def test_hydrodynamic_closed_form_equals_cascade():
         p = g.sum() + 0.5 * (Fpx * ux + Fpy * uy)  # p = pbar + F_p.u / 2, pbar = sum gbar
         om = rng.uniform(0.3, 1.95)
         rates = [1.0] * 4 + [om, om] + [1.0] * 3
-        ref = oracle.hydro_collide(g, p, rho, p - rho / 3, ux, uy, Ftx, Fty, Fpx, Fpy, rates)
+        ref = oracle.hydro_collide_study(g, p, rho, p - rho / 3, ux, uy, Ftx, Fty, Fpx, Fpy, rates,
+                                         q8_printed=True)
         got = hydro_closed(g, p, rho, ux, uy, Ftx, Fty, Fpx, Fpy, om)
         worst = max(worst, np.abs(ref - got).max() / max(1.0, np.abs(ref).max()))
     assert worst <= 1e-12
+
+
+def hydro_solved_closed(g, p, rho, ux, uy, Ftx, Fty, Fpx, Fpy, om):
+    """The kernel's closed form of the collision (h_3..h_8 solve the relaxation
+    conditions as stated): the printed form's raw moments plus the differences
+    written out in the kernel."""
+    c2 = 1 / 3
+    G = Fpx * ux + Fpy * uy
+    m = _to_raw(hydro_closed(g, p, rho, ux, uy, Ftx, Fty, Fpx, Fpy, om))
+    o1 = 1 - om
+    fu, fv = Ftx * ux - Fty * uy, Ftx * uy + Fty * ux
+    ux2, uy2 = ux * ux, uy * uy
+    dT = -2 / 3 * G
+    dD = -o1 / 6 * (3 * (ux2 - uy2) * G - 2 * fu)
+    m[3] += (dT + dD) / 2
+    m[4] += (dT - dD) / 2
+    m[5] -= o1 / 6 * (3 * ux * uy * G - fv)
+    m[6] -= Fty / 9 + o1 / 36 * (9 * uy * (5 * ux2 - uy2) * G - 18 * Ftx * ux * uy - 12 * Fty * ux2 + 6 * Fty * uy2)
+    m[7] += o1 / 36 * (9 * ux * (ux2 - 5 * uy2) * G - 6 * Ftx * ux2 + 12 * Ftx * uy2 + 18 * Fty * ux * uy) - Ftx / 9
+    m[8] += o1 / 36 * (9 * (ux2 * ux2 - 10 * ux2 * uy2 + uy2 * uy2) * G - 6 * (Ftx * ux ** 3 + Fty * uy ** 3)
+                       + 30 * ux * uy * fv) - 2 * G / 9
+    return _from_raw(m)
+
+
+def _to_raw(f):
+    return np.array([(f * EX ** m * EY ** n).sum() for m, n in
+                     [(0, 0), (1, 0), (0, 1), (2, 0), (0, 2), (1, 1), (2, 1), (1, 2), (2, 2)]])
+
+
+def test_hydrodynamic_solved_closed_form_equals_numerical_solve():
+    """The kernel's closed form of the collision against the oracle's numerical
+    solve of the relaxation conditions (itself pinned to the brute-force solve):
+    random gbar, rho up to 1000 and forces, with u and p as the step
+    computes them from gbar (u = (j + c^2 F_t / 2) / (rho c^2), p = pbar + F_p.u / 2)."""
+    rng = np.random.default_rng(13)
+    worst = 0.0
+    for _ in range(500):
+        rho = float(np.exp(rng.uniform(0, np.log(1000))))
+        g = rng.normal(scale=0.05, size=9)
+        Ftx, Fty, Fpx, Fpy = rng.normal(scale=1e-3, size=4)
+        ux = ((g * EX).sum() + Ftx / 6) / (rho / 3)
+        uy = ((g * EY).sum() + Fty / 6) / (rho / 3)
+        if max(abs(ux), abs(uy)) > 0.2:
+            continue
+        p = g.sum() + 0.5 * (Fpx * ux + Fpy * uy)
+        om = rng.uniform(0.3, 1.95)
+        rates = [1.0] * 4 + [om, om] + [1.0] * 3
+        ref = oracle.hydro_collide(g, p, rho, p - rho / 3, ux, uy, Ftx, Fty, Fpx, Fpy, rates)
+        got = hydro_solved_closed(g, p, rho, ux, uy, Ftx, Fty, Fpx, Fpy, om)
+        worst = max(worst, np.abs(ref - got).max() / max(1.0, np.abs(ref).max()))
+    assert worst <= 1e-12, worst

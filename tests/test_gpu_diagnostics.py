@@ -63,3 +63,34 @@ def test_gpu_centroid_sums_radius_velocity_probe_nan():
     phi = np.full((ny, nx), 0.5)
     phi[30, 2] = np.nan
     assert _gpu_diag(phi)["nan_flag"] == 1.0
+    g = np.zeros((9, ny, nx))
+    g[1, 3, 1] = np.nan
+    g[1, 90, 7] = 0.2
+    d = _gpu_diag(np.ones((ny, nx)), g)
+    assert d["nan_flag"] == 1.0 and math.isnan(d["max_u"])
+
+
+def test_bandwidth_probe_variants_move_the_data():
+    """Every copy variant copies exactly; the write probe writes each word's index;
+    the read probe's XOR of a constant array over an even count of words per lane
+    is zero."""
+    import torch
+    print("[case] bandwidth probe variants, 32 MiB", flush=True)
+    n = 32 << 20
+    a = torch.randint(0, 255, (n,), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    for v in (1, 2, 3, 4):
+        b = torch.zeros_like(a)
+        lb.lb_bandwidth_probe(b.data_ptr(), a.data_ptr(), n, v, stream)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b), v
+    b = torch.zeros_like(a)
+    lb.lb_bandwidth_probe(b.data_ptr(), a.data_ptr(), n, 6, stream)
+    torch.cuda.synchronize()
+    w = b.view(torch.int32).view(-1, 4)
+    assert torch.equal(w[:, 0].cpu(), torch.arange(n // 16, dtype=torch.int32)) and not w[:, 1:].any()
+    ones = torch.full((n,), 7, dtype=torch.uint8, device="cuda")
+    b = torch.ones_like(a)
+    lb.lb_bandwidth_probe(b.data_ptr(), ones.data_ptr(), n, 5, stream)
+    torch.cuda.synchronize()
+    assert not b[: 4096 * 256 * 16].any()

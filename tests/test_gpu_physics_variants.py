@@ -26,8 +26,16 @@ from paper_1909_04166_amd import lb, workloads as W
 pytestmark = pytest.mark.gpu
 
 
-def test_young_migration_langmuir():
-    print("[case] Young migration, 51 x 201, sigma0 beta = 0.0048, 0.0146, 0.0244", flush=True)
+# Measured V / V_Young in the paper's 51 x 201 set-up (steps 40000-80000): 0.451,
+# 0.463 and 0.466 for the three sensitivities, and 0.47-0.56 under the other
+# readings of Q6, Q8 and Q11 tried; refinement (D 60, W 8) and wider boxes do not
+# bring it nearer 1.
+# The paper reports agreement with V_Young after transients (Sec. 6.7); the
+# factor of about two is an open discrepancy.  The value is a regression pin.
+YOUNG_RATIO = 0.46
+
+
+def _young_ratios():
     B = lb.Batch(3, 40000, "fp64")
     runs = []
     for sb in (0.0048, 0.0146, 0.0244):
@@ -40,17 +48,34 @@ def test_young_migration_langmuir():
             d = B.diagnostics(s)
             assert d["nan_flag"] == 0
             yc[s].append(d["centroid_y"])
-    speeds = []
+    out = []
     for s, c, sb in runs:
         h = np.array(yc[s])
         v = (h[-1] - h[7]) / (8 * 5000)  # late window: steady migration
-        ratio = v / W.young_velocity(c, 30.0)
+        out.append((sb, v, v / W.young_velocity(c, 30.0), h))
+    B.close()
+    return out
+
+
+@pytest.mark.xfail(reason="open discrepancy with Sec. 6.7: V / V_Young is about 0.47 in the "
+                          "paper's 51 x 201 set-up under every reading tried", strict=False)
+def test_young_migration_at_the_papers_claim():
+    """Sec. 6.7: after transients the migration speed agrees with the creeping-flow
+    speed V_Young; held to 20 %."""
+    print("[case] Young migration vs V_Young (expected to fail)", flush=True)
+    for sb, v, ratio, _ in _young_ratios():
+        assert abs(ratio - 1.0) <= 0.2, (sb, ratio)
+
+
+def test_young_migration_langmuir():
+    print("[case] Young migration, 51 x 201, sigma0 beta = 0.0048, 0.0146, 0.0244", flush=True)
+    speeds = []
+    for sb, v, ratio, h in _young_ratios():
         print(f"   sigma0 beta {sb}: V = {v:.3e}, V / V_Young = {ratio:.3f}", flush=True)
         assert np.all(np.diff(h) > 0)  # moves up, toward lower surface tension
-        assert 0.35 <= ratio <= 0.75
+        assert abs(ratio - YOUNG_RATIO) <= 0.1 * YOUNG_RATIO  # regression pin (see YOUNG_RATIO)
         speeds.append(v / sb)
-    assert max(speeds) / min(speeds) <= 1.25  # proportional to sigma0 beta
-    B.close()
+    assert max(speeds) / min(speeds) <= 1.05  # proportional to sigma0 beta
 
 
 @pytest.mark.parametrize("coll,bound", [("cascaded", 0.08), ("srt", 0.03)])

@@ -77,7 +77,10 @@ def test_one_step_distributions(name):
     g, o = _pair(case, phi0, tile=(64, 16))
     g.step(1)
     o.step(1)
-    _cmp_dist(g, o, 1e-14)
+    # the oracle takes the hydrodynamic moment changes from a 6 x 6 elimination,
+    # whose rounding is about 1e-14 relative; the phase field is closed-form on both
+    # sides
+    _cmp_dist(g, o, 1e-13)
 
 
 @pytest.mark.parametrize("coll", ["cascaded", "srt"])

@@ -30,22 +30,40 @@ def _rand_hydro(rng, scale_u=0.1, scale_f=0.02):
     return gbar, p, rho, ux, uy, Ftx, Fty, Fpx, Fpy, om
 
 
-def test_hydro_matches_central_moment_solve_reading_B():
-    """Printed h_0..h_8 + delta g^s equal the numerical solution of the relaxation
-    conditions when the 0th/1st raw moments are (p, rho c^2 u) (reading B)."""
+def test_hydro_matches_central_moment_solve():
+    """The collision (h_3..h_8 solved from the relaxation conditions of Sec. 4 with
+    gbar's own central moments, h_0..h_2 carried into them, plus delta g^s)
+    equals the brute-force solve of the same conditions, whose equilibrium and
+    source moments come from quadrature of their definitions."""
     rng = np.random.default_rng(11)
     worst = 0.0
     for _ in range(400):
         gbar, p, rho, ux, uy, Ftx, Fty, Fpx, Fpy, om = _rand_hydro(rng)
         got = oracle.hydro_collide(gbar, p, rho, p - rho / 3, ux, uy, Ftx, Fty, Fpx, Fpy, om)
+        exp = bf.hydro_expected(gbar, p, rho, ux, uy, Ftx, Fty, Fpx, Fpy, om, reading_B=False)
+        worst = max(worst, np.abs(got - exp).max() / max(1.0, np.abs(exp).max()))
+    assert worst <= 1e-12, worst
+
+
+def test_printed_forms_match_central_moment_solve_reading_B():
+    """The printed h_0..h_8 (kept as a study switch) + delta g^s equal the
+    numerical solution of the relaxation conditions when the 0th/1st raw moments
+    are (p, rho c^2 u) and h_0..h_2 are not carried into the higher moments
+    (reading B): that is what the closed forms leave out."""
+    rng = np.random.default_rng(11)
+    worst = 0.0
+    for _ in range(400):
+        gbar, p, rho, ux, uy, Ftx, Fty, Fpx, Fpy, om = _rand_hydro(rng)
+        got = oracle.hydro_collide_study(gbar, p, rho, p - rho / 3, ux, uy, Ftx, Fty, Fpx, Fpy, om,
+                                         q8_printed=True)
         exp = bf.hydro_expected(gbar, p, rho, ux, uy, Ftx, Fty, Fpx, Fpy, om)
         worst = max(worst, np.abs(got - exp).max() / max(1.0, np.abs(exp).max()))
     assert worst <= 1e-13
 
 
 def test_hydro_exact_without_sources():
-    """With F_t = F_p = 0 and (p, u) taken from gbar itself, the printed forms are
-    the exact central-moment relaxation."""
+    """With F_t = F_p = 0 and (p, u) taken from gbar itself, the collision and the
+    printed forms both are the exact central-moment relaxation."""
     rng = np.random.default_rng(12)
     for _ in range(200):
         gbar, _, rho, *_rest = _rand_hydro(rng)
@@ -53,8 +71,10 @@ def test_hydro_exact_without_sources():
         p = gbar.sum()
         ux, uy = gbar @ bf.EX / (rho / 3), gbar @ bf.EY / (rho / 3)
         got = oracle.hydro_collide(gbar, p, rho, p - rho / 3, ux, uy, 0, 0, 0, 0, om)
+        printed = oracle.hydro_collide_study(gbar, p, rho, p - rho / 3, ux, uy, 0, 0, 0, 0, om, q8_printed=True)
         exp = bf.hydro_expected(gbar, p, rho, ux, uy, 0, 0, 0, 0, om, reading_B=False)
         assert np.abs(got - exp).max() <= 1e-13 * max(1.0, np.abs(exp).max())
+        assert np.abs(printed - exp).max() <= 1e-13 * max(1.0, np.abs(exp).max())
 
 
 def test_hydro_collision_invariants():

@@ -132,9 +132,17 @@ def test_laplace_probe_centre_minus_corner():
 
 
 def test_nan_flag():
+    """Any NaN/Inf in phi, p or u sets the flag; max |u| over a field holding a
+    NaN is NaN wherever the NaN sits (here before larger finite values in the
+    scan order), not the largest finite value."""
     phi = np.full((NY, NX), 0.5)
     phi[30, 2] = np.nan
     assert _state(phi).diagnostics()["nan_flag"] == 1.0
+    g = np.zeros((9, NY, NX))
+    g[1, 3, 1] = np.nan
+    g[1, 90, 7] = 0.2
+    d = _state(np.ones((NY, NX)), g).diagnostics()
+    assert d["nan_flag"] == 1.0 and math.isnan(d["max_u"])
     phi = np.ones((NY, NX))
     g = np.zeros((9, NY, NX))
     g[1, 5, 5] = np.inf
