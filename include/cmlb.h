@@ -99,6 +99,16 @@ enum { LB_FP64 = 0, LB_FP32 = 1, LB_FP32_F16 = 2, LB_FP32_BF16 = 3 };
  *                     d = y - y0 - A cos(2 pi k x / nx).
  * Node (i, j) sits at (x, y) = (i, j). */
 enum { LB_INIT_NONE = 0, LB_INIT_DROPLET = 1, LB_INIT_ELLIPSE = 2, LB_INIT_INTERFACE = 3 };
+/* rounding of the values a step stores in 16-bit storage (LB_FP32_F16, LB_FP32_BF16;
+ * ignored otherwise).  LB_ROUND_STOCHASTIC: each value is rounded up or down at
+ * random with the probabilities that make it unbiased (the gfx950 conversions with
+ * stochastic rounding), the random bits a hash of the step count, the node and the
+ * direction, so that results do not depend on the schedule and repeat bit for bit.
+ * With round to nearest, a change of a stored value below half its unit in the
+ * last place is lost every step: a slowly moving interface (the thermocapillary
+ * drop of Sec. 6.6 at about 3e-4 nodes per step) stays where it is.
+ * Initial states, lb_set_dist and lb_load_state round to nearest. */
+enum { LB_ROUND_STOCHASTIC = 0, LB_ROUND_NEAREST = 1 };
 
 /*
  * Problem description (Secs. 2, 4, 5).  Phase A is phi = 1, phase B is phi = 0.
@@ -122,8 +132,10 @@ typedef struct lb_config {
     double T0, dTdy, y_ref;  /* imposed linear temperature T(y) */
     double W, M;             /* interface width (> 0) and mobility (> 0) */
     double gx, gy;           /* body-force acceleration */
-    double shift_f, shift_g; /* 16-bit storage stores f_a - w_a shift_f and g_a - w_a shift_g
-                                (9/16 and 0 recommended: w_a 9/16 is exact in fp16 and bf16) */
+    double shift_f, shift_g; /* 16-bit storage stores f_a - w_a shift_f and g_a - w_a shift_g.
+                                Recommended: shift_f the light phase's phi (0 when rho_A >=
+                                rho_B, else 1), whose values are then stored near zero where
+                                rho(phi) is most sensitive to phi, and shift_g 0 */
     double u_max;            /* stability limit for diagnostics (0: 0.3) */
     int32_t tile_x;          /* workgroup width in lanes: 64, 128, 132, 256, 260, 452, 512,
                                 516 (not with FP64 prefetching), or 1024 (FP32-compute
@@ -139,7 +151,7 @@ typedef struct lb_config {
                                 must be 0 otherwise */
     double beta, psi_a, psi_G; /* Langmuir law parameters */
     int32_t init_kind;       /* LB_INIT_*: the built-in initial phase field */
-    int32_t init_pad_;
+    int32_t rounding;        /* LB_ROUND_*: rounding of 16-bit stores (0: stochastic) */
     double init_par[8];      /* its parameters (see LB_INIT_*) */
 } lb_config;
 
@@ -169,8 +181,15 @@ const char* lb_status_string(lb_status s);
 lb_status lb_workspace_bytes(const lb_config* cfg, uint64_t* bytes);
 
 /* Validates cfg, lays the lattice out in dev_ws (device memory, 256-byte aligned,
- * at least lb_workspace_bytes), picks the tile shape and returns a handle.
- * The state is undefined until lb_init_fields or lb_load_state / lb_set_dist.
+ * at least lb_workspace_bytes), picks the tile shape and returns a handle.  The
+ * parameters are the paper's problem statement: the two phases' densities and
+ * viscosities with rho(phi), mu(phi) and omega(nu) of Eqs.
+ * sfluidpropertiesinterpolation and fluidviscosity (Secs. 2, 4), the surface
+ * tension kappa~ = 1.5 W sigma of the geometric form (Eq. surfacetensiongeometric
+ * and its surfactant extension, Sec. 6.7), the interface width W and mobility M of
+ * the conservative Allen-Cahn equation (Sec. 2; omega^phi of Sec. 5), a body force
+ * (Secs. 6.3-6.5) and the boundary kinds.  The state is undefined until
+ * lb_init_fields or lb_load_state / lb_set_dist.
  * Errors: LB_E_INVALID_ARG, LB_E_WORKSPACE, LB_E_HIP. */
 lb_status lb_create(const lb_config* cfg, void* dev_ws, uint64_t ws_bytes, void* stream,
                     lb_handle** out);
@@ -189,10 +208,15 @@ lb_status lb_init_fields(lb_handle* h, const double* phi0);
  * Errors: LB_E_INVALID_ARG (NULL, or a coupled lattice). */
 lb_status lb_set_velocity(lb_handle* h, const double* ux, const double* uy);
 
-/* Advances n time steps (stream-collide of both schemes per step).  Enqueued
- * asynchronously on the handle's stream.  With diag_every > 0, a stability check
- * runs every diag_every steps; LB_E_UNSTABLE is returned by the first call after
- * a check has found NaN/Inf or max|u| > u_max. */
+/* Advances n time steps.  One step (Secs. 4 and 5): the coupling fields at time t
+ * (phi, pbar, grad phi, n, div n or the chemical potential, rho, F_s, F_t, u,
+ * F_p, p; Eqs. netgradientpressureforce, hydrodynamicfields), the cascaded
+ * collision of gbar with its sources (Eqs. cascadedcollisionoperator,
+ * cumulativesourcetermcomponents, postcollisioncascadedLBscheme) and of f
+ * (Sec. 5), then streaming with the boundary rules (Eq. ACEstreamingLB).
+ * Enqueued asynchronously on the handle's stream.  With diag_every > 0, a
+ * stability check runs every diag_every steps; LB_E_UNSTABLE is returned by the
+ * first call after a check has found NaN/Inf or max|u| > u_max. */
 lb_status lb_step(lb_handle* h, int64_t n);
 
 /* phi (Sec. 5, zeroth moment of f), p and u (Eq. hydrodynamicfields) at the
@@ -204,7 +228,11 @@ lb_status lb_get_fields(lb_handle* h, double* phi, double* p, double* ux, double
  * F_p x, F_p y.  For diagnosis of parity failures.  Synchronizes. */
 lb_status lb_get_coupling(lb_handle* h, double* dev_out);
 
-/* FP64 diagnostics at the current time (sums in a fixed order).  Synchronizes. */
+/* FP64 diagnostics at the current time (sums in a fixed order): total phase sum
+ * phi (conserved by the Allen-Cahn scheme, Sec. 5), total mass, max |u|, the
+ * Laplace probe p(centre) - p(corner) and R_eff = sqrt(sum phi / pi) (Sec. 6.2),
+ * the spike and bubble tips (Sec. 6.3: phi = 1/2 crossings at the centre and edge
+ * columns) and the centroid y (Secs. 6.4-6.7).  Synchronizes. */
 lb_status lb_diagnostics(lb_handle* h, lb_diag* out);
 
 /* Post-streaming distributions f, gbar at the current time (FP64 host arrays of
@@ -231,8 +259,11 @@ lb_status lb_get_step(lb_handle* h, int64_t* step);
 void lb_destroy(lb_handle* h);
 
 /* ------------------------------------------------------------------ batch ----
- * Many independent lattices of uneven sizes advanced by ONE persistent kernel
- * launch per step over a shared work list of (instance, strip, rows) items.
+ * Many independent lattices of uneven sizes, each advanced by the step of
+ * lb_step (Secs. 4, 5), by ONE persistent kernel launch per step over a shared
+ * work list of (instance, strip, rows) items.  The paper runs one lattice at a
+ * time; batching is this library's (the problem statement of each slot is an
+ * lb_config, as for lb_create).
  * All instances share the storage precision, the collision model and one tile
  * shape; LB_FLOW_IMPOSED lattices are not batched.  A slot holds one lattice; slots can be filled and emptied between
  * steps (continuous batching).  Results of a slot do not depend on the other
@@ -244,7 +275,10 @@ void lb_destroy(lb_handle* h);
 lb_status lb_batch_workspace_bytes(int32_t slots, int64_t node_capacity, int32_t precision,
                                    uint64_t* bytes);
 
-/* Creates an empty batch over dev_ws. tile_x / tile_h as in lb_config (0: defaults). */
+/* Creates an empty batch over dev_ws.  tile_x / tile_h as in lb_config (0: defaults).
+ * Unlike lb_create the batch is sized by slots and a node capacity, not by one
+ * lattice: lattices are added and removed later (continuous batching), so the
+ * workspace holds a pool from which each slot takes its two buffers. */
 lb_status lb_batch_create(int32_t slots, int64_t node_capacity, int32_t precision,
                           int32_t tile_x, int32_t tile_h, void* dev_ws, uint64_t ws_bytes,
                           void* stream, lb_batch** out);
@@ -267,6 +301,13 @@ lb_status lb_batch_remove(lb_batch* b, int32_t slot);
  * captured HIP graphs; the steps of a call up to that point, and the remainder
  * below 32, are launched one by one.  Asynchronous. */
 lb_status lb_batch_step(lb_batch* b, int64_t n, int32_t use_graph);
+
+/* Pins the batch's schedule as lb_set_schedule does for one lattice (mode 2 over
+ * lattices of different heights is cut as mode 1); the autotuner no longer runs.
+ * Synchronizes the stream and drops captured graphs.  Errors: LB_E_INVALID_ARG
+ * (an invalid value or a cut that does not fit the work-list capacity; the
+ * previous schedule then stays). */
+lb_status lb_batch_set_schedule(lb_batch* b, int32_t tile_x, int32_t mode, int32_t param, int32_t prefetch);
 
 /* Steps the batch has replayed from captured graphs and launched one by one
  * since it was created. */
@@ -332,12 +373,15 @@ lb_status lb_batch_get_schedule(lb_batch* b, int32_t* tile_x, int32_t* rows, int
  *                  layout lb_save_state writes after that header.  The current
  *                  state is read from state0; after the call it is in state0 if n
  *                  is even and in state1 if n is odd.
+ *   step           step count of the state in state0 (as lb_get_step reports it for
+ *                  a handle); it seeds the stochastic rounding of 16-bit storage, so
+ *                  the same step count gives the same bits as lb_step.
  *   stream         HIP stream (void*); every launch is enqueued there and the
  *                  call returns without synchronizing.  It makes no copy, memset or
  *                  synchronization, so it can be captured into a HIP graph once a
  *                  first call on the device has looked up the scratch address.
  *
- * The descriptor, work list and per-row table live in a static 1 MiB device
+ * The descriptor, step counter, work list and per-row table live in a static 1 MiB device
  * array that each GPU holds until the process ends; it must hold the work list
  * (16 bytes per (strip, row block)) and, under the Langmuir law, 16 ny bytes:
  * larger lattices (or tiles that cut them finer) return LB_E_TOO_LARGE before any
@@ -346,7 +390,7 @@ lb_status lb_batch_get_schedule(lb_batch* b, int32_t* tile_x, int32_t* rows, int
  * Errors: LB_E_INVALID_ARG, LB_E_UNSUPPORTED, LB_E_WORKSPACE (buffers too small
  * or misaligned), LB_E_TOO_LARGE, LB_E_HIP. */
 lb_status lb_step_noalloc(const lb_config* cfg, void* state0, void* state1, uint64_t state_bytes,
-                          int64_t n, void* stream);
+                          int64_t step, int64_t n, void* stream);
 
 /* sizeof(lb_config) and sizeof(lb_diag) as compiled, for binding checks. */
 lb_status lb_struct_sizes(uint64_t* config_bytes, uint64_t* diag_bytes);

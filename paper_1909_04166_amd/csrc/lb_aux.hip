@@ -389,6 +389,20 @@ __global__ void __launch_bounds__(256) k_copy(uint4* __restrict__ dst, const uin
     }
 }
 
+// Both slots of a lattice's step counter (one thread; a kernel rather than a
+// copy, so that it needs no host buffer and records no memset node in a graph).
+__global__ void k_set_step(uint32_t* __restrict__ tstep, uint32_t t) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        tstep[0] = t;
+        tstep[1] = t;
+    }
+}
+
+hipError_t launch_set_step(uint32_t* tstep, uint32_t t, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_step, dim3(1), dim3(64), 0, s, tstep, t);
+    return hipGetLastError();
+}
+
 hipError_t launch_copy(void* dst, const void* src, uint64_t n, hipStream_t s) {
     const int64_t n16 = (int64_t)(n / 16);
     int64_t g = (n16 + 1023) / 1024;

@@ -104,6 +104,7 @@ lb_status validate(const lb_config* c) {
     if (c->tile_h < 0 || (c->tile_h > 0 && c->tile_h < kMinH)) return LB_E_INVALID_ARG;
     if (c->diag_every < 0) return LB_E_INVALID_ARG;
     if (c->init_kind < LB_INIT_NONE || c->init_kind > LB_INIT_INTERFACE) return LB_E_INVALID_ARG;
+    if (c->rounding != LB_ROUND_STOCHASTIC && c->rounding != LB_ROUND_NEAREST) return LB_E_INVALID_ARG;
     for (double v : c->init_par)
         if (!std::isfinite(v)) return LB_E_INVALID_ARG;
     if (c->init_kind == LB_INIT_DROPLET &&
@@ -167,6 +168,7 @@ void fill_desc(const lb_config* c, LatDesc& D, void* b0, void* b1, int64_t plane
     const bool half = c->precision == LB_FP32_F16 || c->precision == LB_FP32_BF16;
     D.shift_f = half ? c->shift_f : 0.0;
     D.shift_g = half ? c->shift_g : 0.0;
+    D.sround = half && c->rounding == LB_ROUND_STOCHASTIC ? 1 : 0;
     D.kt0 = 1.5 * c->W * c->sigma0;
     D.lbeta = c->beta;
     D.ps_a = c->psi_a;
@@ -268,7 +270,7 @@ struct lb_handle {
 namespace {
 
 struct Layout {
-    uint64_t desc, desc_cp, items, items64, part, dout, fields, bufA, bufB, vel, ktab, total;
+    uint64_t desc, desc_cp, tstep, items, items64, part, dout, fields, bufA, bufB, vel, ktab, total;
 };
 
 Layout layout_of(const lb_config* c) {
@@ -279,6 +281,7 @@ Layout layout_of(const lb_config* c) {
     uint64_t o = 0;
     L.desc = o; o += align_up(sizeof(LatDesc));
     L.desc_cp = o; o += align_up(sizeof(LatDesc));
+    L.tstep = o; o += align_up(2 * sizeof(uint32_t));
     L.items = o; o += align_up((uint64_t)max_items_for(c->nx, c->ny) * sizeof(WorkItem));
     L.items64 = o; o += align_up((uint64_t)((c->nx + 59) / 60) * ((c->ny + 63) / 64) * sizeof(WorkItem));
     L.part = o; o += align_up((uint64_t)4 * c->ny * sizeof(double));
@@ -520,6 +523,7 @@ lb_status lb_create(const lb_config* cfg, void* dev_ws, uint64_t ws_bytes, void*
     h->walls = h->hdesc.wall_y != WALL_NONE || h->hdesc.wall_x != WALL_NONE;
     h->hdesc.vel = cfg->flow == LB_FLOW_IMPOSED ? (void*)(h->ws + L.vel) : nullptr;
     h->hdesc.ktab = (double*)(h->ws + L.ktab);
+    h->hdesc.tstep = (uint32_t*)(h->ws + L.tstep);
     auto fail = [&](lb_status s) { lb_destroy(h); return s; };
     if (hipHostMalloc((void**)&h->h_diag, 16 * sizeof(double), hipHostMallocDefault) != hipSuccess)
         return fail(LB_E_HIP);
@@ -529,6 +533,7 @@ lb_status lb_create(const lb_config* cfg, void* dev_ws, uint64_t ws_bytes, void*
         return fail(LB_E_HIP);
     if (hipMemcpyAsync(h->d_desc, &h->hdesc, sizeof(LatDesc), hipMemcpyHostToDevice, h->s) != hipSuccess)
         return fail(LB_E_HIP);
+    if (launch_set_step(h->hdesc.tstep, 0, h->s) != hipSuccess) return fail(LB_E_HIP);
     if (cfg->surf == LB_SIGMA_LANGMUIR && launch_kappa_table(h->d_desc, cfg->ny, h->s) != hipSuccess)
         return fail(LB_E_HIP);
     // the imposed velocity is zero until lb_set_velocity
@@ -563,6 +568,7 @@ lb_status lb_init_fields(lb_handle* h, const double* phi0) {
     // the phase-field-only kernel never writes gbar: keep it zero in both buffers
     if (h->cfg.flow == LB_FLOW_IMPOSED)
         HIPC(launch_state_op(h->cfg.precision, 0, h->d_desc, h->d_fields, 0, 0, h->parity ^ 1, N, h->s));
+    HIPC(launch_set_step(h->hdesc.tstep, 0, h->s));
     HIPC(hipStreamSynchronize(h->s));
     h->step = 0;
     h->unstable = false;
@@ -700,6 +706,8 @@ lb_status lb_set_dist(lb_handle* h, const double* f, const double* g, int64_t st
             HIPC(launch_state_op(h->cfg.precision, 1, h->d_desc, h->d_fields, b, which, h->parity, N, h->s));
             HIPC(hipStreamSynchronize(h->s));
         }
+    HIPC(launch_set_step(h->hdesc.tstep, (uint32_t)step, h->s));
+    HIPC(hipStreamSynchronize(h->s));
     h->step = step;
     h->unstable = false;
     h->diag_pending = false;
@@ -733,6 +741,7 @@ lb_status lb_load_state(lb_handle* h, const void* host, uint64_t bytes) {
     std::memcpy(hdr, host, 16);
     if (hdr[1] != h->cfg.precision || hdr[0] < 0) return LB_E_STATE;
     HIPC(hipMemcpyAsync(h->buf[h->parity], (const char*)host + 16, need - 16, hipMemcpyHostToDevice, h->s));
+    HIPC(launch_set_step(h->hdesc.tstep, (uint32_t)hdr[0], h->s));
     HIPC(hipStreamSynchronize(h->s));
     h->step = hdr[0];
     h->unstable = false;
@@ -900,9 +909,10 @@ BatchLayout batch_layout(int32_t slots, int64_t cap, int prec) {
     L.part = o; o += align_up((uint64_t)4 * L.max_ny * sizeof(double));
     L.dout = o; o += align_up(16 * sizeof(double));
     L.fields = o; o += align_up((uint64_t)4 * L.max_slot_nodes * sizeof(double));
-    // per slot: two buffers of 18 planes and the per-row table (2 ny doubles <= 2 N bytes)
+    // per slot: two buffers of 18 planes, the per-row table (2 ny doubles <= 2 N bytes)
+    // and the step counter
     L.pool = o; o += align_up((uint64_t)2 * 18 * sb * (uint64_t)(cap + 64 * (int64_t)slots) + 2 * (uint64_t)cap +
-                              kAlign * 3 * slots);
+                              kAlign * 4 * slots);
     L.total = o;
     return L;
 }
@@ -1127,25 +1137,28 @@ lb_status lb_batch_add(lb_batch* b, const lb_config* cfg, const double* phi0, in
     const int64_t P = plane_elems(cfg->nx, cfg->ny);
     const uint64_t one = align_up((uint64_t)18 * P * b->sbytes);
     const uint64_t tab = align_up((uint64_t)2 * cfg->ny * sizeof(double));
+    const uint64_t ctr = align_up(2 * sizeof(uint32_t));
     uint64_t off;
-    if (!pool_alloc(b, 2 * one + tab, &off)) return LB_E_WORKSPACE;
+    if (!pool_alloc(b, 2 * one + tab + ctr, &off)) return LB_E_WORKSPACE;
     BatchSlot& S = b->slot[free_slot];
     S.used = true;
     S.cfg = *cfg;
     S.add_step = b->gstep;
     S.off = off;
-    S.bytes = 2 * one + tab;
+    S.bytes = 2 * one + tab + ctr;
     S.plane = P;
     LatDesc& D = b->hdescs[free_slot];
     fill_desc(cfg, D, b->pool + off, b->pool + off + one, P, b->d_fields);
     D.ktab = (double*)(b->pool + off + 2 * one);
+    D.tstep = (uint32_t*)(b->pool + off + 2 * one + tab);
     auto undo = [&](lb_status s) {
         S.used = false;
-        pool_free(b, off, 2 * one + tab);
+        pool_free(b, off, 2 * one + tab + ctr);
         return s;
     };
     if (hipMemcpyAsync(b->d_descs + free_slot, &D, sizeof(LatDesc), hipMemcpyHostToDevice, b->s) != hipSuccess)
         return undo(LB_E_HIP);
+    if (launch_set_step(D.tstep, 0, b->s) != hipSuccess) return undo(LB_E_HIP);
     if (cfg->surf == LB_SIGMA_LANGMUIR && launch_kappa_table(b->d_descs + free_slot, cfg->ny, b->s) != hipSuccess)
         return undo(LB_E_HIP);
     const int64_t N = (int64_t)cfg->nx * cfg->ny;
@@ -1316,6 +1329,33 @@ lb_status lb_batch_timing_read(lb_batch* b, double* ms_per_step, int64_t* steps)
     return LB_OK;
 }
 
+lb_status lb_batch_set_schedule(lb_batch* b, int32_t tile_x, int32_t mode, int32_t param, int32_t prefetch) {
+    if (!b || mode < 0 || mode > 2 || prefetch < 0 || prefetch > 1) return LB_E_INVALID_ARG;
+    if (!valid_width(tile_x, b->prec, prefetch)) return LB_E_INVALID_ARG;
+    if (prefetch && b->kind >= 0 && b->kind != KIND_COUPLED_CASCADED) return LB_E_INVALID_ARG;
+    if (mode == 0 ? param < kMinH : (param < 1 || param > 4)) return LB_E_INVALID_ARG;
+    Sched sc;
+    sc.tx = tile_x;
+    sc.mode = mode;
+    sc.pf = prefetch;
+    if (mode == 0) sc.th = param; else sc.mult = param;
+    HIPC(hipStreamSynchronize(b->s));
+    const Sched old = b->sc;
+    const bool old_fixed = b->fixed_tile;
+    b->sc = sc;
+    b->fixed_tile = true;
+    if (!batch_shapes(b).empty()) {  // check that the cut fits now
+        const lb_status st = batch_set_sched(b, sc);
+        if (st != LB_OK) {
+            b->sc = old;
+            b->fixed_tile = old_fixed;
+            return st == LB_E_WORKSPACE ? LB_E_INVALID_ARG : st;
+        }
+    }
+    b->dirty = true;  // the next step rebuilds the work list with this schedule (and the wall kind)
+    return LB_OK;
+}
+
 lb_status lb_batch_launch_counts(lb_batch* b, int64_t* graph_steps, int64_t* eager_steps) {
     if (!b || !graph_steps || !eager_steps) return LB_E_INVALID_ARG;
     *graph_steps = b->graph_steps;
@@ -1339,12 +1379,13 @@ lb_status lb_batch_get_schedule(lb_batch* b, int32_t* tile_x, int32_t* rows, int
 //
 // lb_step_noalloc advances a lattice whose two state buffers the caller owns,
 // with no handle and no workspace.  What the step kernels need beyond those
-// buffers -- the lattice descriptor, the work list and (Langmuir law only) the
-// per-row kappa~ table -- lives in `scratch`, a file-scope device array of fixed
-// size.  Each GPU holds its own copy until the process ends; its address on the
-// current device is looked up once (hipGetSymbolAddress) and kept per device.
-// Host code uses only that address, never the array's name.  Every call on one
-// device rewrites the descriptor, table and work list it uses before its step
+// buffers -- the lattice descriptor, the step counter that seeds the stochastic
+// rounding of 16-bit storage, the work list and (Langmuir law only) the per-row
+// kappa~ table -- lives in `scratch`, a file-scope device array of fixed size.
+// Each GPU holds its own copy until the process ends; its address on the current
+// device is looked up once (hipGetSymbolAddress) and kept per device.  Host code
+// uses only that address, never the array's name.  Every call on one device
+// rewrites the descriptor, counter, table and work list it uses before its step
 // kernels read them, so nothing has to start at zero; calls that overlap on one
 // device (different streams, or threads) race on the array.
 
@@ -1395,8 +1436,8 @@ __global__ void k_items_strips(WorkItem* __restrict__ out, int ny, int sw, int t
 extern "C" {
 
 lb_status lb_step_noalloc(const lb_config* cfg, void* state0, void* state1, uint64_t state_bytes,
-                          int64_t n, void* stream) {
-    if (!cfg || !state0 || !state1 || n < 0 || state0 == state1) return LB_E_INVALID_ARG;
+                          int64_t step, int64_t n, void* stream) {
+    if (!cfg || !state0 || !state1 || n < 0 || step < 0 || state0 == state1) return LB_E_INVALID_ARG;
     lb_status st = validate(cfg);
     if (st != LB_OK) return st;
     if (cfg->flow != LB_FLOW_COUPLED || cfg->diag_every != 0) return LB_E_UNSUPPORTED;
@@ -1411,8 +1452,9 @@ lb_status lb_step_noalloc(const lb_config* cfg, void* state0, void* state1, uint
     const int sw = strip_w(sc.tx);
     const int nrb = (cfg->ny + sc.th - 1) / sc.th;
     const int64_t n_items = (int64_t)((cfg->nx + sw - 1) / sw) * nrb;
-    // scratch layout: descriptor | kappa~ table (Langmuir law) | work list
-    const uint64_t o_tab = align_up(sizeof(LatDesc));
+    // scratch layout: descriptor | step counter | kappa~ table (Langmuir law) | work list
+    const uint64_t o_ctr = align_up(sizeof(LatDesc));
+    const uint64_t o_tab = o_ctr + align_up(2 * sizeof(uint32_t));
     const uint64_t tab = cfg->surf == LB_SIGMA_LANGMUIR ? align_up((uint64_t)2 * cfg->ny * sizeof(double)) : 0;
     const uint64_t o_items = o_tab + tab;
     if (o_items + (uint64_t)n_items * sizeof(WorkItem) > kScratchBytes) return LB_E_TOO_LARGE;
@@ -1424,12 +1466,14 @@ lb_status lb_step_noalloc(const lb_config* cfg, void* state0, void* state1, uint
     LatDesc D;
     fill_desc(cfg, D, state0, state1, P, nullptr);
     D.ktab = tab ? (double*)(scr + o_tab) : nullptr;
+    D.tstep = (uint32_t*)(scr + o_ctr);
     D.vel = nullptr;
     const bool walls = D.wall_y != WALL_NONE || D.wall_x != WALL_NONE;
     LatDesc* d_desc = (LatDesc*)scr;
     WorkItem* d_items = (WorkItem*)(scr + o_items);
     hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(64), 0, s, d_desc, D);
     HIPC(hipGetLastError());
+    HIPC(launch_set_step(D.tstep, (uint32_t)step, s));
     hipLaunchKernelGGL(k_items_strips, dim3((unsigned)((n_items + 255) / 256)), dim3(256), 0, s, d_items, cfg->ny,
                        sw, sc.th, nrb, (int)n_items);
     HIPC(hipGetLastError());

@@ -33,6 +33,8 @@ namespace cmlb {
 // ------------------------------------------------------------------ storage
 
 // `shifted`: whether the storage holds f_a - w_a shift (16-bit types only).
+// st_sr(v, r): the stored value rounded stochastically with the random bits r
+// (16-bit types; the wider types store v as it is).
 struct StF64 {
     using T = double;
     using R = double;
@@ -40,6 +42,7 @@ struct StF64 {
     static constexpr bool shifted = false;
     static __device__ __forceinline__ R ld(T v) { return v; }
     static __device__ __forceinline__ T st(R v) { return v; }
+    static __device__ __forceinline__ T st_sr(R v, uint32_t) { return v; }
 };
 struct StF32 {
     using T = float;
@@ -48,7 +51,14 @@ struct StF32 {
     static constexpr bool shifted = false;
     static __device__ __forceinline__ R ld(T v) { return v; }
     static __device__ __forceinline__ T st(R v) { return v; }
+    static __device__ __forceinline__ T st_sr(R v, uint32_t) { return v; }
 };
+// The gfx950 conversions with stochastic rounding (v_cvt_sr_f16_f32,
+// v_cvt_sr_bf16_f32) take their random bits from the high 16 bits of r: the
+// result is the representable neighbour above |v| with probability equal to the
+// fraction of the gap that |v| has passed, so the stored value is unbiased.
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+typedef short short2_t __attribute__((ext_vector_type(2)));
 struct StF16 {
     using T = _Float16;
     using R = float;
@@ -56,6 +66,11 @@ struct StF16 {
     static constexpr bool shifted = true;
     static __device__ __forceinline__ R ld(T v) { return (float)v; }
     static __device__ __forceinline__ T st(R v) { return (_Float16)v; }  // round to nearest even
+    static __device__ __forceinline__ T st_sr(R v, uint32_t r) {
+        half2_t h = {0, 0};
+        h = __builtin_amdgcn_cvt_sr_f16_f32(h, v, r, false);
+        return h.x;
+    }
 };
 struct StBF16 {
     using T = uint16_t;
@@ -69,6 +84,11 @@ struct StBF16 {
             return (T)((u >> 16) | 0x0040u);
         u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
         return (T)(u >> 16);
+    }
+    static __device__ __forceinline__ T st_sr(R v, uint32_t r) {
+        short2_t h = {0, 0};
+        h = __builtin_amdgcn_cvt_sr_bf16_f32(h, v, r, false);
+        return (T)(unsigned short)h.x;
     }
 };
 
@@ -84,11 +104,12 @@ struct alignas(16) LatDesc {
     int32_t surf;       // kappa~(y): 0 linear, 1 Langmuir of an imposed linear psi(y)
     int32_t flow;       // 0 coupled, 1 phase field only under an imposed velocity
     int32_t wall_x;     // walls at x = -1/2, nx - 1/2: same codes as wall_y
-    int32_t pad2;
+    int32_t sround;     // 16-bit storage: 1 stochastic rounding of the stored values, 0 nearest even
     void* buf[2];       // 18 stored values per node each, row-interleaved (see row_stride)
     double* fields;     // FP64 output planes (phi, p, ux, uy or the 9 coupling planes)
     void* vel;          // imposed velocity: planes ux, uy in the compute type (flow 1)
     double* ktab;       // Langmuir law: kappa~(y) for y < ny, then d kappa~/dy (surf 1)
+    uint32_t* tstep;    // tstep[p]: step count of the state in buf[p] (seeds the stochastic rounding)
     double rhoB, dRho;  // rho(phi) = rhoB + phi dRho
     double muB, dMu;    // mu(phi)  = muB + phi dMu
     double kt_a, kt_b;  // kappa~(y) = kt_a + kt_b y = 1.5 W sigma(y)
@@ -206,6 +227,65 @@ __device__ __forceinline__ void store_row(typename ST::T* row, int nx, int first
     }
 }
 
+// Random bits of the stochastic rounding.  seed_step: an integer hash of the step
+// count (uniform over the launch); node_hash: a hash of that seed and the node
+// (two multiply-xorshift rounds, Wellons' lowbias32 constants).  Stored value q of
+// the node (0..8 f, 9..17 gbar) then takes the low 32 bits of (h mod 2^24) x C_q,
+// one full-rate 24-bit multiply per value, with 18 odd 24-bit multipliers C_q: for
+// a uniform h the top 16 bits of each product (the bits the conversions use) are
+// uniform, and across q their pairwise correlation is below 0.003.  The bits depend
+// on the step and the node only, so every schedule stores the same values.
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+__device__ __forceinline__ uint32_t seed_step(uint32_t t) { return mix32(t * 0x9e3779b9u + 0x7f4a7c15u); }
+__device__ __forceinline__ uint32_t node_hash(uint32_t seed, int x, int y) {
+    return mix32(seed ^ ((uint32_t)y * 0x85ebca6bu + (uint32_t)x));
+}
+constexpr uint32_t kSRMul[18] = {0xa58a9du, 0xfb4889u, 0x987a27u, 0xb9e081u, 0xe3f42fu, 0xe90a67u,
+                                 0xfe72f1u, 0x8a7dabu, 0x937427u, 0x99dcefu, 0xae49f3u, 0xbe1d1bu,
+                                 0xd0335du, 0xfcb1d9u, 0xdf8a85u, 0xd8aadfu, 0xbd9efbu, 0x8eca35u};
+
+// As store_row, rounding value first + a stochastically with the bits of node hash h.
+template <class ST, int N, bool BUF>
+__device__ __forceinline__ void store_row_sr(typename ST::T* row, int nx, int first, int col,
+                                             const typename ST::R* v, uint32_t h) {
+    using T = typename ST::T;
+    gmem_t<char>* base = (gmem_t<char>*)row;
+    const uint32_t P = (uint32_t)nx * (uint32_t)sizeof(T), b = (uint32_t)col * (uint32_t)sizeof(T);
+    const uint32_t h24 = h & 0xffffffu;
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+        const T s = ST::st_sr(v[a], h24 * kSRMul[first + a]);
+        if constexpr (BUF) {
+            const rsrc_t R = row_rsrc(row);
+            __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, s), R, (int)b,
+                                                  (int)((uint32_t)(first + a) * P), 0);
+        } else {
+            *(gmem_t<T>*)(base + (uint32_t)(first + a) * P + b) = s;
+        }
+    }
+}
+
+// The nine collided values of a node from value `first` on: rounded
+// stochastically with node hash h when sr (16-bit storage), else to nearest.
+template <class ST, bool BUF>
+__device__ __forceinline__ void store_collided(bool sr, typename ST::T* row, int nx, int first, int col,
+                                               const typename ST::R* v, uint32_t h) {
+    if constexpr (ST::shifted) {
+        if (sr) {
+            store_row_sr<ST, 9, BUF>(row, nx, first, col, v, h);
+            return;
+        }
+    }
+    store_row<ST, 9, BUF>(row, nx, first, col, v);
+}
+
 // Buffer layout: the 18 stored values of a lattice are row-interleaved, value q
 // (0..8 f, 9..17 gbar) of node (x, y) at element (18 y + q) nx + x.  The nine f
 // (or gbar) rows of one lattice row form one contiguous block, so a workgroup
@@ -318,6 +398,63 @@ __device__ __forceinline__ R sum9(const R v[9]) {
     return s;
 }
 
+// What the cascaded collisions read of the pulled values (see ace_collide and
+// hydro_collide): of f the sum of the stored values and the first moments k10,
+// k01; of gbar the first moments j and the two shear differences of its raw
+// second moments, (g1 + g3) - (g2 + g4) = eta_20 - eta_02 and (g5 - g6) + (g7 - g8)
+// = eta_11.  The sum of gbar (pbar) goes to the LDS ring when the row is pulled.
+// The row pipeline of the fused step holds these instead of the nine values (the
+// SRT collisions read every value and hold them all).
+template <class R>
+struct FMom {
+    R tot, k10, k01;
+};
+template <class R>
+struct GMom {
+    R jx, jy, nd, xd;
+};
+template <class R>
+struct Vals9 {
+    R v[9];
+};
+template <class R>
+__device__ __forceinline__ R first_x(const R v[9]) {
+    return (v[1] - v[3]) + (v[5] - v[6]) + (v[8] - v[7]);
+}
+template <class R>
+__device__ __forceinline__ R first_y(const R v[9]) {
+    return (v[2] - v[4]) + (v[5] + v[6]) - (v[7] + v[8]);
+}
+template <class R>
+__device__ __forceinline__ void hold(FMom<R>& h, const R v[9]) {
+    h.tot = sum9(v);
+    h.k10 = first_x(v);
+    h.k01 = first_y(v);
+}
+template <class R>
+__device__ __forceinline__ void hold(GMom<R>& h, const R v[9]) {
+    h.jx = first_x(v);
+    h.jy = first_y(v);
+    h.nd = (v[1] + v[3]) - (v[2] + v[4]);
+    h.xd = (v[5] - v[6]) + (v[7] - v[8]);
+}
+template <class R>
+__device__ __forceinline__ void hold(Vals9<R>& h, const R v[9]) {
+#pragma unroll
+    for (int a = 0; a < 9; ++a) h.v[a] = v[a];
+}
+template <class R>
+__device__ __forceinline__ R held_sum(const FMom<R>& h) { return h.tot; }
+template <class R>
+__device__ __forceinline__ R held_sum(const Vals9<R>& h) { return sum9(h.v); }
+template <class R>
+__device__ __forceinline__ void held_first(const GMom<R>& h, R& jx, R& jy) { jx = h.jx; jy = h.jy; }
+template <class R>
+__device__ __forceinline__ void held_first(const Vals9<R>& h, R& jx, R& jy) {
+    jx = first_x(h.v);
+    jy = first_y(h.v);
+}
+
 // Isotropic D2Q9 gradient (1/c^2) sum_a w_a e_a q(x + e_a) from a 3x3 patch:
 // rows s (y-1), m (y), n (y+1); columns c-1, c, c+1.
 template <class R>
@@ -406,8 +543,8 @@ struct NodeOut {
 // surfacetensionthermodynamic, netgradientpressureforce, hydrodynamicfields,
 // fluidviscosity).
 template <class R>
-__device__ __forceinline__ NodeOut<R> node_macro(const KConst<R>& K, int chem, const NodeIn<R>& in,
-                                                 const R g[9]) {
+__device__ __forceinline__ NodeOut<R> node_macro(const KConst<R>& K, int chem, const NodeIn<R>& in, R jx,
+                                                 R jy) {
     NodeOut<R> o;
     const R rho = K.rhoB + in.phi * K.dRho;
     const R mu = K.muB + in.phi * K.dMu;
@@ -429,8 +566,6 @@ __device__ __forceinline__ NodeOut<R> node_macro(const KConst<R>& K, int chem, c
     const R bf = rho - K.rho_ref;
     o.Ftx = Fsx + bf * K.gx;
     o.Fty = Fsy + bf * K.gy;
-    const R jx = (g[1] - g[3]) + (g[5] - g[6]) + (g[8] - g[7]);
-    const R jy = (g[2] - g[4]) + (g[5] + g[6]) - (g[7] + g[8]);
     o.jx = jx;
     o.jy = jy;
     o.ux = (R(3) * jx + R(0.5) * o.Ftx) * inv_rho;
@@ -478,17 +613,15 @@ __device__ __forceinline__ NodeOut<R> node_macro(const KConst<R>& K, int chem, c
 // stated, with the central moments of the incoming gbar itself (zeroth moment
 // pbar, first j) and the source-driven h_0..h_2 carried into the higher central
 // moments, instead of the printed closed forms of h_3..h_8 (which leave those two
-// effects out).  The post-collision raw moments then differ from the ones above by
-//   T   - (2/3) G
-//   D   - (1 - omv)/6  [3 (ux^2 - uy^2) G - 2 (F_tx ux - F_ty uy)]
-//   m11 - (1 - omv)/6  [3 ux uy G - (F_tx uy + F_ty ux)]
-//   m21 - c^4 F_ty - (1 - omv)/36 [9 uy (5 ux^2 - uy^2) G - 18 F_tx ux uy - 12 F_ty ux^2 + 6 F_ty uy^2]
-//   m12 - c^4 F_tx + (1 - omv)/36 [9 ux (ux^2 - 5 uy^2) G - 6 F_tx ux^2 + 12 F_tx uy^2 + 18 F_ty ux uy]
-//   m22 - 2 c^4 G  + (1 - omv)/36 [9 (ux^4 - 10 ux^2 uy^2 + uy^4) G - 6 (F_tx ux^3 + F_ty uy^3)
-//                                  + 30 ux uy (F_tx uy + F_ty ux)]
-// (a symbolic identity with the numerical solve of the same conditions).
+// effects out).  The post-collision raw moments are then the ones above with the
+// shear non-equilibria taken about u,
+//   N' = N + c^2 (F_tx ux - F_ty uy) - (ux^2 - uy^2) G / 2,
+//   X' = X + c^2 (F_tx uy + F_ty ux) / 2 - ux uy G / 2,
+// and without the force terms (2/3) G of m20 + m02, c^4 F_ty of m21, c^4 F_tx of
+// m12 and 2 c^4 G of m22 (a symbolic identity with the numerical solve of the same
+// conditions; it costs the printed form's operations).
 template <class R, bool SH = false, bool SOLVED = false>
-__device__ __forceinline__ void hydro_collide(R g[9], const NodeOut<R>& o, R sh = R(0)) {
+__device__ __forceinline__ void hydro_collide(R g[9], const NodeOut<R>& o, R nd, R xd, R sh = R(0)) {
     const R ux = o.ux, uy = o.uy, ux2 = ux * ux, uy2 = uy * uy, uxy = ux * uy;
     const R third = R(1.0 / 3.0), ninth = R(1.0 / 9.0);
     const R rc2 = o.rho * third;
@@ -496,35 +629,25 @@ __device__ __forceinline__ void hydro_collide(R g[9], const NodeOut<R>& o, R sh 
     const R Sx = o.Ftx + o.Fpx, Sy = o.Fty + o.Fpy;
     const R hw = R(1) - R(0.5) * o.omv;
     const R om1 = R(1) - o.omv;
-    const R nn = om1 * (((g[1] + g[3]) - (g[2] + g[4])) - rc2 * (ux2 - uy2));
-    const R xx = om1 * (((g[5] - g[6]) + (g[7] - g[8])) - rc2 * uxy);
+    R nraw = nd - rc2 * (ux2 - uy2);  // N
+    R xraw = xd - rc2 * uxy;          // X
+    if constexpr (SOLVED) {  // N', X': the non-equilibria about u
+        nraw += third * (o.Ftx * ux - o.Fty * uy) - R(0.5) * (ux2 - uy2) * Gam;
+        xraw += R(1.0 / 6.0) * (o.Ftx * uy + o.Fty * ux) - R(0.5) * uxy * Gam;
+    }
+    const R nn = om1 * nraw;
+    const R xx = om1 * xraw;
     const R m00 = o.p + R(0.5) * Gam - (SH ? sh : R(0));
     const R m10 = o.jx + third * o.Ftx, m01 = o.jy + third * o.Fty;
-    R T = R(2.0 / 3.0) * o.p + rc2 * (ux2 + uy2) + R(4.0 / 3.0) * Gam +
+    const R T = R(2.0 / 3.0) * o.p + rc2 * (ux2 + uy2) + (SOLVED ? R(2.0 / 3.0) : R(4.0 / 3.0)) * Gam +
                 third * (o.Ftx * ux + o.Fty * uy) - (SH ? R(2.0 / 3.0) * sh : R(0));
-    R D = rc2 * (ux2 - uy2) + nn + hw * R(2.0 / 3.0) * (Sx * ux - Sy * uy);
-    R m11 = rc2 * uxy + xx + hw * third * (Sx * uy + Sy * ux);
-    R m21 = rc2 * uy * (third + ux2) + ninth * o.Fty + R(0.5) * uy * nn + R(2) * ux * xx;
-    R m12 = rc2 * ux * (third + uy2) + ninth * o.Ftx - R(0.5) * ux * nn + R(2) * uy * xx;
-    R m22 = ninth * o.p + o.rho * (ninth * (ux2 + uy2) + third * ux2 * uy2) +
-            R(2.0 / 9.0) * Gam - R(0.5) * (ux2 - uy2) * nn + R(4) * uxy * xx -
-            (SH ? ninth * sh : R(0));
-    if constexpr (SOLVED) {
-        const R fu = o.Ftx * ux - o.Fty * uy, fv = o.Ftx * uy + o.Fty * ux;
-        const R o6 = om1 * R(1.0 / 6.0), o36 = om1 * R(1.0 / 36.0);
-        T -= R(2.0 / 3.0) * Gam;
-        D -= o6 * (R(3) * (ux2 - uy2) * Gam - R(2) * fu);
-        m11 -= o6 * (R(3) * uxy * Gam - fv);
-        m21 -= ninth * o.Fty +
-               o36 * (R(9) * uy * (R(5) * ux2 - uy2) * Gam - R(18) * o.Ftx * uxy - R(12) * o.Fty * ux2 +
-                      R(6) * o.Fty * uy2);
-        m12 += o36 * (R(9) * ux * (ux2 - R(5) * uy2) * Gam - R(6) * o.Ftx * ux2 + R(12) * o.Ftx * uy2 +
-                      R(18) * o.Fty * uxy) -
-               ninth * o.Ftx;
-        m22 += o36 * (R(9) * (ux2 * ux2 - R(10) * ux2 * uy2 + uy2 * uy2) * Gam -
-                      R(6) * (o.Ftx * ux * ux2 + o.Fty * uy * uy2) + R(30) * uxy * fv) -
-               R(2.0 / 9.0) * Gam;
-    }
+    const R D = rc2 * (ux2 - uy2) + nn + hw * R(2.0 / 3.0) * (Sx * ux - Sy * uy);
+    const R m11 = rc2 * uxy + xx + hw * third * (Sx * uy + Sy * ux);
+    const R m21 = rc2 * uy * (third + ux2) + (SOLVED ? R(0) : ninth * o.Fty) + R(0.5) * uy * nn + R(2) * ux * xx;
+    const R m12 = rc2 * ux * (third + uy2) + (SOLVED ? R(0) : ninth * o.Ftx) - R(0.5) * ux * nn + R(2) * uy * xx;
+    const R m22 = ninth * o.p + o.rho * (ninth * (ux2 + uy2) + third * ux2 * uy2) +
+                  (SOLVED ? R(0) : R(2.0 / 9.0) * Gam) - R(0.5) * (ux2 - uy2) * nn + R(4) * uxy * xx -
+                  (SH ? ninth * sh : R(0));
     // inverse of the moment map (m20 = (T + D)/2, m02 = (T - D)/2)
     const R a = R(0.5) * (T + D) - m22, b = m10 - m12;
     const R c = R(0.5) * (T - D) - m22, d = m01 - m21;
@@ -572,12 +695,12 @@ __device__ __forceinline__ void ace_axis(R u, Axis3<R>& W, Axis3<R>& D, Axis3<R>
     D.m = u - R(0.5); D.z = R(-2) * u; D.p = u + R(0.5);
     V.m = hv - hu; V.z = R(1) - u2; V.p = hv + hu;
 }
+// From the held moments of the pulled f (m.tot is read only when shifted).
 template <class R, bool SH = false>
-__device__ __forceinline__ void ace_collide(R f[9], R phi, R ux, R uy, R Mth_x, R Mth_y,
+__device__ __forceinline__ void ace_collide(R f[9], const FMom<R>& m, R phi, R ux, R uy, R Mth_x, R Mth_y,
                                             R omphi, R sh = R(0)) {
-    const R tot = SH ? sum9(f) : phi;  // sum of the stored values
-    const R k10 = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
-    const R k01 = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+    const R tot = SH ? m.tot : phi;  // sum of the stored values
+    const R k10 = m.k10, k01 = m.k01;
     const R a = k10 + omphi * (phi * ux + Mth_x - k10) - ux * phi;
     const R b = k01 + omphi * (phi * uy + Mth_y - k01) - uy * phi;
     Axis3<R> Wx, Dx, Vx, Wy, Dy, Vy;
@@ -597,6 +720,14 @@ __device__ __forceinline__ void ace_collide(R f[9], R phi, R ux, R uy, R Mth_x, 
     f[7] = P.m * Wy.m - s5 + A.m * Vy.m + Vx.m * B.m;
     f[8] = P.p * Wy.m - s5 + A.p * Vy.m + Vx.p * B.m;
     f[0] = tot - (((f[1] + f[2]) + (f[3] + f[4])) + ((f[5] + f[6]) + (f[7] + f[8])));
+}
+// From the nine pulled values, collided in place.
+template <class R, bool SH = false>
+__device__ __forceinline__ void ace_collide(R f[9], R phi, R ux, R uy, R Mth_x, R Mth_y, R omphi,
+                                            R sh = R(0)) {
+    FMom<R> m;
+    hold(m, f);
+    ace_collide<R, SH>(f, m, phi, ux, uy, Mth_x, Mth_y, omphi, sh);
 }
 
 // --------------------------------------------------- SRT collisions (Sec. 7)
@@ -656,22 +787,25 @@ __device__ __forceinline__ void ace_srt(R f[9], R phi, R ux, R uy, R Mth_x, R Mt
 
 // ------------------------------------------------------------- fused kernel
 
-// The values pulled for phi (two rows ahead of the collision) and for pbar (one
-// row ahead) stay in registers until their row collides.  PF_PREFETCH: each row
-// iteration starts by issuing the pulls of the next one (f at the next leading
-// row, gbar at the next pbar row) into registers of the stored type; they are
-// converted when the iteration ends, so those loads are in flight through the
+// What the collisions read of the rows pulled for phi (two rows ahead of the
+// collision) and for pbar (one row ahead) stays in registers until their row
+// collides: three moments of f and four of gbar for the cascaded pair, the nine
+// values for the SRT pair.  PF_PREFETCH: each row iteration starts by issuing the
+// pulls of the next one (f at the next leading row, gbar at the next pbar row)
+// into registers of the stored type; they are converted and reduced to the held
+// moments when the iteration ends, so those loads are in flight through the
 // barriers, the stencils and both collisions (18 values more per lane).
 //
-// Register budget: the kernels are built for ST::waves resident waves per SIMD,
-// except the FP64 cascaded kernel without prefetching, whose 166 VGPRs allow three
-// (the prefetching and SRT FP64 kernels would spill at three), and the prefetching
-// 16-bit kernels, which would spill at four and are built for three.
+// Register budget (resident waves per SIMD the kernels are built for): holding
+// moments, the cascaded kernels without prefetching need about 110 VGPRs in FP64
+// (four waves) and 85-95 in FP32 and 16-bit storage (five, so that two workgroups
+// of nine waves fit a CU); the FP64 prefetching and SRT kernels about 150-165
+// (three); the rest fits in ST::waves.
 template <class ST, int PF, int COLL>
 constexpr int fused_waves() {
-    if (ST::waves == 2) return (PF == PF_HOLD && COLL == COLL_CASCADED) ? 3 : 2;
-    if (ST::shifted && PF == PF_PREFETCH) return 3;
-    return ST::waves;
+    const bool lean = PF == PF_HOLD && COLL != COLL_SRT;
+    if (ST::waves == 2) return lean ? 4 : 3;
+    return lean ? 5 : ST::waves;
 }
 
 //
@@ -688,13 +822,11 @@ lb_fused(const LatDesc* __restrict__ descs, const WorkItem* __restrict__ items, 
     using R = typename ST::R;
     using T = typename ST::T;
     // Role-based register pipeline (see below): the coupled cascaded step with 16-
-    // or 32-bit storage, without prefetching or walls.  Elsewhere it is not used:
-    // FP64 waits on memory, the FP32 prefetching and the SRT kernels would spill,
-    // the 16-bit prefetching one gained nothing, and the wall logic unrolled six
-    // times (about 6000 instructions) outgrows the instruction cache (a batch with
-    // walled lattices ran 14% slower with it).
-    constexpr bool kRoles =
-        MODE == MODE_STEP && PF == PF_HOLD && COLL == COLL_CASCADED && sizeof(T) < 8 && !WALLS;
+    // or 32-bit storage without walls.  Elsewhere it is not used: FP64 waits on
+    // memory, the SRT kernels would spill, and the wall logic unrolled six times
+    // (about 6000 instructions) outgrows the instruction cache (a batch with walled
+    // lattices ran 14% slower with it).
+    constexpr bool kRoles = MODE == MODE_STEP && COLL == COLL_CASCADED && sizeof(T) < 8 && !WALLS;
     constexpr int RING = kRoles ? 6 : 4;  // rows held in each LDS ring
     __shared__ R s_phi[RING][TX];
     __shared__ R s_pb[RING][TX];
@@ -709,6 +841,19 @@ lb_fused(const LatDesc* __restrict__ descs, const WorkItem* __restrict__ items, 
         const int nx = D.nx, ny = D.ny, chem = D.st_form;
         const int wall = WALLS ? D.wall_y : WALL_NONE, wallx = WALLS ? D.wall_x : WALL_NONE;
         const KConst<R> K = load_const<R>(D);
+        // Stochastic rounding of 16-bit stores: the step count of the state read now
+        // seeds the random bits, and the launch records the count of the state it
+        // writes (every work item of the lattice stores the same value).
+        uint32_t tseed = 0;
+        bool sr = false;
+        if constexpr (ST::shifted && MODE == MODE_STEP) {
+            sr = D.sround != 0;
+            if (sr) {
+                const uint32_t tv = D.tstep[parity];
+                if (threadIdx.x == 0) D.tstep[parity ^ 1] = tv + 1u;
+                tseed = seed_step(tv);
+            }
+        }
         const double* ktab = D.surf ? D.ktab : nullptr;  // per-row Langmuir table
         const T* __restrict__ src = reinterpret_cast<const T*>(D.buf[parity]);
         T* __restrict__ dst = reinterpret_cast<T*>(D.buf[parity ^ 1]);
@@ -732,13 +877,30 @@ lb_fused(const LatDesc* __restrict__ descs, const WorkItem* __restrict__ items, 
         // in F[k % 3], G[k % 2] and entry k % 2, the rings hold the row leading in
         // iteration k in slot k % 6, and the loop is unrolled six times so that
         // every role and slot is a constant: nothing is moved between iterations.
-        R F[3][9], G[2][9];
+        // The prefetched rows (PF_PREFETCH) are then reduced into the entries the
+        // collision has just consumed, F[(k + 1) % 3] and G[(k + 1) % 2], which are
+        // the next iteration's leading ones.
+        // Each F and G entry holds what the collision reads of its row (FMom,
+        // GMom), or the nine values for the SRT collisions.
+        constexpr bool kMom = COLL != COLL_SRT;
+        using HF = std::conditional_t<kMom, FMom<R>, Vals9<R>>;
+        using HG = std::conditional_t<kMom, GMom<R>, Vals9<R>>;
+        HF F[3];
+        HG G[2];
         T nf[9], ng[9];  // next rows' pulls in flight (PF_PREFETCH)
+        R Pn = R(0);     // sum of the prefetched gbar (PF_PREFETCH)
         R Dx[2], Dy[2], Dm[2], Nx[2], Ny[2];  // grad phi, |grad phi|^2, normal
+        {
+            R z[9];
 #pragma unroll
-        for (int a = 0; a < 9; ++a) {
-            F[0][a] = F[1][a] = F[2][a] = G[0][a] = G[1][a] = R(0);
-            nf[a] = ng[a] = T(0);
+            for (int a = 0; a < 9; ++a) {
+                z[a] = R(0);
+                nf[a] = ng[a] = T(0);
+            }
+            hold(F[0], z);
+            F[2] = F[1] = F[0];
+            hold(G[0], z);
+            G[1] = G[0];
         }
 #pragma unroll
         for (int j = 0; j < 2; ++j) Dx[j] = Dy[j] = Dm[j] = Nx[j] = Ny[j] = R(0);
@@ -751,10 +913,10 @@ lb_fused(const LatDesc* __restrict__ descs, const WorkItem* __restrict__ items, 
         // the gradient found now and one iteration ago.
         auto row_step = [&](const int k, auto S0, auto S1, auto S2, auto S3, auto fo, auto ft, auto go, auto gt,
                             auto dw, auto dr) __attribute__((always_inline)) {
-            R* const f0 = F[fo];
-            R* const f2 = F[ft];
-            R* const g0 = G[go];
-            R* const g1 = G[gt];
+            HF& f0 = F[fo];
+            const HF& f2 = F[ft];
+            HG& g0 = G[go];
+            const HG& g1 = G[gt];
             const int L = it.y0 - 2 + k;
             if constexpr (!kBufIO<ST>) lane_columns_in_loop(xc, xm, xp);
             if (ahead && k + 1 < H + 4) {  // the next iteration's pulls
@@ -763,16 +925,25 @@ lb_fused(const LatDesc* __restrict__ descs, const WorkItem* __restrict__ items, 
             }
             // ---- A: phi at the leading row
             if (inA) {
-                if (!ahead || k == 0) pull9<ST, kBufIO<ST>>(src, nx, ny, wall, wallx, xc, xm, xp, map_row(L, ny, wall), f0);
-                R ph = sum9(f0);
+                if (!ahead || k == 0) {
+                    R v[9];
+                    pull9<ST, kBufIO<ST>>(src, nx, ny, wall, wallx, xc, xm, xp, map_row(L, ny, wall), v);
+                    hold(f0, v);
+                }
+                R ph = held_sum(f0);
                 if constexpr (ST::shifted) ph += K.shf;
                 s_phi[S0][t] = ph;
             }
             // ---- B: pbar one row behind
             if (k >= 2 && inB) {
                 const int Lg = L - 1;
-                if (!ahead || k == 2) pull9<ST, kBufIO<ST>>(srcg, nx, ny, wall, wallx, xc, xm, xp, map_row(Lg, ny, wall), g0);
-                R pb = sum9(g0);
+                R pb = Pn;
+                if (!ahead || k == 2) {
+                    R v[9];
+                    pull9<ST, kBufIO<ST>>(srcg, nx, ny, wall, wallx, xc, xm, xp, map_row(Lg, ny, wall), v);
+                    hold(g0, v);
+                    pb = sum9(v);
+                }
                 if constexpr (ST::shifted) pb += K.shg;
                 s_pb[S1][t] = pb;
             }
@@ -823,25 +994,35 @@ lb_fused(const LatDesc* __restrict__ descs, const WorkItem* __restrict__ items, 
                         grad3x3(s_nb[S3], s_nb[S2], s_nb[S1], t, b1, b2);
                         in.divn = a1 + b2;
                     }
-                    o = node_macro<R>(K, chem, in, g1);
+                    R jx, jy;
+                    held_first(g1, jx, jy);
+                    o = node_macro<R>(K, chem, in, jx, jy);
                     idx = (uint32_t)C * (uint32_t)nx + (uint32_t)xc;
                 }
                 if constexpr (MODE == MODE_STEP) {
+                    // gbar first: fewer values stay live across the second collision
+                    const uint32_t hn = ST::shifted && sr ? node_hash(tseed, xc, C) : 0u;
                     if (inF) {
-                        const R Mth = K.M * (K.four_W * in.phi * (R(1) - in.phi));
-                        if constexpr (COLL == COLL_SRT)
-                            ace_srt<R, ST::shifted>(f2, in.phi, o.ux, o.uy, Mth * in.nx, Mth * in.ny, K.omphi, K.shf);
-                        else
-                            ace_collide<R, ST::shifted>(f2, in.phi, o.ux, o.uy, Mth * in.nx, Mth * in.ny, K.omphi,
-                                                        K.shf);
-                        store_row<ST, 9, kBufIO<ST>>(row_at(dst, C, nx), nx, 0, xc, f2);
+                        R v[9];
+                        if constexpr (COLL == COLL_SRT) {
+                            for (int a = 0; a < 9; ++a) v[a] = g1.v[a];
+                            hydro_srt<R, ST::shifted>(v, o, K.shg);
+                        } else {
+                            hydro_collide<R, ST::shifted, COLL != COLL_PRINTED>(v, o, g1.nd, g1.xd, K.shg);
+                        }
+                        store_collided<ST, kBufIO<ST>>(sr, row_at(dst, C, nx), nx, 9, xc, v, hn);
                     }
                     if (inF) {
-                        if constexpr (COLL == COLL_SRT)
-                            hydro_srt<R, ST::shifted>(g1, o, K.shg);
-                        else
-                            hydro_collide<R, ST::shifted, COLL != COLL_PRINTED>(g1, o, K.shg);
-                        store_row<ST, 9, kBufIO<ST>>(row_at(dst, C, nx), nx, 9, xc, g1);
+                        const R Mth = K.M * (K.four_W * in.phi * (R(1) - in.phi));
+                        R v[9];
+                        if constexpr (COLL == COLL_SRT) {
+                            for (int a = 0; a < 9; ++a) v[a] = f2.v[a];
+                            ace_srt<R, ST::shifted>(v, in.phi, o.ux, o.uy, Mth * in.nx, Mth * in.ny, K.omphi, K.shf);
+                        } else {
+                            ace_collide<R, ST::shifted>(v, f2, in.phi, o.ux, o.uy, Mth * in.nx, Mth * in.ny, K.omphi,
+                                                        K.shf);
+                        }
+                        store_collided<ST, kBufIO<ST>>(sr, row_at(dst, C, nx), nx, 0, xc, v, hn);
                     }
                 } else if constexpr (MODE == MODE_FIELDS) {
                     if (inF) {
@@ -869,12 +1050,24 @@ lb_fused(const LatDesc* __restrict__ descs, const WorkItem* __restrict__ items, 
                 }
             }
         };
+        // The prefetched rows, converted and reduced into F entry fn and G entry gn.
+        auto take_prefetch = [&](HF& fn, HG& gn) __attribute__((always_inline)) {
+            R v[9];
+#pragma unroll
+            for (int a = 0; a < 9; ++a) v[a] = ST::ld(nf[a]);
+            hold(fn, v);
+#pragma unroll
+            for (int a = 0; a < 9; ++a) v[a] = ST::ld(ng[a]);
+            hold(gn, v);
+            Pn = sum9(v);
+        };
         if constexpr (kRoles) {
             // slots and roles of iteration k = k0 + PH
             auto phase = [&](auto Pc, const int k) __attribute__((always_inline)) {
                 constexpr int PH = decltype(Pc)::value;
                 row_step(k, IC<PH>{}, IC<(PH + 5) % 6>{}, IC<(PH + 4) % 6>{}, IC<(PH + 3) % 6>{}, IC<PH % 3>{},
                          IC<(PH + 1) % 3>{}, IC<PH % 2>{}, IC<(PH + 1) % 2>{}, IC<PH % 2>{}, IC<(PH + 1) % 2>{});
+                if constexpr (ahead) take_prefetch(F[(PH + 1) % 3], G[(PH + 1) % 2]);
             };
             for (int k0 = 0; k0 < H + 4; k0 += 6) {
                 phase(IC<0>{}, k0);
@@ -890,16 +1083,10 @@ lb_fused(const LatDesc* __restrict__ descs, const WorkItem* __restrict__ items, 
                 row_step(k, L & 3, (L - 1) & 3, (L - 2) & 3, (L - 3) & 3, IC<0>{}, IC<2>{}, IC<0>{}, IC<1>{}, IC<0>{},
                          IC<1>{});
                 // ---- shift the register pipeline
-#pragma unroll
-                for (int a = 0; a < 9; ++a) {
-                    F[2][a] = F[1][a];
-                    F[1][a] = F[0][a];
-                    G[1][a] = G[0][a];
-                    if constexpr (ahead) {
-                        F[0][a] = ST::ld(nf[a]);
-                        G[0][a] = ST::ld(ng[a]);
-                    }
-                }
+                F[2] = F[1];
+                F[1] = F[0];
+                G[1] = G[0];
+                if constexpr (ahead) take_prefetch(F[0], G[0]);
                 Dx[1] = Dx[0]; Dy[1] = Dy[0]; Dm[1] = Dm[0]; Nx[1] = Nx[0]; Ny[1] = Ny[0];
             }
         }
@@ -935,6 +1122,16 @@ __global__ void __launch_bounds__(TX) lb_ace(const LatDesc* __restrict__ descs,
         const T* __restrict__ src = reinterpret_cast<const T*>(D.buf[parity]);
         T* __restrict__ dst = reinterpret_cast<T*>(D.buf[parity ^ 1]);
         const R* __restrict__ vel = reinterpret_cast<const R*>(D.vel);
+        uint32_t tseed = 0;  // stochastic rounding of 16-bit stores, as in lb_fused
+        bool sr = false;
+        if constexpr (ST::shifted && MODE == MODE_STEP) {
+            sr = D.sround != 0;
+            if (sr) {
+                const uint32_t tv = D.tstep[parity];
+                if (threadIdx.x == 0) D.tstep[parity ^ 1] = tv + 1u;
+                tseed = seed_step(tv);
+            }
+        }
         const int w = min(TX - 4, nx - it.x0);
         const bool inA = t < w + 4;
         const bool inF = t >= 2 && t < w + 2;
@@ -971,7 +1168,8 @@ __global__ void __launch_bounds__(TX) lb_ace(const LatDesc* __restrict__ descs,
                         ace_srt<R, ST::shifted>(f1, phi, ux, uy, Mth * ix, Mth * iy, omphi, shf);
                     else
                         ace_collide<R, ST::shifted>(f1, phi, ux, uy, Mth * ix, Mth * iy, omphi, shf);
-                    store_row<ST, 9, kBufIOAce<ST>>(row_at(dst, C, nx), nx, 0, xc, f1);
+                    store_collided<ST, kBufIOAce<ST>>(sr, row_at(dst, C, nx), nx, 0, xc, f1,
+                                                       ST::shifted && sr ? node_hash(tseed, xc, C) : 0u);
                 } else {
                     double* F = D.fields;
                     const int64_t N = (int64_t)nx * ny;

@@ -25,6 +25,8 @@ hipError_t launch_state_op(int prec, int op, const LatDesc* d, double* plane, in
 hipError_t launch_diag(const LatDesc* d, const double* fields, double* part, double* out, int ny,
                        double step, double u_max, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, uint64_t n, hipStream_t s);
+// Sets both slots of a step counter (LatDesc::tstep) to t.
+hipError_t launch_set_step(uint32_t* tstep, uint32_t t, hipStream_t s);
 // Bandwidth probe variants (see lb_bandwidth_probe in cmlb.h).
 hipError_t launch_bandwidth_probe(void* dst, const void* src, uint64_t n, int variant, hipStream_t s);
 // Built-in initial phase field of an lb_config (init_kind, init_par, W) into an

@@ -28,6 +28,7 @@ LB_FREF = {"mean": 0, "light": 1, "heavy": 2, "none": 3}
 LB_ST = {"geometric": 0, "chempot": 1}
 PRECISION = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
 LB_INIT = {"none": 0, "droplet": 1, "ellipse": 2, "interface": 3}
+LB_ROUND = {"stochastic": 0, "nearest": 1}
 STORE_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2}
 
 
@@ -49,7 +50,7 @@ class lb_config(ctypes.Structure):
         ("collision", ctypes.c_int32), ("flow", ctypes.c_int32),
         ("surf", ctypes.c_int32), ("tile_pf", ctypes.c_int32),
         ("beta", ctypes.c_double), ("psi_a", ctypes.c_double), ("psi_G", ctypes.c_double),
-        ("init_kind", ctypes.c_int32), ("init_pad_", ctypes.c_int32), ("init_par", ctypes.c_double * 8),
+        ("init_kind", ctypes.c_int32), ("rounding", ctypes.c_int32), ("init_par", ctypes.c_double * 8),
     ]
 
 
@@ -112,10 +113,12 @@ _SIGS = {
     "lb_set_schedule": ([_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32], ctypes.c_int32),
     "lb_batch_get_schedule": ([_vp, _i32p, _i32p, _i32p, _i32p], ctypes.c_int32),
     "lb_batch_launch_counts": ([_vp, _i64p, _i64p], ctypes.c_int32),
+    "lb_batch_set_schedule": ([_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
+                              ctypes.c_int32),
     "lb_struct_sizes": ([_u64p, _u64p], ctypes.c_int32),
     "lb_copy_kernel": ([_vp, _vp, ctypes.c_uint64, _vp], ctypes.c_int32),
     "lb_bandwidth_probe": ([_vp, _vp, ctypes.c_uint64, ctypes.c_int32, _vp], ctypes.c_int32),
-    "lb_step_noalloc": ([ctypes.POINTER(lb_config), _vp, _vp, ctypes.c_uint64, ctypes.c_int64, _vp],
+    "lb_step_noalloc": ([ctypes.POINTER(lb_config), _vp, _vp, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, _vp],
                         ctypes.c_int32),
 }
 
@@ -162,19 +165,26 @@ def _dptr(a: np.ndarray | None):
     return a.ctypes.data_as(_dp)
 
 
-# Default storage shift of the phase-field values in 16-bit storage (f_a is
-# stored as f_a - w_a SHIFT_F).  With 9/16 the shifts w_a 9/16 are 1/4, 1/16 and
-# 1/64, exact in fp16 and bf16, so the ambient phase (phi = 0) is stored without
-# rounding; with 1/2 the same rounding of w_a / 2 recurred at every node and step
-# and left phi offset by about 1.2e-4 throughout the ambient fluid.
-SHIFT_F = 9.0 / 16.0
+def default_shift_f(case: dict) -> float:
+    """Storage shift of the phase-field values in 16-bit storage (f_a is stored as
+    f_a - w_a shift_f): the light phase's phi, 0 when rho_A >= rho_B, else 1.  The
+    light phase's values are then stored near zero, where the 16-bit formats
+    resolve them finely, and rho(phi) = rho_B + phi (rho_A - rho_B) is most
+    sensitive to phi there: a rounding error d phi moves rho by (ratio - 1) d phi
+    relative to the light density, and only by about d phi relative to the heavy
+    one.  With stochastic rounding (the default) the heavy phase then carries
+    unbiased noise of about 1e-4 in phi and the light phase almost none; a shift
+    of 9/16 (values of about w_a / 2 in both phases) put that noise into the light
+    phase, and at density ratios near 1000 it drove lattices unstable."""
+    return 0.0 if float(case["rho_A"]) >= float(case["rho_B"]) else 1.0
 
 
 def config_from_case(case: dict, precision: str = "fp64", diag_every: int = 0,
-                     tile: tuple = (0, 0), shift_f: float = SHIFT_F, shift_g: float = 0.0,
+                     tile: tuple = (0, 0), shift_f: float | None = None, shift_g: float = 0.0,
                      u_max: float = 0.0) -> lb_config:
     """Translate a case dictionary (paper_1909_04166_amd.workloads) into lb_config.
-    tile: (tile_x, tile_h) or (tile_x, tile_h, tile_pf); zeros autotune."""
+    tile: (tile_x, tile_h) or (tile_x, tile_h, tile_pf); zeros autotune.
+    shift_f None: default_shift_f(case)."""
     c = lb_config()
     c.nx, c.ny = int(case["nx"]), int(case["ny"])
     c.bc_x = LB_BC[case.get("bc_x", "periodic")]
@@ -189,6 +199,8 @@ def config_from_case(case: dict, precision: str = "fp64", diag_every: int = 0,
     c.T0, c.dTdy, c.y_ref = float(case.get("T0", 0.0)), float(case.get("dTdy", 0.0)), float(case.get("y_ref", 0.0))
     c.W, c.M = float(case["W"]), float(case["M"])
     c.gx, c.gy = float(case.get("gx", 0.0)), float(case.get("gy", 0.0))
+    if shift_f is None:
+        shift_f = default_shift_f(case)
     c.shift_f, c.shift_g, c.u_max = float(shift_f), float(shift_g), float(u_max)
     c.tile_x, c.tile_h = int(tile[0]), int(tile[1])
     c.tile_pf = int(tile[2]) if len(tile) > 2 else 0
@@ -197,6 +209,7 @@ def config_from_case(case: dict, precision: str = "fp64", diag_every: int = 0,
     c.surf = LB_SIGMA[case.get("surf", "linear")]
     c.beta = float(case.get("beta", 0.0))
     c.psi_a, c.psi_G = float(case.get("psi_a", 0.0)), float(case.get("psi_G", 0.0))
+    c.rounding = LB_ROUND[case.get("rounding", "stochastic")]
     kind, par = case.get("init", ("none", ()))
     c.init_kind = LB_INIT[kind]
     for i, v in enumerate(par):
@@ -344,11 +357,13 @@ def lb_copy_kernel(dst: int, src: int, n: int, stream: int) -> None:
     _check("lb_copy_kernel", lib().lb_copy_kernel(_vp(dst), _vp(src), int(n), _vp(stream)))
 
 
-def lb_step_noalloc(cfg: lb_config, state0: int, state1: int, state_bytes: int, n: int, stream: int) -> None:
+def lb_step_noalloc(cfg: lb_config, state0: int, state1: int, state_bytes: int, step: int, n: int,
+                    stream: int) -> None:
     """n steps of a lattice held in two caller-owned device buffers (the checkpoint
-    payload layout); the state ends in state0 for even n, state1 for odd n."""
+    payload layout) whose state is at step count `step`; the state ends in state0
+    for even n, state1 for odd n."""
     _check("lb_step_noalloc", lib().lb_step_noalloc(ctypes.byref(cfg), _vp(state0), _vp(state1),
-                                                     int(state_bytes), int(n), _vp(stream)))
+                                                     int(state_bytes), int(step), int(n), _vp(stream)))
 
 
 def lb_batch_workspace_bytes(slots: int, node_capacity: int, precision: str) -> int:
@@ -435,7 +450,7 @@ class Lattice:
     """One lattice in a torch-allocated device workspace on the current stream."""
 
     def __init__(self, case: dict, phi0: np.ndarray | None = None, precision: str = "fp64",
-                 diag_every: int = 0, tile: tuple = (0, 0), shift_f: float = SHIFT_F,
+                 diag_every: int = 0, tile: tuple = (0, 0), shift_f: float | None = None,
                  shift_g: float = 0.0, u_max: float = 0.0, device: str = "cuda:0"):
         torch = _torch()
         self.case = dict(case)
@@ -537,7 +552,7 @@ class Batch:
         except Exception:
             pass
 
-    def add(self, case: dict, phi0: np.ndarray, diag_every: int = 0, shift_f: float = SHIFT_F,
+    def add(self, case: dict, phi0: np.ndarray, diag_every: int = 0, shift_f: float | None = None,
             shift_g: float = 0.0) -> int:
         cfg = config_from_case(case, self.precision, diag_every, (0, 0), shift_f, shift_g)
         shape = (int(case["ny"]), int(case["nx"]))
@@ -568,6 +583,11 @@ class Batch:
 
     def usage(self) -> tuple[int, int]:
         return lb_batch_usage(self.b)
+
+    def set_schedule(self, tile_x: int, mode: int, param: int, prefetch: int = 0) -> None:
+        """Pin the persistent step's schedule (see Lattice.set_schedule)."""
+        _check("lb_batch_set_schedule", lib().lb_batch_set_schedule(self.b, int(tile_x), int(mode), int(param),
+                                                                    int(prefetch)))
 
     def launch_counts(self) -> tuple[int, int]:
         """(steps replayed from captured graphs, steps launched one by one)."""

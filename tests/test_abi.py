@@ -121,6 +121,7 @@ def test_option_validation():
     assert code(psi_G=1.0 / 200.0) == lb.LB_E_INVALID_ARG  # psi reaches 1 on the last row
     assert code(psi_G=0.99 / 200.0) == lb.LB_OK
     assert code(beta=float("nan")) == lb.LB_E_INVALID_ARG
+    assert code(rounding=2) == lb.LB_E_INVALID_ARG and code(rounding=1) == lb.LB_OK
     c = lb.config_from_case(case, "fp64")
     c.flow = lb.LB_FLOW["imposed"]
     assert lb.lb_workspace_bytes(c) >= base + 2 * 8 * case["nx"] * case["ny"]
@@ -134,9 +135,9 @@ def test_noalloc_rejects_before_device_work():
     big = 1 << 40
     a, b = 1 << 20, 1 << 21  # never dereferenced: every call below fails first
 
-    def code(c, n=1, nbytes=big, p0=a, p1=b):
+    def code(c, n=1, nbytes=big, p0=a, p1=b, step=0):
         try:
-            lb.lb_step_noalloc(c, p0, p1, nbytes, n, 0)
+            lb.lb_step_noalloc(c, p0, p1, nbytes, step, n, 0)
             return lb.LB_OK
         except lb.LBError as e:
             return e.code
@@ -148,6 +149,7 @@ def test_noalloc_rejects_before_device_work():
     assert code(cfg, p0=a + 64) == lb.LB_E_WORKSPACE
     assert code(cfg, p1=a) == lb.LB_E_INVALID_ARG
     assert code(cfg, n=-1) == lb.LB_E_INVALID_ARG
+    assert code(cfg, step=-1) == lb.LB_E_INVALID_ARG
     c = lb.config_from_case(case, "fp64", diag_every=10)
     assert code(c) == lb.LB_E_UNSUPPORTED
     c = lb.config_from_case(dict(case, flow="imposed"), "fp64")

@@ -109,29 +109,29 @@ def test_hydrodynamic_closed_form_equals_cascade():
 
 def hydro_solved_closed(g, p, rho, ux, uy, Ftx, Fty, Fpx, Fpy, om):
     """The kernel's closed form of the collision (h_3..h_8 solve the relaxation
-    conditions as stated): the printed form's raw moments plus the differences
-    written out in the kernel."""
+    conditions as stated): the printed form's raw moments with the shear
+    non-equilibria taken about u (N', X') and without the pure force terms
+    (2/3) G, c^4 F_ty, c^4 F_tx and 2 c^4 G."""
     c2 = 1 / 3
+    pbar = p - 0.5 * (Fpx * ux + Fpy * uy)
+    jx, jy = (g * EX).sum(), (g * EY).sum()
+    e20, e02, e11 = (g * EX ** 2).sum(), (g * EY ** 2).sum(), (g * EX * EY).sum()
     G = Fpx * ux + Fpy * uy
-    m = _to_raw(hydro_closed(g, p, rho, ux, uy, Ftx, Fty, Fpx, Fpy, om))
-    o1 = 1 - om
-    fu, fv = Ftx * ux - Fty * uy, Ftx * uy + Fty * ux
-    ux2, uy2 = ux * ux, uy * uy
-    dT = -2 / 3 * G
-    dD = -o1 / 6 * (3 * (ux2 - uy2) * G - 2 * fu)
-    m[3] += (dT + dD) / 2
-    m[4] += (dT - dD) / 2
-    m[5] -= o1 / 6 * (3 * ux * uy * G - fv)
-    m[6] -= Fty / 9 + o1 / 36 * (9 * uy * (5 * ux2 - uy2) * G - 18 * Ftx * ux * uy - 12 * Fty * ux2 + 6 * Fty * uy2)
-    m[7] += o1 / 36 * (9 * ux * (ux2 - 5 * uy2) * G - 6 * Ftx * ux2 + 12 * Ftx * uy2 + 18 * Fty * ux * uy) - Ftx / 9
-    m[8] += o1 / 36 * (9 * (ux2 * ux2 - 10 * ux2 * uy2 + uy2 * uy2) * G - 6 * (Ftx * ux ** 3 + Fty * uy ** 3)
-                       + 30 * ux * uy * fv) - 2 * G / 9
+    Sx, Sy = Ftx + Fpx, Fty + Fpy
+    s20, s02, s11 = 2 * c2 * Sx * ux + c2 * G, 2 * c2 * Sy * uy + c2 * G, c2 * (Sx * uy + Sy * ux)
+    N = (e20 - e02) - c2 * rho * (ux ** 2 - uy ** 2) + c2 * (Ftx * ux - Fty * uy) - (ux ** 2 - uy ** 2) * G / 2
+    X = e11 - c2 * rho * ux * uy + c2 * (Ftx * uy + Fty * ux) / 2 - ux * uy * G / 2
+    nn, xx = (1 - om) * N, (1 - om) * X
+    hw = 1 - om / 2
+    T = 2 * c2 * p + c2 * rho * (ux ** 2 + uy ** 2) + 2 / 3 * G + c2 * (Ftx * ux + Fty * uy)
+    Dd = c2 * rho * (ux ** 2 - uy ** 2) + nn + hw * (s20 - s02)
+    m = [pbar + G, jx + c2 * Ftx, jy + c2 * Fty, (T + Dd) / 2, (T - Dd) / 2,
+         c2 * rho * ux * uy + xx + hw * s11,
+         c2 * rho * uy * (c2 + ux ** 2) + uy * nn / 2 + 2 * ux * xx,
+         c2 * rho * ux * (c2 + uy ** 2) - ux * nn / 2 + 2 * uy * xx,
+         p / 9 + rho * (ux ** 2 + uy ** 2) / 9 + rho * ux ** 2 * uy ** 2 / 3
+         - (ux ** 2 - uy ** 2) * nn / 2 + 4 * ux * uy * xx]
     return _from_raw(m)
-
-
-def _to_raw(f):
-    return np.array([(f * EX ** m * EY ** n).sum() for m, n in
-                     [(0, 0), (1, 0), (0, 1), (2, 0), (0, 2), (1, 1), (2, 1), (1, 2), (2, 2)]])
 
 
 def test_hydrodynamic_solved_closed_form_equals_numerical_solve():

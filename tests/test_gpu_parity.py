@@ -248,12 +248,13 @@ def test_flat_interface_fp32():
     assert abs(co - 63.5) <= 1e-9 and abs(cg - co) <= 1e-4 * case["W"]
 
 
-@pytest.mark.parametrize("prec,ratio,tol", [("fp16", 1000.0, 5e-3), ("bf16", 10.0, 5e-2)])
+@pytest.mark.parametrize("prec,ratio,tol", [("fp16", 1000.0, 5e-3), ("bf16", 10.0, 5e-2), ("bf16", 1000.0, 5e-2)])
 def test_16bit_storage_error_stated(prec, ratio, tol):
-    """FP32 compute with 16-bit storage of the distributions (f shifted by
-    w_a 9/16, gbar unshifted).  The error against the FP64 oracle is measured and bounded.
-    bf16 keeps 8 mantissa bits: f is resolved to ~1e-3 in phi, which moves rho by
-    O(1) at density ratio 1000, so bf16 is exercised at ratio 10."""
+    """FP32 compute with 16-bit storage of the distributions (f shifted by the
+    light phase's phi, here 0; gbar unshifted; stores rounded stochastically).  The
+    error against the FP64 oracle is measured and bounded.  bf16 keeps 8 mantissa
+    bits, so phi is resolved to about 2e-3 near 1; the light phase, stored near
+    zero, is resolved finely, which keeps rho(phi) there accurate at ratio 1000."""
     case, phi0 = W.droplet(128, 25.0, W=5.0, ratio=ratio)
     _print_case(f"droplet128-W5 {prec}", case, ratio=ratio)
     g = lb.Lattice(case, phi0, prec)
@@ -333,15 +334,19 @@ def test_workgroup_widths_bit_identical(prec):
         assert err <= 1e-4
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 2e-5), ("fp16", 5e-3)])
-def test_bench_grid_tiles_equal_and_match_oracle(precision, tol):
+@pytest.mark.parametrize("precision,rounding,tol", [("fp64", "nearest", 1e-10), ("fp32", "nearest", 2e-5),
+                                                    ("fp16", "nearest", 5e-3), ("fp16", "stochastic", 5e-3)])
+def test_bench_grid_tiles_equal_and_match_oracle(precision, rounding, tol):
     """The benchmark's own workload and launch configuration (the 8192^2 grid of
-    64 x 64 periodic tiles of the 128^2 droplet, autotuned schedule): nothing in
-    the step depends on absolute position here, so every tile stays bit-identical
-    to every other, and the first tile matches the oracle's 128^2 run (FP64 within
-    1e-10; FP32 phi within 2e-5; fp16 storage within its 5e-3 bound)."""
+    64 x 64 periodic tiles of the 128^2 droplet, autotuned schedule).  Rounding to
+    nearest, nothing in the step depends on absolute position, so every tile stays
+    bit-identical to every other, and the first tile matches the oracle's 128^2 run
+    (FP64 within 1e-10; FP32 phi within 2e-5; fp16 storage within its 5e-3 bound).
+    With stochastic rounding of the 16-bit stores (the default) the random bits
+    depend on the node, so the tiles differ; every one of them must then match the
+    oracle within the same bound."""
     case, phi0 = W.droplet(128, 25.0, W=5.0)
-    big, bphi = W.tiled(case, phi0, 64, 64)
+    big, bphi = W.tiled(dict(case, rounding=rounding), phi0, 64, 64)
     _print_case("bench grid", big, precision=precision)
     g = lb.Lattice(big, bphi, precision)
     del bphi
@@ -352,12 +357,15 @@ def test_bench_grid_tiles_equal_and_match_oracle(precision, tol):
     o = oracle.Oracle(case, phi0)
     o.step(20)
     ref = o.fields()
-    for a, b in zip((phi, p, ux, uy), ref):
-        t = a.reshape(64, 128, 64, 128)
-        first = t[0, :, 0, :]
-        assert np.array_equal(t, np.broadcast_to(first[None, :, None, :], t.shape)), "tiles differ"
-    err = np.abs(phi[:128, :128] - ref[0]).max()
-    print(f"   tile vs oracle: phi {err:.3e}", flush=True)
+    if rounding == "nearest":
+        for a, b in zip((phi, p, ux, uy), ref):
+            t = a.reshape(64, 128, 64, 128)
+            first = t[0, :, 0, :]
+            assert np.array_equal(t, np.broadcast_to(first[None, :, None, :], t.shape)), "tiles differ"
+        err = np.abs(phi[:128, :128] - ref[0]).max()
+    else:
+        err = np.abs(phi.reshape(64, 128, 64, 128) - ref[0][None, :, None, :]).max()
+    print(f"   tiles vs oracle: phi {err:.3e}", flush=True)
     assert err <= tol
 
 
@@ -409,11 +417,12 @@ def test_degenerate_calls():
 
 def test_thermocapillary_config_fp16():
     """The thermocapillary workload at full size (512 x 256, walls, sigma(y)) in its
-    own precision, FP32 compute with shifted fp16 storage: phi within the 16-bit
-    bound 5e-3 of the FP64 oracle after 300 steps, the mean phi offset below 1e-5
-    (the default shift stores the ambient phase exactly; with w_a / 2 the offset
-    was 1.2e-4 and moved the domain-wide centroid by 0.3 nodes), and the centroid
-    of the drop (nodes with phi > 1/2) and of all phi within 1e-2 lattice units."""
+    own precision, FP32 compute with fp16 storage: phi within the 16-bit bound
+    5e-3 of the FP64 oracle after 300 steps, the mean phi offset below 1e-5 (the
+    default shift stores the ambient phase phi = 0 as exact zeros; a shift of w_a / 2
+    left an offset of 1.2e-4 that moved the domain-wide centroid by 0.3 nodes), and
+    the centroid of the drop (nodes with phi > 1/2) and of all phi within 1e-2
+    lattice units."""
     case, phi0 = W.config("thermo512")
     _print_case("thermo512 fp16", case)
     g = lb.Lattice(case, phi0, "fp16")

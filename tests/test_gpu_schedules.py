@@ -38,9 +38,10 @@ def _run(case, phi0, prec, sched, steps):
 @pytest.mark.parametrize("prec", ["fp64", "fp16"])
 @pytest.mark.parametrize("bc_y", ["periodic", "wall"])
 def test_pinned_schedules_bit_identical(prec, bc_y):
-    # tall enough that every persistent cut gets bands of at least 8 rows
-    case, phi0 = W.random_case(1030, 2600, seed=31, bc_y=bc_y, gy=-1e-5 if bc_y == "wall" else 0.0)
-    print(f"[case] schedules {prec} {bc_y} 1030x2600", flush=True)
+    # tall enough that every persistent cut gets bands of at least 8 rows (up to
+    # 4 resident 260-lane workgroups per CU: 2 x 4 x 256 / 5 strips -> 408 bands)
+    case, phi0 = W.random_case(1030, 3400, seed=31, bc_y=bc_y, gy=-1e-5 if bc_y == "wall" else 0.0)
+    print(f"[case] schedules {prec} {bc_y} 1030x3400", flush=True)
     ref, _ = _run(case, phi0, prec, SCHEDULES[0], 12)
     for sched in SCHEDULES[1:]:
         if prec == "fp64" and sched[0] == 516 and sched[3]:
