@@ -460,6 +460,11 @@ def cpu_baseline(target_s: float = 15.0, ref_steps: int = 0, gpu_tile=None):
     return out, err
 
 
+def progress(msg: str) -> None:
+    """One line per finished stage on stderr (the JSON line goes to stdout)."""
+    print(f"[bench] {time.strftime('%H:%M:%S')} {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -544,6 +549,7 @@ def main():
                      sched=sched)
     del phi0
     mlups = N * args.steps / r["wall_s"] / 1e6
+    progress(f"headline step timed: {mlups:.1f} MLUPS")
     s = STORE[args.precision]
     bytes_per_launch = 36 * s * N
     achieved = bytes_per_launch / (r["ms_kernel"] * 1e-3) / 1e9 if r["ms_kernel"] > 0 else None
@@ -576,14 +582,17 @@ def main():
     }
     if not args.no_configs:
         out["paper_configs"] = bench_configs()
+        progress("paper configurations timed")
     if not args.no_batched:
         out["batched"] = {"fp16": bench_batched("fp16", max(args.steps, 320))}
+        progress("batch timed")
         out["batched"]["fp16"]["vs_plain_fp64"] = round(out["batched"]["fp16"]["MLUPS"] / out["value"], 3)
         out["batched"]["workload"] = ("256 uneven lattices (droplet or Rayleigh-Taylor by seed 20190909, sides "
                                       "64-512, ratio log-uniform 3-1000, W 5, M 0.02), one persistent launch "
                                       "per step")
     if not args.no_served:
         out["served"] = bench_served_compact()
+        progress("served stream run")
     if args.extra:
         extra = {}
         for prec in ("fp32", "fp16", "bf16"):
@@ -593,6 +602,7 @@ def main():
             extra[prec] = {"MLUPS": round(N * args.steps / rr["wall_s"] / 1e6, 1),
                            "kernel_GBs": round(36 * STORE[prec] * N / (rr["ms_kernel"] * 1e-3) / 1e9, 1),
                            "tile": list(rr["tile"])}
+            progress(f"extra {prec} timed")
         if args.workload == "tiled8192":  # the smaller roofline grid of the same tiling
             c4, p4, _ = make_workload("tiled4096")
             n4 = c4["nx"] * c4["ny"]
@@ -602,18 +612,24 @@ def main():
                     "MLUPS": round(n4 * args.steps / rr["wall_s"] / 1e6, 1),
                     "kernel_GBs": round(36 * STORE[prec] * n4 / (rr["ms_kernel"] * 1e-3) / 1e9, 1),
                     "tile": list(rr["tile"])}
+                progress(f"extra 4096^2 {prec} timed")
         out["extra"] = extra
     if args.batched:
-        full = {p: bench_batched(p, 5000) for p in ("fp16", "bf16", "fp32")}
+        full = {}
+        for p in ("fp16", "bf16", "fp32"):
+            full[p] = bench_batched(p, 5000)
+            progress(f"5000-step batch {p} timed")
         for p, rb in full.items():
             rb["vs_plain_fp64"] = round(rb["MLUPS"] / out["value"], 3)
         out.setdefault("batched", {})["5000_steps"] = full
     if args.served:
         sat = bench_served("fp16", 500, 50.0)
+        progress("saturated served stream run")
         cap_glups = max(sat["MLUPS"] / 1e3, 1e-3)
         # a second stream at 70 % of the measured capacity, so latency is not pure queue growth
         mean_work = 1.93e9
         low = bench_served("fp16", 200, 0.7 * cap_glups * 1e9 / mean_work)
+        progress("served stream at 0.7 load run")
         # plain form of the same stream: 60 requests of the 0.7-load trace, FP64,
         # one lattice at a time, beside the same 60 through the batching server
         rate7 = 0.7 * cap_glups * 1e9 / mean_work
@@ -624,9 +640,12 @@ def main():
     if args.variants:
         side = case["nx"] if args.workload.startswith("tiled") else 8192
         out["variants"] = bench_variants(side, args.steps, args.warmup)
+        progress("variants timed")
     if args.stability:
         out["stability"] = bench_stability()
+        progress("stability sweep run")
     if not args.no_cpu_baseline:
+        progress("CPU oracle baseline starts")
         out["cpu_baseline"], err = cpu_baseline(ref_steps=args.warmup + args.steps if tiled else 0,
                                                 gpu_tile=r["first_tile"])
         if err is not None:
