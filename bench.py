@@ -513,8 +513,10 @@ def main():
         stream = torch.cuda.current_stream().cuda_stream
         variants = [int(v) for v in args.copy_variants.split(",")]
         # bytes each variant moves: copies read and write n, the read probe reads
-        # n (and writes 16 MiB), the write probe writes n
-        moved = {5: n + (16 << 20), 6: n}
+        # n (and writes 16 MiB), the write probe writes n, the row-pattern probes
+        # read and write whole rows of 18 x 8064 two-byte values
+        rows_bytes = n // (18 * 8064 * 2) * (18 * 8064 * 2)
+        moved = {5: n + (16 << 20), 6: n, 7: 2 * rows_bytes, 8: 2 * rows_bytes}
         out = {"bytes": n, "variants": {}}
         for v in variants:
             run = (lambda: lb.lb_copy_kernel(b.data_ptr(), a.data_ptr(), n, stream)) if v == 0 else \

@@ -406,7 +406,12 @@ lb_status lb_copy_kernel(void* dst, const void* src, uint64_t n, void* stream);
  *   2 as 1 with nontemporal loads and stores;  3 as 1 with 4 in flight and
  *     nontemporal stores;  4 copy, one contiguous chunk per workgroup;
  *   5 read only: reads src, writes one 16-byte word per lane of the grid to dst
- *     (16 MiB);  6 write only: fills dst.
+ *     (16 MiB);  6 write only: fills dst;
+ *   7 the step kernel's memory pattern in 16-bit storage without its arithmetic:
+ *     whole rows of 18 planes of 8064 two-byte values (the first
+ *     floor(n / 290304) rows), 18 strips of 448 columns x 28 row segments, each
+ *     lane loading its 18 values of a row and storing them, one column per lane
+ *     with 2-byte accesses;  8 as 7 with two columns per lane and 4-byte accesses.
  * Errors: LB_E_INVALID_ARG. */
 lb_status lb_bandwidth_probe(void* dst, const void* src, uint64_t n, int32_t variant, void* stream);
 

@@ -497,6 +497,41 @@ __global__ void __launch_bounds__(256) k_write_only(u32x4* __restrict__ dst, int
     }
 }
 
+// The step kernel's memory pattern without its arithmetic: rows of 18 planes of
+// 16-bit values, kRowCols columns each (18 strips of 448), a grid of 18 strips x
+// 28 row segments (two workgroups per CU).  Per row a lane loads its 18 values,
+// then stores them: one column per lane with 2-byte accesses (W2 false, 448
+// lanes), or two columns per lane with 4-byte accesses (W2 true, 224 lanes).
+constexpr int kRowCols = 8064, kRowStrips = 18, kRowSegs = 28;
+template <bool W2>
+__global__ void __launch_bounds__(448) k_rows16(uint16_t* __restrict__ dst, const uint16_t* __restrict__ src,
+                                                int rows) {
+    const int strip = blockIdx.x % kRowStrips, seg = blockIdx.x / kRowStrips;
+    const int per = (rows + kRowSegs - 1) / kRowSegs;
+    const int r0 = seg * per, r1 = min(rows, r0 + per);
+    const uint32_t col = (uint32_t)(strip * 448 + (W2 ? 2 : 1) * (int)threadIdx.x);
+    const uint32_t P = kRowCols * 2;  // bytes per plane
+    for (int r = r0; r < r1; ++r) {
+        const auto rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t*>(src) + (size_t)r * 18 * kRowCols,
+                                                          (short)0, -1, 0x00020000);
+        const auto rd = __builtin_amdgcn_make_buffer_rsrc(dst + (size_t)r * 18 * kRowCols, (short)0, -1, 0x00020000);
+        if constexpr (W2) {
+            uint32_t v[18];
+#pragma unroll
+            for (int q = 0; q < 18; ++q) v[q] = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)(col * 2), (int)(q * P), 0);
+#pragma unroll
+            for (int q = 0; q < 18; ++q) __builtin_amdgcn_raw_buffer_store_b32(v[q] ^ 1u, rd, (int)(col * 2), (int)(q * P), 0);
+        } else {
+            uint16_t v[18];
+#pragma unroll
+            for (int q = 0; q < 18; ++q) v[q] = __builtin_amdgcn_raw_buffer_load_b16(rs, (int)(col * 2), (int)(q * P), 0);
+#pragma unroll
+            for (int q = 0; q < 18; ++q)
+                __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(v[q] ^ 1u), rd, (int)(col * 2), (int)(q * P), 0);
+        }
+    }
+}
+
 hipError_t launch_bandwidth_probe(void* dst, const void* src, uint64_t n, int variant, hipStream_t s) {
     const int64_t n16 = (int64_t)(n / 16);
     if (n16 < 256 * 8) return hipErrorInvalidValue;
@@ -522,6 +557,18 @@ hipError_t launch_bandwidth_probe(void* dst, const void* src, uint64_t n, int va
         hipLaunchKernelGGL((k_read_only<8>), dim3(grid), dim3(256), 0, s, d, c, n16);
         break;
     case 6: hipLaunchKernelGGL((k_write_only<8>), dim3(grid), dim3(256), 0, s, d, n16); break;
+    case 7:
+    case 8: {
+        const int rows = (int)(n / (18ull * kRowCols * 2));
+        if (rows < kRowSegs) return hipErrorInvalidValue;
+        if (variant == 7)
+            hipLaunchKernelGGL((k_rows16<false>), dim3(kRowStrips * kRowSegs), dim3(448), 0, s, (uint16_t*)dst,
+                               (const uint16_t*)src, rows);
+        else
+            hipLaunchKernelGGL((k_rows16<true>), dim3(kRowStrips * kRowSegs), dim3(224), 0, s, (uint16_t*)dst,
+                               (const uint16_t*)src, rows);
+        break;
+    }
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -826,7 +826,7 @@ lb_status lb_copy_kernel(void* dst, const void* src, uint64_t n, void* stream) {
 }
 
 lb_status lb_bandwidth_probe(void* dst, const void* src, uint64_t n, int32_t variant, void* stream) {
-    if (!dst || !src || ((uintptr_t)dst % 16) || ((uintptr_t)src % 16) || variant < 0 || variant > 6)
+    if (!dst || !src || ((uintptr_t)dst % 16) || ((uintptr_t)src % 16) || variant < 0 || variant > 8)
         return LB_E_INVALID_ARG;
     if (n < ((uint64_t)16 << 20)) return LB_E_INVALID_ARG;  // at least 16 MiB (the read probe's output fits)
     HIPC(launch_bandwidth_probe(dst, src, n, variant, (hipStream_t)stream));

@@ -94,3 +94,18 @@ def test_bandwidth_probe_variants_move_the_data():
     lb.lb_bandwidth_probe(b.data_ptr(), ones.data_ptr(), n, 5, stream)
     torch.cuda.synchronize()
     assert not b[: 4096 * 256 * 16].any()
+    # row-pattern probes: whole rows of 18 x 8064 two-byte values, each value's
+    # lowest bit flipped (16-bit words for 7, 32-bit words for 8), the rest untouched
+    used = n // (18 * 8064 * 2) * (18 * 8064 * 2)
+    for v, flip in ((7, 1), (8, 1)):
+        b = torch.zeros_like(a)
+        lb.lb_bandwidth_probe(b.data_ptr(), a.data_ptr(), n, v, stream)
+        torch.cuda.synchronize()
+        if v == 7:
+            want = a[:used].view(torch.int16) ^ flip
+            got = b[:used].view(torch.int16)
+        else:
+            want = a[:used].view(torch.int32) ^ flip
+            got = b[:used].view(torch.int32)
+        assert torch.equal(got, want), v
+        assert not b[used:].any(), v
