@@ -169,6 +169,7 @@ void fill_desc(const lb_config* c, LatDesc& D, void* b0, void* b1, int64_t plane
     D.shift_f = half ? c->shift_f : 0.0;
     D.shift_g = half ? c->shift_g : 0.0;
     D.sround = half && c->rounding == LB_ROUND_STOCHASTIC ? 1 : 0;
+    D.ntstore = ((int64_t)c->nx * store_bytes(c->precision)) % 128 == 0 ? 1 : 0;
     D.kt0 = 1.5 * c->W * c->sigma0;
     D.lbeta = c->beta;
     D.ps_a = c->psi_a;
@@ -233,6 +234,7 @@ struct lb_handle {
     lb_config cfg;
     int kind = KIND_COUPLED_CASCADED;
     bool walls = true;  // the lattice has a wall on some side (else the wall-free kernels run)
+    bool nt = false;    // its rows are whole cache lines (nontemporal stores where the strips are too)
     hipStream_t s = nullptr;
     char* ws = nullptr;
     uint64_t ws_bytes = 0;
@@ -312,7 +314,7 @@ lb_status set_sched(lb_handle* h, Sched sc) {
 
 lb_status launch_steps_eager(lb_handle* h, int64_t n) {
     for (int64_t i = 0; i < n; ++i) {
-        HIPC(launch_step(h->cfg.precision, h->kind, h->walls, h->sc.tx, h->sc.pf, h->d_desc, h->d_items, h->n_items,
+        HIPC(launch_step(h->cfg.precision, h->kind, h->walls, h->nt, h->sc.tx, h->sc.pf, h->d_desc, h->d_items, h->n_items,
                          h->sc.grid, h->parity, h->s));
         h->parity ^= 1;
         h->step += 1;
@@ -329,7 +331,7 @@ lb_status graph_for(lb_handle* h, int parity, hipGraphExec_t* out) {
         hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         int p = parity;
         for (int i = 0; i < h->glen && e == hipSuccess; ++i) {
-            e = launch_step(h->cfg.precision, h->kind, h->walls, h->sc.tx, h->sc.pf, h->d_desc, h->d_items, h->n_items,
+            e = launch_step(h->cfg.precision, h->kind, h->walls, h->nt, h->sc.tx, h->sc.pf, h->d_desc, h->d_items, h->n_items,
                             h->sc.grid, p, cs);
             p ^= 1;
         }
@@ -360,16 +362,16 @@ lb_status enqueue_diag(lb_handle* h) {
 
 // Times `reps` launches of one candidate without advancing the state (every
 // launch reads the current buffer and overwrites the other one).
-double time_candidate(int prec, int kind, bool walls, int tx, int pf, const LatDesc* d, const WorkItem* items, int n,
+double time_candidate(int prec, int kind, bool walls, bool nt, int tx, int pf, const LatDesc* d, const WorkItem* items, int n,
                       int grid, int parity, hipStream_t s, int reps) {
     hipEvent_t a, b;
     if (hipEventCreate(&a) != hipSuccess) return 1e30;
     if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return 1e30; }
     double ms_out = 1e30;
-    bool ok = launch_step(prec, kind, walls, tx, pf, d, items, n, grid, parity, s) == hipSuccess;
+    bool ok = launch_step(prec, kind, walls, nt, tx, pf, d, items, n, grid, parity, s) == hipSuccess;
     ok = ok && hipEventRecord(a, s) == hipSuccess;
     for (int i = 0; i < reps && ok; ++i)
-        ok = launch_step(prec, kind, walls, tx, pf, d, items, n, grid, parity, s) == hipSuccess;
+        ok = launch_step(prec, kind, walls, nt, tx, pf, d, items, n, grid, parity, s) == hipSuccess;
     ok = ok && hipEventRecord(b, s) == hipSuccess && hipEventSynchronize(b) == hipSuccess;
     float ms = 0;
     if (ok && hipEventElapsedTime(&ms, a, b) == hipSuccess) ms_out = ms / reps;
@@ -387,7 +389,7 @@ std::vector<Sched> candidates(int prec, int nx, int ny, int kind) {
             if (pf != PF_HOLD && kind != KIND_COUPLED_CASCADED) continue;
             if (!valid_width(tx, prec, pf)) continue;
             if (tx > 64 && nx <= strip_w(tx / 2)) continue;
-            for (int th : {16, 32, 64, 128, 256}) {
+            for (int th : {8, 16, 32, 64, 128, 256}) {
                 if (th > ny && th != 16) continue;
                 Sched sc;
                 sc.tx = tx; sc.th = th; sc.mode = 0; sc.pf = pf;
@@ -436,7 +438,7 @@ lb_status autotune_single(lb_handle* h) {
             return LB_OK;
         HIPC(hipMemcpyAsync(h->d_items, items.data(), items.size() * sizeof(WorkItem),
                             hipMemcpyHostToDevice, h->s));
-        *ms = time_candidate(h->cfg.precision, h->kind, h->walls, sc.tx, sc.pf, h->d_desc, h->d_items, sc.n_items,
+        *ms = time_candidate(h->cfg.precision, h->kind, h->walls, h->nt, sc.tx, sc.pf, h->d_desc, h->d_items, sc.n_items,
                              sc.grid, h->parity, h->s, r);
         return LB_OK;
     };
@@ -521,6 +523,7 @@ lb_status lb_create(const lb_config* cfg, void* dev_ws, uint64_t ws_bytes, void*
     h->kind = kind_of(cfg);
     fill_desc(cfg, h->hdesc, h->buf[0], h->buf[1], h->plane, h->d_fields);
     h->walls = h->hdesc.wall_y != WALL_NONE || h->hdesc.wall_x != WALL_NONE;
+    h->nt = h->hdesc.ntstore != 0;
     h->hdesc.vel = cfg->flow == LB_FLOW_IMPOSED ? (void*)(h->ws + L.vel) : nullptr;
     h->hdesc.ktab = (double*)(h->ws + L.ktab);
     h->hdesc.tstep = (uint32_t*)(h->ws + L.tstep);
@@ -873,6 +876,7 @@ struct lb_batch {
     bool fixed_tile = false;
     bool dirty = true;
     bool walls = true;  // some occupied slot has walls (set when the work list is rebuilt)
+    bool nt = false;    // every occupied slot's rows are whole cache lines (set with walls)
     int64_t stable = 0;  // steps taken since the work list last changed
     int64_t tuned_nodes = 0;  // nodes in use when the schedule was last autotuned
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
@@ -998,7 +1002,7 @@ lb_status batch_autotune(lb_batch* b) {
         if (!build_schedule(lats, b->prec, b->kind, b->walls, sc, b->max_items, items)) return LB_OK;
         HIPC(hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(WorkItem),
                             hipMemcpyHostToDevice, b->s));
-        *ms = time_candidate(b->prec, b->kind, b->walls, sc.tx, sc.pf, b->d_descs, b->d_items, sc.n_items, sc.grid,
+        *ms = time_candidate(b->prec, b->kind, b->walls, b->nt, sc.tx, sc.pf, b->d_descs, b->d_items, sc.n_items, sc.grid,
                              b->parity, b->s, reps);
         return LB_OK;
     };
@@ -1030,7 +1034,7 @@ lb_status batch_graph(lb_batch* b, int parity, hipGraphExec_t* out) {
         hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         int p = parity;
         for (int i = 0; i < b->glen && e == hipSuccess; ++i) {
-            e = launch_step(b->prec, b->kind, b->walls, b->sc.tx, b->sc.pf, b->d_descs, b->d_items, b->n_items, b->sc.grid,
+            e = launch_step(b->prec, b->kind, b->walls, b->nt, b->sc.tx, b->sc.pf, b->d_descs, b->d_items, b->n_items, b->sc.grid,
                             p, cs);
             p ^= 1;
         }
@@ -1197,9 +1201,12 @@ lb_status lb_batch_step(lb_batch* b, int64_t n, int32_t use_graph) {
         lb_batch_usage(b, &used, &nodes);
         // the kernels without wall logic serve batches of periodic lattices only
         b->walls = false;
-        for (int i = 0; i < b->nslots; ++i)
-            if (b->slot[i].used && (b->slot[i].cfg.bc_x != LB_PERIODIC || b->slot[i].cfg.bc_y != LB_PERIODIC))
-                b->walls = true;
+        b->nt = used > 0;
+        for (int i = 0; i < b->nslots; ++i) {
+            if (!b->slot[i].used) continue;
+            if (b->slot[i].cfg.bc_x != LB_PERIODIC || b->slot[i].cfg.bc_y != LB_PERIODIC) b->walls = true;
+            if (!b->hdescs[i].ntstore) b->nt = false;
+        }
         // autotune when the load changed by more than 2x since the last tuning,
         // otherwise rebuild the work list with the current schedule
         const bool retune = !b->fixed_tile && nodes > 0 &&
@@ -1215,7 +1222,7 @@ lb_status lb_batch_step(lb_batch* b, int64_t n, int32_t use_graph) {
     if (b->n_items > 0) {
         auto eager = [&](int64_t k) -> lb_status {
             for (int64_t i = 0; i < k; ++i) {
-                HIPC(launch_step(b->prec, b->kind, b->walls, b->sc.tx, b->sc.pf, b->d_descs, b->d_items, b->n_items,
+                HIPC(launch_step(b->prec, b->kind, b->walls, b->nt, b->sc.tx, b->sc.pf, b->d_descs, b->d_items, b->n_items,
                                  b->sc.grid, b->parity, b->s));
                 b->parity ^= 1;
             }
@@ -1481,7 +1488,8 @@ lb_status lb_step_noalloc(const lb_config* cfg, void* state0, void* state1, uint
     const int kind = kind_of(cfg);
     int parity = 0;
     for (int64_t i = 0; i < n; ++i) {
-        HIPC(launch_step(cfg->precision, kind, walls, sc.tx, sc.pf, d_desc, d_items, (int)n_items, (int)n_items,
+        HIPC(launch_step(cfg->precision, kind, walls, D.ntstore != 0, sc.tx, sc.pf, d_desc, d_items, (int)n_items,
+                         (int)n_items,
                          parity, s));
         parity ^= 1;
     }

@@ -9,10 +9,12 @@
 namespace cmlb {
 
 // kind: KIND_*; walls false: no lattice of the launch has walls (the kernels
-// without wall logic run); pf != 0 selects the variant that prefetches the next
-// rows (coupled cascaded kind only).
-hipError_t launch_step(int prec, int kind, bool walls, int tx, int pf, const LatDesc* d, const WorkItem* items,
-                       int n_items, int grid, int parity, hipStream_t s);
+// without wall logic run); nt: every lattice of the launch has rows of whole cache
+// lines (LatDesc::ntstore), so widths whose strips are whole lines store
+// nontemporally; pf != 0 selects the variant that prefetches the next rows
+// (coupled cascaded kind only).
+hipError_t launch_step(int prec, int kind, bool walls, bool nt, int tx, int pf, const LatDesc* d,
+                       const WorkItem* items, int n_items, int grid, int parity, hipStream_t s);
 hipError_t launch_extract(int prec, int kind, int mode, const LatDesc* d, const WorkItem* items64,
                           int n_items, int parity, hipStream_t s);
 // stage: FP64 ux plane then uy plane, N values each.

@@ -10,26 +10,43 @@ namespace cmlb {
 // The kernel behind a step: the coupled pair (lb_fused) or the phase field alone
 // (lb_ace), with the cascaded or the SRT collisions.  The variant that prefetches
 // rows (PF_PREFETCH) exists for the coupled cascaded kernel only.  W false: the
-// launch's lattices have no walls (the kernels' wall logic is compiled out).
-template <class ST, int TX, int MODE, int PF, int KIND, bool W>
+// launch's lattices have no walls (the kernels' wall logic is compiled out).  NT:
+// nontemporal stores (coupled kernels whose strips are whole cache lines).
+template <class ST, int TX, int MODE, int PF, int KIND, bool W, bool NT = false>
 static void launch_one(dim3 grid, const LatDesc* d, const WorkItem* items, int n_items, int parity,
                        hipStream_t s) {
     if constexpr (KIND == KIND_COUPLED_CASCADED)
-        hipLaunchKernelGGL((lb_fused<ST, TX, MODE, PF, COLL_CASCADED, W>), grid, dim3(TX), 0, s, d, items, n_items, parity);
-    else if constexpr (KIND == KIND_COUPLED_SRT)
-        hipLaunchKernelGGL((lb_fused<ST, TX, MODE, PF_HOLD, COLL_SRT, W>), grid, dim3(TX), 0, s, d, items, n_items, parity);
-    else if constexpr (KIND == KIND_COUPLED_PRINTED)
-        hipLaunchKernelGGL((lb_fused<ST, TX, MODE, PF_HOLD, COLL_PRINTED, W>), grid, dim3(TX), 0, s, d, items, n_items,
+        hipLaunchKernelGGL((lb_fused<ST, TX, MODE, PF, COLL_CASCADED, W, NT>), grid, dim3(TX), 0, s, d, items, n_items,
                            parity);
+    else if constexpr (KIND == KIND_COUPLED_SRT)
+        hipLaunchKernelGGL((lb_fused<ST, TX, MODE, PF_HOLD, COLL_SRT, W, NT>), grid, dim3(TX), 0, s, d, items, n_items,
+                           parity);
+    else if constexpr (KIND == KIND_COUPLED_PRINTED)
+        hipLaunchKernelGGL((lb_fused<ST, TX, MODE, PF_HOLD, COLL_PRINTED, W, NT>), grid, dim3(TX), 0, s, d, items,
+                           n_items, parity);
     else if constexpr (KIND == KIND_ACE_CASCADED)
         hipLaunchKernelGGL((lb_ace<ST, TX, MODE, COLL_CASCADED, W>), grid, dim3(TX), 0, s, d, items, n_items, parity);
     else
         hipLaunchKernelGGL((lb_ace<ST, TX, MODE, COLL_SRT, W>), grid, dim3(TX), 0, s, d, items, n_items, parity);
 }
 
+// A width whose strips are whole cache lines, with or without nontemporal stores.
+template <class ST, int TX, int MODE, int PF, int KIND, bool W>
+static void launch_lines(bool nt, dim3 grid, const LatDesc* d, const WorkItem* items, int n_items, int parity,
+                         hipStream_t s) {
+    static_assert(kStripLines<ST, TX>, "strips of whole cache lines");
+    if constexpr (MODE == MODE_STEP && KIND != KIND_ACE_CASCADED && KIND != KIND_ACE_SRT) {
+        if (nt) {
+            launch_one<ST, TX, MODE, PF, KIND, W, true>(grid, d, items, n_items, parity, s);
+            return;
+        }
+    }
+    launch_one<ST, TX, MODE, PF, KIND, W, false>(grid, d, items, n_items, parity, s);
+}
+
 template <class ST, int MODE, int PF, int KIND, bool W = true>
 static hipError_t launch_tx(int tx, const LatDesc* d, const WorkItem* items, int n_items, int grid,
-                            int parity, hipStream_t s) {
+                            int parity, hipStream_t s, bool nt = false) {
     if (n_items <= 0) return hipSuccess;
     if (grid <= 0 || grid > n_items) grid = n_items;
     switch (tx) {
@@ -41,25 +58,25 @@ static hipError_t launch_tx(int tx, const LatDesc* d, const WorkItem* items, int
     // whole cache lines (see lane_slot); step kernels only
     case 132:
         if constexpr (MODE == MODE_STEP)
-            launch_one<ST, 132, MODE, PF, KIND, W>(dim3(grid), d, items, n_items, parity, s);
+            launch_lines<ST, 132, MODE, PF, KIND, W>(nt, dim3(grid), d, items, n_items, parity, s);
         else
             return hipErrorInvalidValue;
         break;
     case 260:
         if constexpr (MODE == MODE_STEP)
-            launch_one<ST, 260, MODE, PF, KIND, W>(dim3(grid), d, items, n_items, parity, s);
+            launch_lines<ST, 260, MODE, PF, KIND, W>(nt, dim3(grid), d, items, n_items, parity, s);
         else
             return hipErrorInvalidValue;
         break;
     case 452:
         if constexpr (MODE == MODE_STEP)
-            launch_one<ST, 452, MODE, PF, KIND, W>(dim3(grid), d, items, n_items, parity, s);
+            launch_lines<ST, 452, MODE, PF, KIND, W>(nt, dim3(grid), d, items, n_items, parity, s);
         else
             return hipErrorInvalidValue;
         break;
     case 516:  // 9 waves: FP64 prefetching would spill at the 3 waves per SIMD this needs
         if constexpr (MODE == MODE_STEP && !(sizeof(typename ST::R) == 8 && PF == PF_PREFETCH))
-            launch_one<ST, 516, MODE, PF, KIND, W>(dim3(grid), d, items, n_items, parity, s);
+            launch_lines<ST, 516, MODE, PF, KIND, W>(nt, dim3(grid), d, items, n_items, parity, s);
         else
             return hipErrorInvalidValue;
         break;
@@ -75,17 +92,18 @@ static hipError_t launch_tx(int tx, const LatDesc* d, const WorkItem* items, int
 }
 
 template <class ST, bool W>
-static hipError_t launch_step_kind(int kind, int tx, int pf, const LatDesc* d, const WorkItem* items,
+static hipError_t launch_step_kind(int kind, bool nt, int tx, int pf, const LatDesc* d, const WorkItem* items,
                                  int n_items, int grid, int parity, hipStream_t s) {
     switch (kind) {
     case KIND_COUPLED_CASCADED:
         if (pf == PF_PREFETCH)
-            return launch_tx<ST, MODE_STEP, PF_PREFETCH, KIND_COUPLED_CASCADED, W>(tx, d, items, n_items, grid, parity, s);
-        return launch_tx<ST, MODE_STEP, PF_HOLD, KIND_COUPLED_CASCADED, W>(tx, d, items, n_items, grid, parity, s);
+            return launch_tx<ST, MODE_STEP, PF_PREFETCH, KIND_COUPLED_CASCADED, W>(tx, d, items, n_items, grid, parity, s,
+                                                                                   nt);
+        return launch_tx<ST, MODE_STEP, PF_HOLD, KIND_COUPLED_CASCADED, W>(tx, d, items, n_items, grid, parity, s, nt);
     case KIND_COUPLED_SRT:
-        return launch_tx<ST, MODE_STEP, PF_HOLD, KIND_COUPLED_SRT, W>(tx, d, items, n_items, grid, parity, s);
+        return launch_tx<ST, MODE_STEP, PF_HOLD, KIND_COUPLED_SRT, W>(tx, d, items, n_items, grid, parity, s, nt);
     case KIND_COUPLED_PRINTED:
-        return launch_tx<ST, MODE_STEP, PF_HOLD, KIND_COUPLED_PRINTED, W>(tx, d, items, n_items, grid, parity, s);
+        return launch_tx<ST, MODE_STEP, PF_HOLD, KIND_COUPLED_PRINTED, W>(tx, d, items, n_items, grid, parity, s, nt);
     case KIND_ACE_CASCADED:
         return launch_tx<ST, MODE_STEP, PF_HOLD, KIND_ACE_CASCADED, W>(tx, d, items, n_items, grid, parity, s);
     case KIND_ACE_SRT:
@@ -95,19 +113,19 @@ static hipError_t launch_step_kind(int kind, int tx, int pf, const LatDesc* d, c
 }
 
 template <class ST>
-static hipError_t launch_step_st(int kind, bool walls, int tx, int pf, const LatDesc* d, const WorkItem* items,
-                                 int n_items, int grid, int parity, hipStream_t s) {
-    return walls ? launch_step_kind<ST, true>(kind, tx, pf, d, items, n_items, grid, parity, s)
-                 : launch_step_kind<ST, false>(kind, tx, pf, d, items, n_items, grid, parity, s);
+static hipError_t launch_step_st(int kind, bool walls, bool nt, int tx, int pf, const LatDesc* d,
+                                 const WorkItem* items, int n_items, int grid, int parity, hipStream_t s) {
+    return walls ? launch_step_kind<ST, true>(kind, nt, tx, pf, d, items, n_items, grid, parity, s)
+                 : launch_step_kind<ST, false>(kind, nt, tx, pf, d, items, n_items, grid, parity, s);
 }
 
-hipError_t launch_step(int prec, int kind, bool walls, int tx, int pf, const LatDesc* d, const WorkItem* items,
-                       int n_items, int grid, int parity, hipStream_t s) {
+hipError_t launch_step(int prec, int kind, bool walls, bool nt, int tx, int pf, const LatDesc* d,
+                       const WorkItem* items, int n_items, int grid, int parity, hipStream_t s) {
     switch (prec) {
-    case LB_FP64: return launch_step_st<StF64>(kind, walls, tx, pf, d, items, n_items, grid, parity, s);
-    case LB_FP32: return launch_step_st<StF32>(kind, walls, tx, pf, d, items, n_items, grid, parity, s);
-    case LB_FP32_F16: return launch_step_st<StF16>(kind, walls, tx, pf, d, items, n_items, grid, parity, s);
-    case LB_FP32_BF16: return launch_step_st<StBF16>(kind, walls, tx, pf, d, items, n_items, grid, parity, s);
+    case LB_FP64: return launch_step_st<StF64>(kind, walls, nt, tx, pf, d, items, n_items, grid, parity, s);
+    case LB_FP32: return launch_step_st<StF32>(kind, walls, nt, tx, pf, d, items, n_items, grid, parity, s);
+    case LB_FP32_F16: return launch_step_st<StF16>(kind, walls, nt, tx, pf, d, items, n_items, grid, parity, s);
+    case LB_FP32_BF16: return launch_step_st<StBF16>(kind, walls, nt, tx, pf, d, items, n_items, grid, parity, s);
     }
     return hipErrorInvalidValue;
 }
