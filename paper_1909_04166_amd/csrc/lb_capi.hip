@@ -29,6 +29,10 @@ struct TraceRange {
 
 constexpr uint64_t kAlign = 256;
 constexpr int kMinH = 8;
+// Nontemporal stores only for states well above the 256 MB last-level cache
+// (MALL): a smaller state stays there between steps, and streaming its stores
+// past it made the 75 MB Rayleigh-Taylor lattice 13% slower.
+constexpr uint64_t kStreamBytes = (uint64_t)1 << 30;
 // A batch replays captured step graphs once its work list has been unchanged for
 // this many graph lengths (steps).
 constexpr int kGraphAfter = 4;
@@ -234,7 +238,8 @@ struct lb_handle {
     lb_config cfg;
     int kind = KIND_COUPLED_CASCADED;
     bool walls = true;  // the lattice has a wall on some side (else the wall-free kernels run)
-    bool nt = false;    // its rows are whole cache lines (nontemporal stores where the strips are too)
+    bool nt = false;    // its rows are whole cache lines and its state is large (nontemporal stores
+                        // where the strips are whole lines too)
     hipStream_t s = nullptr;
     char* ws = nullptr;
     uint64_t ws_bytes = 0;
@@ -523,7 +528,7 @@ lb_status lb_create(const lb_config* cfg, void* dev_ws, uint64_t ws_bytes, void*
     h->kind = kind_of(cfg);
     fill_desc(cfg, h->hdesc, h->buf[0], h->buf[1], h->plane, h->d_fields);
     h->walls = h->hdesc.wall_y != WALL_NONE || h->hdesc.wall_x != WALL_NONE;
-    h->nt = h->hdesc.ntstore != 0;
+    h->nt = h->hdesc.ntstore != 0 && (uint64_t)2 * 18 * h->plane * h->sbytes >= kStreamBytes;
     h->hdesc.vel = cfg->flow == LB_FLOW_IMPOSED ? (void*)(h->ws + L.vel) : nullptr;
     h->hdesc.ktab = (double*)(h->ws + L.ktab);
     h->hdesc.tstep = (uint32_t*)(h->ws + L.tstep);
@@ -1201,7 +1206,7 @@ lb_status lb_batch_step(lb_batch* b, int64_t n, int32_t use_graph) {
         lb_batch_usage(b, &used, &nodes);
         // the kernels without wall logic serve batches of periodic lattices only
         b->walls = false;
-        b->nt = used > 0;
+        b->nt = used > 0 && (uint64_t)2 * 18 * nodes * b->sbytes >= kStreamBytes;
         for (int i = 0; i < b->nslots; ++i) {
             if (!b->slot[i].used) continue;
             if (b->slot[i].cfg.bc_x != LB_PERIODIC || b->slot[i].cfg.bc_y != LB_PERIODIC) b->walls = true;
@@ -1488,9 +1493,8 @@ lb_status lb_step_noalloc(const lb_config* cfg, void* state0, void* state1, uint
     const int kind = kind_of(cfg);
     int parity = 0;
     for (int64_t i = 0; i < n; ++i) {
-        HIPC(launch_step(cfg->precision, kind, walls, D.ntstore != 0, sc.tx, sc.pf, d_desc, d_items, (int)n_items,
-                         (int)n_items,
-                         parity, s));
+        HIPC(launch_step(cfg->precision, kind, walls, D.ntstore != 0 && 2 * need >= kStreamBytes, sc.tx, sc.pf, d_desc,
+                         d_items, (int)n_items, (int)n_items, parity, s));
         parity ^= 1;
     }
     return LB_OK;
