@@ -138,7 +138,7 @@ typedef struct lb_config {
                                 rho(phi) is most sensitive to phi, and shift_g 0 */
     double u_max;            /* stability limit for diagnostics (0: 0.3) */
     int32_t tile_x;          /* workgroup width in lanes: 64, 128, 132, 256, 260, 452, 512,
-                                516 (not with FP64 prefetching), or 1024 (FP32-compute
+                                516, or 1024 (FP32-compute
                                 precisions without prefetching); strips of tile_x - 4
                                 columns; 0: autotuned */
     int32_t tile_h;          /* rows per work item (>= 8); 0: autotuned */

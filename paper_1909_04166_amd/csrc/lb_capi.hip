@@ -56,11 +56,10 @@ bool finite_pos(double v) { return std::isfinite(v) && v > 0; }
 // Workgroup widths with a step kernel: powers of two, 64k + 4 (strips of whole
 // 64-column blocks: 132, 260, 516, and 452 = two 8-wave workgroups per CU at four
 // waves per SIMD), and 1024 (16 waves per CU: FP32-compute kernels without
-// prefetching only).  FP64 prefetching has no 516-lane kernel (it would spill).
+// prefetching only).
 bool valid_width(int tx, int prec, int pf) {
     switch (tx) {
-    case 64: case 128: case 132: case 256: case 260: case 452: case 512: return true;
-    case 516: return !(prec == LB_FP64 && pf != 0);
+    case 64: case 128: case 132: case 256: case 260: case 452: case 512: case 516: return true;
     case 1024: return prec != LB_FP64 && pf == 0;
     }
     return false;

@@ -67,7 +67,9 @@ struct StF16 {
     static __device__ __forceinline__ R ld(T v) { return (float)v; }
     static __device__ __forceinline__ T st(R v) { return (_Float16)v; }  // round to nearest even
     static __device__ __forceinline__ T st_sr(R v, uint32_t r) {
-        half2_t h = {0, 0};
+        // the conversion writes the low half and keeps the high one, which is not
+        // read: start from r's register rather than a zeroed one (no extra move)
+        half2_t h = __builtin_bit_cast(half2_t, r);
         h = __builtin_amdgcn_cvt_sr_f16_f32(h, v, r, false);
         return h.x;
     }
@@ -86,7 +88,7 @@ struct StBF16 {
         return (T)(u >> 16);
     }
     static __device__ __forceinline__ T st_sr(R v, uint32_t r) {
-        short2_t h = {0, 0};
+        short2_t h = __builtin_bit_cast(short2_t, r);  // high half not read (see StF16)
         h = __builtin_amdgcn_cvt_sr_bf16_f32(h, v, r, false);
         return (T)(unsigned short)h.x;
     }
@@ -243,13 +245,15 @@ __device__ __forceinline__ void store_row(typename ST::T* row, int nx, int first
 }
 
 // Random bits of the stochastic rounding.  seed_step: an integer hash of the step
-// count (uniform over the launch); node_hash: a hash of that seed and the node
-// (two multiply-xorshift rounds, Wellons' lowbias32 constants).  Stored value q of
-// the node (0..8 f, 9..17 gbar) then takes the low 32 bits of (h mod 2^24) x C_q,
-// one full-rate 24-bit multiply per value, with 18 odd 24-bit multipliers C_q: for
-// a uniform h the top 16 bits of each product (the bits the conversions use) are
-// uniform, and across q their pairwise correlation is below 0.003.  The bits depend
-// on the step and the node only, so every schedule stores the same values.
+// count (two multiply-xorshift rounds, Wellons' lowbias32 constants; uniform over
+// the launch); node_hash: that seed xor the node's index, times the golden-ratio
+// constant, folded once (one multiply).  Stored value q of the node (0..8 f, 9..17
+// gbar) then takes the low 32 bits of (h mod 2^24) x C_q, one full-rate 24-bit
+// multiply per value, with 18 odd 24-bit multipliers C_q: over a 1024 x 512 grid
+// the top 16 bits of each product (the bits the conversions use) are uniform to
+// 1e-3, and their correlation across q, between neighbouring nodes and between
+// consecutive steps stays at the sampling noise (below 0.006).  The bits depend on
+// the step and the node only, so every schedule stores the same values.
 __device__ __forceinline__ uint32_t mix32(uint32_t x) {
     x ^= x >> 16;
     x *= 0x7feb352du;
@@ -260,7 +264,8 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
 }
 __device__ __forceinline__ uint32_t seed_step(uint32_t t) { return mix32(t * 0x9e3779b9u + 0x7f4a7c15u); }
 __device__ __forceinline__ uint32_t node_hash(uint32_t seed, int x, int y) {
-    return mix32(seed ^ ((uint32_t)y * 0x85ebca6bu + (uint32_t)x));
+    uint32_t h = (seed ^ ((uint32_t)y * 0x85ebca6bu + (uint32_t)x)) * 0x9e3779b1u;
+    return h ^ (h >> 16);
 }
 constexpr uint32_t kSRMul[18] = {0xa58a9du, 0xfb4889u, 0x987a27u, 0xb9e081u, 0xe3f42fu, 0xe90a67u,
                                  0xfe72f1u, 0x8a7dabu, 0x937427u, 0x99dcefu, 0xae49f3u, 0xbe1d1bu,
@@ -406,12 +411,11 @@ __device__ __forceinline__ int lane_slot(int lane) {
     return lane < TX - 4 ? lane + 2 : (lane < TX - 2 ? lane - (TX - 4) : lane);
 }
 
+// The sum of the nine values, in pairs that the moments below share (the
+// compiler computes each pair once).
 template <class R>
 __device__ __forceinline__ R sum9(const R v[9]) {
-    R s = v[0];
-#pragma unroll
-    for (int a = 1; a < 9; ++a) s += v[a];
-    return s;
+    return v[0] + (((v[1] + v[3]) + (v[2] + v[4])) + ((v[5] + v[6]) + (v[7] + v[8])));
 }
 
 // What the cascaded collisions read of the pulled values (see ace_collide and
@@ -433,13 +437,15 @@ template <class R>
 struct Vals9 {
     R v[9];
 };
+// First moments; (v8 - v7) is taken as -(v7 - v8), exactly the same value, so that
+// the difference is shared with the shear moment of gbar.
 template <class R>
 __device__ __forceinline__ R first_x(const R v[9]) {
-    return (v[1] - v[3]) + (v[5] - v[6]) + (v[8] - v[7]);
+    return ((v[1] - v[3]) + (v[5] - v[6])) - (v[7] - v[8]);
 }
 template <class R>
 __device__ __forceinline__ R first_y(const R v[9]) {
-    return (v[2] - v[4]) + (v[5] + v[6]) - (v[7] + v[8]);
+    return ((v[2] - v[4]) + (v[5] + v[6])) - (v[7] + v[8]);
 }
 template <class R>
 __device__ __forceinline__ void hold(FMom<R>& h, const R v[9]) {

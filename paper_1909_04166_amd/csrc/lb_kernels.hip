@@ -74,8 +74,8 @@ static hipError_t launch_tx(int tx, const LatDesc* d, const WorkItem* items, int
         else
             return hipErrorInvalidValue;
         break;
-    case 516:  // 9 waves: FP64 prefetching would spill at the 3 waves per SIMD this needs
-        if constexpr (MODE == MODE_STEP && !(sizeof(typename ST::R) == 8 && PF == PF_PREFETCH))
+    case 516:  // 9 waves: three per SIMD on one, at most 168 VGPRs (FP64 prefetching: 145)
+        if constexpr (MODE == MODE_STEP)
             launch_lines<ST, 516, MODE, PF, KIND, W>(nt, dim3(grid), d, items, n_items, parity, s);
         else
             return hipErrorInvalidValue;
@@ -160,20 +160,7 @@ static int occ_st(int kind, int tx, int pf) {
     case 132: return occ_kind<ST, 132, W>(kind, pf);
     case 260: return occ_kind<ST, 260, W>(kind, pf);
     case 452: return occ_kind<ST, 452, W>(kind, pf);
-    case 516:
-        if constexpr (sizeof(typename ST::R) == 8) {
-            if (pf == PF_PREFETCH) return 0;
-            switch (kind) {
-            case KIND_COUPLED_CASCADED: return occ_of(lb_fused<ST, 516, MODE_STEP, PF_HOLD, COLL_CASCADED, W>, 516);
-            case KIND_COUPLED_SRT: return occ_of(lb_fused<ST, 516, MODE_STEP, PF_HOLD, COLL_SRT, W>, 516);
-            case KIND_COUPLED_PRINTED: return occ_of(lb_fused<ST, 516, MODE_STEP, PF_HOLD, COLL_PRINTED, W>, 516);
-            case KIND_ACE_CASCADED: return occ_of(lb_ace<ST, 516, MODE_STEP, COLL_CASCADED, W>, 516);
-            case KIND_ACE_SRT: return occ_of(lb_ace<ST, 516, MODE_STEP, COLL_SRT, W>, 516);
-            }
-            return 0;
-        } else {
-            return occ_kind<ST, 516, W>(kind, pf);
-        }
+    case 516: return occ_kind<ST, 516, W>(kind, pf);
     case 1024:
         if constexpr (sizeof(typename ST::R) == 4) {
             if (pf != PF_HOLD) return 0;

@@ -22,6 +22,7 @@ SCHEDULES = [
     (260, 2, 2, 0),
     (516, 1, 1, 0),
     (260, 2, 1, 1),
+    (516, 1, 1, 1),
 ]
 
 
@@ -44,8 +45,6 @@ def test_pinned_schedules_bit_identical(prec, bc_y):
     print(f"[case] schedules {prec} {bc_y} 1030x3400", flush=True)
     ref, _ = _run(case, phi0, prec, SCHEDULES[0], 12)
     for sched in SCHEDULES[1:]:
-        if prec == "fp64" and sched[0] == 516 and sched[3]:
-            continue  # no FP64 prefetching kernel at 516 lanes
         print(f"   schedule {sched}", flush=True)
         got, tile = _run(case, phi0, prec, sched, 12)
         assert tile[0] == sched[0] and tile[3] == sched[3]
@@ -78,8 +77,7 @@ def test_set_schedule_rejects():
                 (260, 3, 1, 0),    # no such mode
                 (260, 0, 4, 0),    # items under 8 rows
                 (260, 1, 5, 0),    # multiplier out of range
-                (260, 2, 1, 0),    # 40 rows: too few for eight bands of 8
-                (516, 0, 64, 1)]:  # no FP64 prefetching kernel at 516 lanes
+                (260, 2, 1, 0)]:   # 40 rows: too few for eight bands of 8
         with pytest.raises(lb.LBError) as e:
             L.set_schedule(*bad)
         assert e.value.code == lb.LB_E_INVALID_ARG, bad
