@@ -821,8 +821,9 @@ __device__ __forceinline__ void ace_srt(R f[9], R phi, R ux, R uy, R Mth_x, R Mt
 // Register budget (resident waves per SIMD the kernels are built for): holding
 // moments, the cascaded kernels without prefetching need about 110 VGPRs in FP64
 // (four waves) and 85-95 in FP32 and 16-bit storage (five, so that two workgroups
-// of nine waves fit a CU); the FP64 prefetching and SRT kernels about 150-165
-// (three); the rest fits in ST::waves.
+// of nine waves fit a CU); the FP64 prefetching and SRT kernels about 145-165
+// (three, which is also what a 9-wave 516-lane workgroup gets on one SIMD); the
+// rest fits in ST::waves.
 template <class ST, int PF, int COLL>
 constexpr int fused_waves() {
     const bool lean = PF == PF_HOLD && COLL != COLL_SRT;
@@ -854,8 +855,8 @@ lb_fused(const LatDesc* __restrict__ descs, const WorkItem* __restrict__ items, 
     using R = typename ST::R;
     using T = typename ST::T;
     // Role-based register pipeline (see below): the coupled cascaded step with 16-
-    // or 32-bit storage without walls.  Elsewhere it is not used: FP64 waits on
-    // memory, the SRT kernels would spill, and the wall logic unrolled six times
+    // or 32-bit storage without walls.  Elsewhere it is not used: in FP64 it
+    // spills (168 VGPRs with prefetching), so would the SRT kernels, and the wall logic unrolled six times
     // (about 6000 instructions) outgrows the instruction cache (a batch with walled
     // lattices ran 14% slower with it).
     constexpr bool kRoles = MODE == MODE_STEP && COLL == COLL_CASCADED && sizeof(T) < 8 && !WALLS;
