@@ -145,6 +145,65 @@ def test_imposed_flow_fp64(tile, coll):
     assert np.allclose(ux, _shear(case, -1.0)[0], rtol=0, atol=1e-16)
 
 
+def _swirl(nx, ny, amp=1.0):
+    """A smooth seeded-phase velocity on an nx x ny lattice (|u| <= 0.03 amp),
+    periodic in both directions, for the phase field alone next to walls."""
+    y, x = np.mgrid[0:ny, 0:nx].astype(float) + 0.5
+    return (amp * 0.03 * np.sin(2 * np.pi * y / ny + 0.3) * np.cos(2 * np.pi * x / nx + 1.1),
+            -amp * 0.02 * np.cos(2 * np.pi * y / ny + 0.7) * np.sin(2 * np.pi * x / nx + 0.2))
+
+
+@pytest.mark.parametrize("tile", [(64, 8), (260, 12), (516, 16)])
+@pytest.mark.parametrize("bcx,bcy,coll", [("periodic", "wall", "cascaded"), ("slip", "wall", "srt"),
+                                          ("wall", "slip", "cascaded"), ("wall", "wall", "srt")])
+def test_imposed_flow_walls_fp64(tile, bcx, bcy, coll):
+    """Phase field alone next to no-slip and free-slip walls in x and y, ragged
+    size: the rows pulled ahead of their use (32- and 64-bit storage) include the
+    mirrored and bounced rows at the walls."""
+    case, phi0 = W.random_case(97, 70, seed=43, bc_y=bcy)
+    case.update(flow="imposed", collision=coll, bc_x=bcx)
+    _print_case(f"imposed walls x={bcx}", case, tile=tile)
+    g, o = _pair(case, phi0, tile=tile, vel=_swirl(97, 70))
+    g.step(60)
+    o.step(60)
+    _cmp_dist(g, o, 1e-10)
+    _cmp_fields(g, o, 1e-10, 1e-12)
+
+
+def _channel_drop(bc_x):
+    """A drop of radius 18 in a 97 x 70 channel (walls in y, bc_x in x) sheared
+    by u_x = 0.03 sin(pi y / ny), u_y = 0: well conditioned (a relative change of
+    1e-7 in phi0 moves phi by 1.4e-7 over 200 steps in the oracle; the random
+    cases amplify such changes a thousandfold)."""
+    nx, ny = 97, 70
+    case = W.base_case(nx, ny, flow="imposed", W=4.0, M=0.02, bc_y="wall", bc_x=bc_x)
+    y, x = np.mgrid[0:ny, 0:nx].astype(float) + 0.5
+    phi0 = W.tanh_profile(18.0 - np.hypot(x - 48.0, y - 35.0), 4.0)
+    return case, phi0, (0.03 * np.sin(np.pi * y / ny), np.zeros_like(y))
+
+
+@pytest.mark.parametrize("coll", ["cascaded", "srt"])
+def test_imposed_flow_fp32(coll):
+    """FP32 phase field alone in the reversing vortex and in a walled channel
+    against the FP64 oracle: phi within 1e-4 (the FP32 bound for the stationary
+    cases), the imposed velocity as stored in FP32 (relative 1e-7)."""
+    for case, phi0, vel in [(*W.reversing_shear(150)[:2], None), _channel_drop("periodic"),
+                            _channel_drop("wall")]:
+        case = dict(case, flow="imposed", collision=coll)
+        if vel is None:
+            vel = _shear(case)
+        _print_case("imposed fp32", case)
+        g, o = _pair(case, phi0, precision="fp32", tile=(516, 16), vel=vel)
+        g.step(200)
+        o.step(200)
+        a, b = g.fields(), o.fields()
+        e_phi = np.abs(a[0] - b[0]).max()
+        e_u = max(np.abs(a[i] - b[i]).max() / max(np.abs(b[i]).max(), 1e-30) for i in (2, 3))
+        print(f"   phi {e_phi:.3e}  u {e_u:.3e}", flush=True)
+        assert e_phi <= 1e-4 and e_u <= 1e-7
+        g.close()
+
+
 @pytest.mark.parametrize("bcx,bcy", [("periodic", "slip"), ("wall", "periodic"), ("slip", "wall"),
                                      ("slip", "slip"), ("wall", "wall")])
 def test_set_get_dist_roundtrip_walls(bcx, bcy):
