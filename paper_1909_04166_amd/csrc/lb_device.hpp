@@ -1139,9 +1139,9 @@ lb_fused(const LatDesc* __restrict__ descs, const WorkItem* __restrict__ items, 
 // the SRT one the nine values.  kPF (32- and 64-bit storage): each iteration
 // issues the next row's pull (stored type, in registers) and the velocity of the
 // row it collides next as soon as the current ones are read, so the loads fly
-// through the barrier, the stencil and the collision: FP32 +6%, the FP64 SRT
-// pair +5% on the 8192^2 grid, the FP64 cascaded one unchanged; the 16-bit
-// kernels ran 14% slower with it and pull each row where they use it.
+// through the barrier, the stencil and the collision: FP32 +5%, FP64 with the
+// SRT collision +5% on the 8192^2 grid, FP64 with the cascaded one unchanged;
+// the 16-bit kernels ran 14% slower with it and pull each row where they use it.
 template <class ST, int TX, int MODE, int COLL, bool WALLS = true>
 __global__ void __launch_bounds__(TX) lb_ace(const LatDesc* __restrict__ descs,
                                              const WorkItem* __restrict__ items, int n_items,
