@@ -48,3 +48,12 @@ def test_noalloc_langmuir_and_fp16_pinned_tile():
     print("[case] lb_step_noalloc Langmuir 51x201 fp16 tile 128x16, from step 7, n=25", flush=True)
     got, ref = _noalloc_vs_handle(case, phi0, "fp16", 25, tile=(128, 16), pre=7)
     assert np.array_equal(got, ref)
+
+
+def test_noalloc_fp64_prefetching_516_lanes():
+    """The FP64 prefetching kernel at 516 lanes (the one the 8192^2 grid runs) on a
+    ragged walled lattice: a partial second strip and a partial last item."""
+    case, phi0 = W.random_case(700, 150, seed=12, bc_y="wall", gy=-1e-5)
+    print("[case] lb_step_noalloc 700x150 fp64 tile 516x64 prefetching, n=21", flush=True)
+    got, ref = _noalloc_vs_handle(case, phi0, "fp64", 21, tile=(516, 64, 1))
+    assert np.array_equal(got, ref)
