@@ -141,7 +141,7 @@ typedef struct lb_config {
                                 516, or 1024 (FP32-compute
                                 precisions without prefetching); strips of tile_x - 4
                                 columns; 0: autotuned */
-    int32_t tile_h;          /* rows per work item (>= 2); 0: autotuned */
+    int32_t tile_h;          /* rows per work item (>= 1); 0: autotuned */
     int32_t collision;       /* LB_CASCADED or LB_SRT */
     int32_t flow;            /* LB_FLOW_COUPLED or LB_FLOW_IMPOSED */
     int32_t surf;            /* LB_SIGMA_LINEAR or LB_SIGMA_LANGMUIR */
@@ -335,7 +335,7 @@ lb_status lb_batch_timing_enable(lb_batch* b, int32_t on);
 lb_status lb_batch_timing_read(lb_batch* b, double* ms_per_step, int64_t* steps);
 
 /* Pins the handle's schedule; later steps skip the autotuner.  tile_x as in
- * lb_config; mode 0: work items of `param` rows (>= 2), one per workgroup;
+ * lb_config; mode 0: work items of `param` rows (>= 1), one per workgroup;
  * mode 1: persistent grid of param (1..4) x resident workgroups per CU x CUs,
  * each workgroup one balanced run of the concatenated strip rows; mode 2: as 1,
  * the grid cut down to strips x bands (bands a multiple of 8) so that every

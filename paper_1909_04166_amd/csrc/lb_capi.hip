@@ -28,7 +28,7 @@ struct TraceRange {
 };
 
 constexpr uint64_t kAlign = 256;
-constexpr int kMinH = 2;
+constexpr int kMinH = 1;
 // Nontemporal stores only for states well above the 256 MB last-level cache
 // (MALL): a smaller state stays there between steps, and streaming its stores
 // past it made the 75 MB Rayleigh-Taylor lattice 13% slower.
@@ -204,10 +204,10 @@ bool build_schedule(const std::vector<LatShape>& lats, int prec, int kind, bool 
 
 // The schedule of lattices too small to autotune (and of lb_step_noalloc): one
 // work item per workgroup, rows halved until there are two items per CU (down
-// to kMinH), prefetching where the kernel has it.  A small lattice's step is
-// bound by the latency of its row loop, so the rows per workgroup set its time:
-// the 128^2 droplet ran FP64 at 0.40 GLUPS with 16-row items, 0.86 with 8-row
-// items prefetching and 1.90 with 2-row items prefetching.
+// to single rows), prefetching where the kernel has it.  A small lattice's step
+// is bound by the latency of its row loop, so the rows per workgroup set its
+// time: the 128^2 droplet ran FP64 at 0.40 GLUPS with 16-row items, 0.86 with
+// 8-row items prefetching, 1.89 with 2-row and 2.26 with 1-row items.
 Sched default_sched(int nx, int ny, int kind) {
     Sched sc;
     sc.tx = nx >= 1024 ? 256 : (nx >= 256 ? 128 : 64);
@@ -400,7 +400,7 @@ std::vector<Sched> candidates(int prec, int nx, int ny, int kind) {
             if (pf != PF_HOLD && kind != KIND_COUPLED_CASCADED) continue;
             if (!valid_width(tx, prec, pf)) continue;
             if (tx > 64 && nx <= strip_w(tx / 2)) continue;
-            for (int th : {2, 4, 8, 16, 32, 64, 128, 256}) {
+            for (int th : {1, 2, 4, 8, 16, 32, 64, 128, 256}) {
                 if (th > ny && th != 16) continue;
                 Sched sc;
                 sc.tx = tx; sc.th = th; sc.mode = 0; sc.pf = pf;

@@ -111,7 +111,7 @@ def test_option_validation():
     assert code(tile_x=768, tile_h=16) == lb.LB_E_INVALID_ARG
     assert code(tile_x=516, tile_h=16) == lb.LB_OK and code(tile_x=260, tile_h=16, tile_pf=1) == lb.LB_OK
     assert code(tile_x=516, tile_h=16, tile_pf=1) == lb.LB_OK
-    assert code(tile_x=64, tile_h=1) == lb.LB_E_INVALID_ARG and code(tile_x=64, tile_h=2) == lb.LB_OK
+    assert code(tile_x=64, tile_h=-1) == lb.LB_E_INVALID_ARG and code(tile_x=64, tile_h=1) == lb.LB_OK
     c32 = lb.config_from_case(case, "fp32", tile=(1024, 16))
     assert lb.lb_workspace_bytes(c32) > 0
     c32.tile_pf = 1  # no prefetching variant at 1024 lanes

@@ -107,7 +107,7 @@ def test_coupling_fields_match_oracle():
 # (workgroup width, rows per item[, 1 = the variant that prefetches the next rows])
 TILES = [(64, 8), (64, 16), (128, 32), (132, 16), (256, 64), (260, 40), (452, 16), (512, 24), (516, 24),
          (64, 16, 1), (256, 64, 1), (260, 40, 1), (452, 16, 1), (512, 24, 1), (516, 24, 1),
-         (64, 2, 1), (132, 4), (260, 3, 1)]
+         (64, 2, 1), (132, 4), (260, 3, 1), (64, 1, 1), (516, 1)]
 
 
 @pytest.mark.parametrize("tile", TILES)

@@ -25,6 +25,8 @@ SCHEDULES = [
     (516, 1, 1, 1),
     (64, 0, 2, 1),
     (132, 0, 4, 0),
+    (64, 0, 1, 1),
+    (260, 0, 1, 0),
 ]
 
 
@@ -77,7 +79,7 @@ def test_set_schedule_rejects():
     L = lb.Lattice(case, phi0, "fp64")
     for bad in [(100, 0, 64, 0),   # not a workgroup width
                 (260, 3, 1, 0),    # no such mode
-                (260, 0, 1, 0),    # items under 2 rows
+                (260, 0, 0, 0),    # items of no rows
                 (260, 1, 5, 0),    # multiplier out of range
                 (260, 2, 1, 0)]:   # 40 rows: too few for eight bands of 8
         with pytest.raises(lb.LBError) as e:
