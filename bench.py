@@ -38,11 +38,11 @@ METRIC = "MLUPS (f+g per node-step) & % HBM roofline; p50/p99 solve latency batc
 KERNEL_SOURCES = ["paper_1909_04166_amd/csrc/lb_device.hpp", "paper_1909_04166_amd/csrc/lb_kernels.hip",
                   "paper_1909_04166_amd/csrc/lb_sched.hpp"]
 TRAFFIC = {
-    "fingerprint": "5f93f4b966316513",
+    "fingerprint": "c2a26308ecb6b848",
     "workload": "tiled8192",
-    "fp64": {"read": 9735001088, "write": 9663723776, "tile": [516, 512, 256, 1]},
-    "fp32": {"read": 4908292096, "write": 4831844352, "tile": [516, 512, 256, 1]},
-    "fp16": {"read": 3045377536, "write": 2415920128, "tile": [452, 304, 512, 1]},
+    "fp64": {"read": 9737072640, "write": 9663729152, "tile": [516, 512, 256, 1]},
+    "fp32": {"read": 4885437440, "write": 4831841792, "tile": [516, 512, 256, 1]},
+    "fp16": {"read": 3045382144, "write": 2415920128, "tile": [452, 304, 512, 1]},
 }
 
 

@@ -202,22 +202,10 @@ bool build_schedule(const std::vector<LatShape>& lats, int prec, int kind, bool 
     return plan_schedule(lats, resident, cu_count(), sc, max_items, items);
 }
 
-// The schedule of lattices too small to autotune (and of lb_step_noalloc): one
-// work item per workgroup, rows halved until there are two items per CU (down
-// to single rows), prefetching where the kernel has it.  A small lattice's step
-// is bound by the latency of its row loop, so the rows per workgroup set its
-// time: the 128^2 droplet ran FP64 at 0.40 GLUPS with 16-row items, 0.86 with
-// 8-row items prefetching, 1.89 with 2-row and 2.26 with 1-row items.
+// The schedule of lattices too small to autotune and of lb_step_noalloc
+// (lb_sched.hpp), prefetching where the kernel has it.
 Sched default_sched(int nx, int ny, int kind) {
-    Sched sc;
-    sc.tx = nx >= 1024 ? 256 : (nx >= 256 ? 128 : 64);
-    sc.mode = 0;
-    sc.pf = kind == KIND_COUPLED_CASCADED ? PF_PREFETCH : PF_HOLD;
-    const int strips = (nx + strip_w(sc.tx) - 1) / strip_w(sc.tx);
-    const int target = 2 * cu_count();
-    sc.th = 256;
-    while (sc.th > kMinH && (int64_t)strips * ((ny + sc.th - 1) / sc.th) < target) sc.th /= 2;
-    return sc;
+    return small_lattice_sched(nx, ny, kind == KIND_COUPLED_CASCADED, cu_count(), kMinH);
 }
 
 struct TuneKey {

@@ -115,6 +115,24 @@ struct Sched {
     int grid = 0, n_items = 0, rows = 0;
 };
 
+// The schedule of a lattice too small to autotune: one work item per workgroup,
+// rows halved from 256 until there are two items per CU (down to min_rows).  A
+// small lattice's step is bound by the latency of its row loop, so the rows per
+// workgroup set its time: the 128^2 droplet ran FP64 at 0.40 GLUPS with 16-row
+// items, 0.86 with 8-row items prefetching, 1.89 with 2-row and 2.26 with 1-row
+// items.
+inline Sched small_lattice_sched(int nx, int ny, bool prefetch, int cus, int min_rows) {
+    Sched sc;
+    sc.tx = nx >= 1024 ? 256 : (nx >= 256 ? 128 : 64);
+    sc.mode = 0;
+    sc.pf = prefetch ? 1 : 0;
+    const int strips = (nx + strip_w(sc.tx) - 1) / strip_w(sc.tx);
+    const int64_t target = 2 * (int64_t)cus;
+    sc.th = 256;
+    while (sc.th > min_rows && (int64_t)strips * ((ny + sc.th - 1) / sc.th) < target) sc.th /= 2;
+    return sc;
+}
+
 // Work list of a schedule over the given lattices; `resident` is the number of
 // workgroups of the chosen kernel that fit on one CU, `cus` the CU count.
 // Fills sc.grid, sc.rows and sc.n_items; false if the schedule does not apply

@@ -171,3 +171,47 @@ def test_max_items_enforced(planner):
     assert not planner(0, 64, lats, th=8, max_items=1000)["ok"]
     assert planner(0, 64, lats, th=8)["ok"]
 
+
+
+SMALL_DRIVER = r"""
+#include <cstdio>
+#include "lb_sched.hpp"
+using namespace cmlb;
+// stdin: nx ny prefetch cus min_rows; stdout: tx th mode pf
+int main() {
+    int nx, ny, pf, cus, mr;
+    while (std::scanf("%d %d %d %d %d", &nx, &ny, &pf, &cus, &mr) == 5) {
+        const Sched sc = small_lattice_sched(nx, ny, pf != 0, cus, mr);
+        std::printf("%d %d %d %d\n", sc.tx, sc.th, sc.mode, sc.pf);
+    }
+    return 0;
+}
+"""
+
+
+def test_small_lattice_schedule(tmp_path):
+    """One item per workgroup; rows per item the largest power of two (<= 256)
+    that still gives two items per CU, down to single rows; the width by the
+    lattice width; prefetching as asked."""
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    src = tmp_path / "small.cpp"
+    src.write_text(SMALL_DRIVER)
+    exe = tmp_path / "small"
+    subprocess.run([gxx, "-std=c++17", "-O1", "-Wall", "-Werror", "-I", CSRC, str(src), "-o", str(exe)], check=True)
+    cases = [(nx, ny, pf) for nx in (64, 100, 128, 255, 256, 600, 1024, 8192) for ny in (8, 77, 128, 1024, 8192)
+             for pf in (0, 1)]
+    req = "".join(f"{nx} {ny} {pf} 256 1\n" for nx, ny, pf in cases)
+    out = subprocess.run([str(exe)], input=req, capture_output=True, text=True, check=True).stdout.split("\n")
+    for (nx, ny, pf), line in zip(cases, out):
+        tx, th, mode, got_pf = map(int, line.split())
+        assert mode == 0 and got_pf == pf
+        assert tx == (256 if nx >= 1024 else 128 if nx >= 256 else 64)
+        strips = -(-nx // (tx - 4))
+        items = strips * -(-ny // th)
+        assert th in (1, 2, 4, 8, 16, 32, 64, 128, 256)
+        assert items >= 512 or th == 1, (nx, ny, th)            # enough items, or single rows
+        assert th == 256 or strips * -(-ny // (2 * th)) < 512, (nx, ny, th)  # the largest such
+    # the 128^2 droplet: three 60-column strips of single rows
+    assert out[cases.index((128, 128, 1))].split() == ["64", "1", "0", "1"]
