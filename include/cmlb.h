@@ -141,7 +141,9 @@ typedef struct lb_config {
                                 516, or 1024 (FP32-compute
                                 precisions without prefetching); strips of tile_x - 4
                                 columns; 0: autotuned */
-    int32_t tile_h;          /* rows per work item (>= 1); 0: autotuned */
+    int32_t tile_h;          /* rows per work item (>= 1); 0: autotuned (lattices under
+                                65536 nodes: one item per workgroup, rows halved until
+                                there are two items per CU, prefetching) */
     int32_t collision;       /* LB_CASCADED or LB_SRT */
     int32_t flow;            /* LB_FLOW_COUPLED or LB_FLOW_IMPOSED */
     int32_t surf;            /* LB_SIGMA_LINEAR or LB_SIGMA_LANGMUIR */
